@@ -1,0 +1,292 @@
+/*
+ * riann_oracle.c -- plain CPU oracle for RIANN ANN fields.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or helper with the GPU
+ * library: it has its own patch extraction, distance, table build, integer
+ * square root, binary search and reduction, all written in the most direct
+ * form, in exact integer arithmetic.
+ *
+ * Paper: Ben-Zrihem & Zelnik-Manor, "Approximate Nearest Neighbor Fields in
+ * Video" (arXiv 1508.07953).
+ *
+ *   orc_extract     query patches q_{x,y,t}: every p x p (x C) window of a
+ *                   frame at stride s, flattened in (dy, dx, c) order
+ *                   (Sec. 3.1 notation; 8x8 patches, Sec. 4).
+ *   orc_ssd         squared L2 distance between two patches.  The paper's
+ *                   dist() is the L2 norm (Sec. 3.1); the square root is
+ *                   dropped because it is monotone, and patches are raw
+ *                   uint8 (no unit normalisation), so every value is an exact
+ *                   integer.
+ *   orc_bf          exact nearest neighbour by exhaustive search: the plain
+ *                   definition of what the search must return.  Ties go to
+ *                   the lowest reference index.
+ *   orc_isqrt       floor(sqrt(x)) for x < 2^53, exact.
+ *   orc_ring_bounds integer form of the ring test |d(r,k) - d(q,k)| <= R
+ *                   (Sec. 3.2, ring of radius d around an anchor; closed
+ *                   interval as in Algorithm 1), with R^2 = c.
+ *   orc_build       pre-processing (Sec. 3.3): for each key point k, the
+ *                   distances from k to every reference patch, sorted
+ *                   ascending; plus the n x K pivot table.
+ *   orc_riann       the online search of Algorithm 1 in exact mode: the
+ *                   radius comes from the previous frame's match and is not
+ *                   capped, rings are taken around K fixed key points, the
+ *                   smallest ring is scanned and every candidate must lie in
+ *                   all K rings; the survivors are checked by exact distance
+ *                   and the argmin is returned.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so riann_oracle.c -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_INF UINT64_MAX
+
+/* Test hook: a non-zero code plants one deliberate mistake so the tests can
+ * show that their pins catch it.  Zero (the default) is the correct oracle. */
+static int g_fault = 0;
+void orc_set_fault(int code) { g_fault = code; }
+
+/* ------------------------------------------------------------------ */
+/* patches                                                             */
+/* ------------------------------------------------------------------ */
+void orc_extract(const uint8_t *frame, int H, int W, int C, int64_t pitch,
+                 int p, int s, uint8_t *out)
+{
+    int hq = (H - p) / s + 1, wq = (W - p) / s + 1;
+    int D = p * p * C;
+    for (int qy = 0; qy < hq; ++qy)
+        for (int qx = 0; qx < wq; ++qx) {
+            uint8_t *q = out + ((int64_t)qy * wq + qx) * D;
+            int y = qy * s, x = qx * s;
+            for (int dy = 0; dy < p; ++dy)
+                for (int dx = 0; dx < p; ++dx)
+                    for (int c = 0; c < C; ++c) {
+                        int yy = y + dy, xx = x + dx;
+                        if (g_fault == 1) { int t = yy; yy = xx; xx = t; } /* transposed */
+                        q[(dy * p + dx) * C + c] =
+                            frame[(int64_t)yy * pitch + (int64_t)xx * C + c];
+                    }
+        }
+}
+
+uint64_t orc_ssd(const uint8_t *a, const uint8_t *b, int D)
+{
+    int64_t s = 0;
+    for (int i = 0; i < D; ++i) {
+        int64_t d = (int64_t)a[i] - (int64_t)b[i];
+        if (g_fault == 2 && i == D - 1) break;          /* dropped term */
+        s += d * d;
+    }
+    return (uint64_t)s;
+}
+
+/* ------------------------------------------------------------------ */
+/* exhaustive search                                                   */
+/* ------------------------------------------------------------------ */
+void orc_bf(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int D,
+            int32_t *idx, uint32_t *ssd)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < Q; ++i) {
+        const uint8_t *q = qp + i * D;
+        uint64_t best = ORC_INF;
+        int64_t arg = -1;
+        for (int64_t r = 0; r < n; ++r) {
+            uint64_t d = orc_ssd(q, ref + r * D, D);
+            int better = (g_fault == 3) ? (d <= best) : (d < best); /* tie rule */
+            if (better) { best = d; arg = r; }
+        }
+        idx[i] = (int32_t)arg;
+        ssd[i] = (uint32_t)(arg < 0 ? 0xFFFFFFFFu : best);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* exact ring bounds                                                   */
+/* ------------------------------------------------------------------ */
+uint64_t orc_isqrt(uint64_t x)
+{
+    uint64_t s = (uint64_t)sqrt((double)x);
+    while (s > 0 && s * s > x) --s;
+    while ((s + 1) * (s + 1) <= x) ++s;
+    return s;
+}
+
+/* Ring of key k for a query: every reference r with
+ *     sqrt(b) - sqrt(c) <= sqrt(a) <= sqrt(b) + sqrt(c)
+ * where a = SSD(r, k), b = SSD(q, k), c = R^2.  For integer a this is
+ *     lo <= a <= hi,  lo = b + c - floor(2 sqrt(bc))  (0 when b <= c),
+ *                     hi = b + c + floor(2 sqrt(bc)).
+ * c == ORC_INF (no radius) gives the whole table. */
+void orc_ring_bounds(uint64_t b, uint64_t c, uint64_t *lo, uint64_t *hi)
+{
+    if (c == ORC_INF) { *lo = 0; *hi = ORC_INF; return; }
+    uint64_t s = orc_isqrt(4 * b * c);
+    if (g_fault == 4) s = orc_isqrt(b * c);           /* lost factor 4 */
+    *lo = (b <= c) ? 0 : b + c - s;
+    if (g_fault == 5) *lo = (b + c > s) ? b + c - s : 0; /* same when b > c */
+    if (g_fault == 6 && b <= c) *lo = c - b;          /* wrong sign case */
+    *hi = b + c + s;
+}
+
+/* ------------------------------------------------------------------ */
+/* pre-processing: sorted key-distance tables                           */
+/* ------------------------------------------------------------------ */
+typedef struct { uint32_t v; int32_t r; } orc_pair;
+
+static int orc_cmp_pair(const void *x, const void *y)
+{
+    const orc_pair *a = (const orc_pair *)x, *b = (const orc_pair *)y;
+    if (a->v != b->v) return a->v < b->v ? -1 : 1;
+    return (a->r > b->r) - (a->r < b->r);
+}
+
+/* T[k*n + j] ascending distances from key k, P[k*n + j] the matching
+ * reference index (ties by index), Piv[r*K + k] = SSD(ref_r, ref_{key_k}). */
+void orc_build(const uint8_t *ref, int64_t n, int D, const int32_t *keys, int K,
+               uint32_t *T, int32_t *P, uint32_t *Piv)
+{
+    for (int k = 0; k < K; ++k) {
+        const uint8_t *kp = ref + (int64_t)keys[k] * D;
+        orc_pair *pr = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(n > 0 ? n : 1));
+        for (int64_t r = 0; r < n; ++r) {
+            uint32_t d = (uint32_t)orc_ssd(ref + r * D, kp, D);
+            Piv[r * K + k] = d;
+            pr[r].v = d;
+            pr[r].r = (int32_t)r;
+        }
+        qsort(pr, (size_t)n, sizeof(orc_pair), orc_cmp_pair);
+        for (int64_t j = 0; j < n; ++j) {
+            T[(int64_t)k * n + j] = pr[j].v;
+            P[(int64_t)k * n + j] = pr[j].r;
+        }
+        free(pr);
+    }
+}
+
+/* first j in [0,n) with t[j] >= v */
+static int64_t orc_lower(const uint32_t *t, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)t[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* first j in [0,n) with t[j] > v */
+static int64_t orc_upper(const uint32_t *t, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)t[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* ------------------------------------------------------------------ */
+/* exact-mode RIANN (Algorithm 1 with a key-point ring and uncapped R)  */
+/* ------------------------------------------------------------------ */
+/* Per query i (patch qp[i*D..]):
+ *   c     = SSD(q, ref[prev[i]]), or "no radius" if prev[i] is outside [0,n)
+ *   b_k   = SSD(q, ref[keys[k]])
+ *   ring k: [lo_k, hi_k] (orc_ring_bounds), located in the sorted table of
+ *           key k by two binary searches: [st_k, en_k), m_k = en_k - st_k
+ *   k*    = smallest m_k (lowest k on ties)
+ *   S     = { P[k*][j], st <= j < en : lo_k <= Piv[r][k] <= hi_k for all k }
+ *   out   = (ssd, idx) minimum over S, ties to the lowest index.
+ * With K == 0 the candidate set is the whole reference set.
+ * Optional per-query outputs (may be NULL): mstar, kstar, nsurv, noprior.
+ * With hinted == 1, prev is a hint only (used the same way). */
+void orc_riann(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int D,
+               const int32_t *keys, int K, const uint32_t *T, const int32_t *P,
+               const uint32_t *Piv, const int32_t *prev,
+               int32_t *idx, uint32_t *ssd, int64_t *mstar, int32_t *kstar,
+               int64_t *nsurv, uint8_t *noprior)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < Q; ++i) {
+        const uint8_t *q = qp + i * D;
+        int32_t pv = prev[i];
+        int np = (pv < 0 || (int64_t)pv >= n);
+        uint64_t c = np ? ORC_INF : orc_ssd(q, ref + (int64_t)pv * D, D);
+        uint64_t *lo = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(K + 1));
+        uint64_t *hi = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(K + 1));
+        int64_t bst = 0, ben = n, bm = n;
+        int bk = -1;
+        for (int k = 0; k < K; ++k) {
+            uint64_t b = orc_ssd(q, ref + (int64_t)keys[k] * D, D);
+            orc_ring_bounds(b, c, &lo[k], &hi[k]);
+            const uint32_t *t = T + (int64_t)k * n;
+            int64_t st = orc_lower(t, n, lo[k]);
+            int64_t en = (hi[k] == ORC_INF) ? n : orc_upper(t, n, hi[k]);
+            if (g_fault == 7) en = (hi[k] == ORC_INF) ? n : orc_lower(t, n, hi[k]); /* open end */
+            int64_t m = en - st;
+            if (bk < 0 || m < bm) { bm = m; bk = k; bst = st; ben = en; }
+        }
+        uint64_t best = ORC_INF;
+        int64_t arg = -1, cnt = 0;
+        for (int64_t j = bst; j < ben; ++j) {
+            int64_t r = (bk < 0) ? j : P[(int64_t)bk * n + j];
+            int in = 1;
+            for (int k = 0; k < K && in; ++k) {
+                uint64_t a = Piv[r * K + k];
+                if (a < lo[k] || a > hi[k]) in = 0;
+            }
+            if (!in) continue;
+            ++cnt;
+            uint64_t d = orc_ssd(q, ref + r * D, D);
+            if (d < best || (d == best && r < arg)) { best = d; arg = r; }
+        }
+        idx[i] = (int32_t)arg;
+        ssd[i] = (uint32_t)(arg < 0 ? 0xFFFFFFFFu : best);
+        if (mstar) mstar[i] = bm;
+        if (kstar) kstar[i] = bk;
+        if (nsurv) nsurv[i] = cnt;
+        if (noprior) noprior[i] = (uint8_t)np;
+        free(lo);
+        free(hi);
+    }
+}
+
+/* Candidate set S of one query, in scan order (for tests of the
+ * containment property).  Returns |S|; writes at most cap indices. */
+int64_t orc_riann_candidates(const uint8_t *q, const uint8_t *ref, int64_t n, int D,
+                             const int32_t *keys, int K, const uint32_t *T,
+                             const int32_t *P, const uint32_t *Piv, int32_t prev,
+                             int32_t *out, int64_t cap)
+{
+    int np = (prev < 0 || (int64_t)prev >= n);
+    uint64_t c = np ? ORC_INF : orc_ssd(q, ref + (int64_t)prev * D, D);
+    uint64_t lo[1024], hi[1024];
+    if (K > 1024) return -1;
+    int64_t bst = 0, ben = n, bm = n;
+    int bk = -1;
+    for (int k = 0; k < K; ++k) {
+        uint64_t b = orc_ssd(q, ref + (int64_t)keys[k] * D, D);
+        orc_ring_bounds(b, c, &lo[k], &hi[k]);
+        const uint32_t *t = T + (int64_t)k * n;
+        int64_t st = orc_lower(t, n, lo[k]);
+        int64_t en = (hi[k] == ORC_INF) ? n : orc_upper(t, n, hi[k]);
+        if (bk < 0 || en - st < bm) { bm = en - st; bk = k; bst = st; ben = en; }
+    }
+    int64_t cnt = 0;
+    for (int64_t j = bst; j < ben; ++j) {
+        int64_t r = (bk < 0) ? j : P[(int64_t)bk * n + j];
+        int in = 1;
+        for (int k = 0; k < K && in; ++k) {
+            uint64_t a = Piv[r * K + k];
+            if (a < lo[k] || a > hi[k]) in = 0;
+        }
+        if (!in) continue;
+        if (cnt < cap) out[cnt] = (int32_t)r;
+        ++cnt;
+    }
+    return cnt;
+}

@@ -1,0 +1,373 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each check ties the oracle to something other than itself: a hand-worked
+example (tests/golden/hand_example.txt), textbook brute force in pure Python,
+library routines (numpy windows, scipy distances, numpy sorting, math.isqrt),
+a sqrt-free form of the ring test derived independently, and the containment
+property that makes exact-mode RIANN equal brute force (every reference at
+distance <= R from the query lies in every key ring, by the triangle
+inequality).  `test_planted_faults` plants each deliberate mistake the oracle
+knows about and checks that at least one pin fails.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+import gen
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "hand_example.txt")
+
+
+def _gold():
+    rows = {}
+    bounds = []
+    with open(GOLD) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            if k == "bounds":
+                bounds.append(tuple(int(x) for x in v))
+            elif k.startswith("riann_"):
+                rows[k] = dict(zip(v[0::2], (int(x) for x in v[1::2])))
+            else:
+                rows[k] = [int(x) for x in v]
+    rows["bounds"] = bounds
+    return rows
+
+
+# ---------------------------------------------------------------- helpers
+def py_ssd(a, b):
+    return sum((int(x) - int(y)) ** 2 for x, y in zip(a, b))
+
+
+def py_bf(Q, R):
+    out = []
+    for q in Q:
+        best, arg = None, -1
+        for r, ref in enumerate(R):
+            d = py_ssd(q, ref)
+            if best is None or d < best:
+                best, arg = d, r
+        out.append((arg, best))
+    return out
+
+
+def lib_bf(Q, R):
+    """Exact NN via scipy's squared-euclidean distances (float64 is exact for
+    these integer magnitudes) and numpy's first-occurrence argmin."""
+    d = cdist(Q.astype(np.float64), R.astype(np.float64), "sqeuclidean")
+    return d.argmin(1).astype(np.int32), d.min(1).astype(np.uint32)
+
+
+def in_ring_exact(a, b, c):
+    """|sqrt(a) - sqrt(b)| <= sqrt(c) decided without square roots.
+    Upper side: sqrt(a) <= sqrt(b) + sqrt(c)  <=>  a-b-c <= 0 or (a-b-c)^2 <= 4bc.
+    Lower side: sqrt(b) <= sqrt(a) + sqrt(c)  <=>  b-a-c <= 0 or (b-a-c)^2 <= 4ac."""
+    u = a - b - c
+    up = u <= 0 or u * u <= 4 * b * c
+    w = b - a - c
+    down = w <= 0 or w * w <= 4 * a * c
+    return up and down
+
+
+def small_case(seed, n=96, K=6, H=20, W=22, p=4, C=1, s=1, dup=0):
+    rng = np.random.default_rng(seed)
+    tex = gen.texture(rng, H, W, C)
+    frame = np.clip(np.rint(tex + rng.normal(0, 2, tex.shape)), 0, 255).astype(np.uint8)
+    rtex = gen.texture(rng, H + 10, W + 10, C)
+    rframe = np.clip(np.rint(rtex), 0, 255).astype(np.uint8)
+    ref = gen.reference_from_frame(rframe, n, p, 1, rng)
+    if dup:
+        ref[rng.choice(n, dup, replace=False)] = ref[rng.choice(n, dup, replace=False)]
+    keys = gen.choose_keys(n, K, rng)
+    return frame, ref, keys, rng
+
+
+# ---------------------------------------------------------------- extraction
+def test_query_counts():
+    assert oracle.field_shape(64, 64, 8, 1) == (57, 57)           # 3,249
+    h, w = oracle.field_shape(720, 1280, 8, 1)
+    assert h * w == 907_649
+    h, w = oracle.field_shape(1080, 1920, 8, 1)
+    assert h * w == 2_052_649
+    h, w = oracle.field_shape(2160, 3840, 12, 2)
+    assert h * w == 2_058_625
+    h, w = oracle.field_shape(360, 640, 12, 2)
+    assert h * w == 55_125
+    h, w = oracle.field_shape(360, 640, 8, 1)
+    assert h * w == 223_449
+
+
+@pytest.mark.parametrize("H,W,C,p,s", [(9, 11, 1, 4, 1), (13, 10, 3, 3, 2),
+                                       (16, 16, 1, 8, 1), (15, 20, 2, 5, 3)])
+def test_extract_matches_numpy_windows(H, W, C, p, s):
+    rng = np.random.default_rng(H * W + C)
+    f = rng.integers(0, 256, (H, W, C), dtype=np.uint8)
+    got = oracle.extract(f, p, s)
+    win = np.lib.stride_tricks.sliding_window_view(f, (p, p, C))[::s, ::s, 0]
+    want = win.reshape(-1, p * p * C)
+    assert got.shape == want.shape
+    np.testing.assert_array_equal(got, want)
+
+
+def test_extract_position_code():
+    # pixel value encodes its position, so any transposition or offset shows
+    H, W = 12, 9
+    f = (np.arange(H)[:, None] * 16 + np.arange(W)[None, :]).astype(np.uint8)[:, :, None]
+    P = oracle.extract(f, 3, 2)
+    hq, wq = oracle.field_shape(H, W, 3, 2)
+    for qy in range(hq):
+        for qx in range(wq):
+            q = P[qy * wq + qx]
+            for dy in range(3):
+                for dx in range(3):
+                    assert q[dy * 3 + dx] == (2 * qy + dy) * 16 + (2 * qx + dx)
+
+
+def test_hand_example_extract_and_nn():
+    g = _gold()
+    f = np.array(g["frame"], np.uint8).reshape(g["H"][0], g["W"][0], 1)
+    P = oracle.extract(f, g["p"][0], g["s"][0])
+    for i in range(4):
+        assert list(P[i]) == g[f"q{i}"]
+    ref = np.array([g[f"r{i}"] for i in range(4)], np.uint8)
+    idx, d = oracle.brute_force(P, ref)
+    assert list(idx) == g["nn_idx"]
+    assert list(d) == g["nn_ssd"]
+
+
+# ---------------------------------------------------------------- distances
+def test_ssd_extremes_and_python():
+    z = np.zeros(64, np.uint8)
+    o = np.full(64, 255, np.uint8)
+    assert oracle.ssd(z, o) == 4_161_600          # 255^2 * 64
+    assert oracle.ssd(np.zeros(192, np.uint8), np.full(192, 255, np.uint8)) == 12_484_800
+    rng = np.random.default_rng(1)
+    for D in (1, 7, 64, 144, 192):
+        a = rng.integers(0, 256, D, dtype=np.uint8)
+        b = rng.integers(0, 256, D, dtype=np.uint8)
+        assert oracle.ssd(a, b) == py_ssd(a, b)
+
+
+def test_bf_matches_pure_python():
+    rng = np.random.default_rng(2)
+    Q = rng.integers(0, 256, (7, 9), dtype=np.uint8)
+    R = rng.integers(0, 256, (23, 9), dtype=np.uint8)
+    R[5] = R[17]                                   # duplicate pair
+    Q[3] = R[17]                                   # exact hit on the duplicate
+    idx, d = oracle.brute_force(Q, R)
+    for i, (a, b) in enumerate(py_bf(Q, R)):
+        assert idx[i] == a and d[i] == b
+    assert idx[3] == 5 and d[3] == 0               # lowest index among ties
+
+
+def test_bf_matches_scipy():
+    frame, ref, _, _ = small_case(3, n=300)
+    P = oracle.extract(frame, 4, 1)
+    idx, d = oracle.brute_force(P, ref)
+    li, ld = lib_bf(P, ref)
+    np.testing.assert_array_equal(idx, li)
+    np.testing.assert_array_equal(d, ld)
+
+
+def test_bf_constant_frame():
+    f = np.full((10, 10, 1), 77, np.uint8)
+    ref = np.random.default_rng(4).integers(0, 256, (50, 16), dtype=np.uint8)
+    ref[31] = 77
+    ref[44] = 77
+    idx, d = oracle.brute_force(oracle.extract(f, 4, 1), ref)
+    assert (idx == 31).all() and (d == 0).all()
+
+
+# ---------------------------------------------------------------- ring bounds
+def test_isqrt():
+    edge = [0, 1, 2, 3, 4, 15, 16, 17, 10**12, (2**26 - 1) ** 2, (2**26 - 1) ** 2 - 1,
+            (2**26) ** 2, 4 * 12_484_800 * 12_484_800, 2**53 - 1]
+    rng = np.random.default_rng(5)
+    vals = edge + [int(x) for x in rng.integers(0, 2**53, 2000, dtype=np.int64)]
+    for x in vals:
+        assert oracle.isqrt(x) == math.isqrt(x), x
+    for r in rng.integers(1, 2**26, 500):
+        r = int(r)
+        for x in (r * r - 1, r * r, r * r + 1):
+            assert oracle.isqrt(x) == math.isqrt(x)
+
+
+def test_ring_bounds_hand():
+    for b, c, lo, hi in _gold()["bounds"]:
+        assert oracle.ring_bounds(b, c) == (lo, hi)
+    assert oracle.ring_bounds(123, None) == (0, oracle.INF)
+
+
+def test_ring_bounds_exhaustive_small():
+    for b in range(0, 40):
+        for c in range(0, 40):
+            lo, hi = oracle.ring_bounds(b, c)
+            for a in range(0, 200):
+                assert (lo <= a <= hi) == in_ring_exact(a, b, c), (a, b, c)
+
+
+def test_ring_bounds_random_large():
+    rng = np.random.default_rng(6)
+    M = 12_484_800
+    for _ in range(20000):
+        b, c = (int(x) for x in rng.integers(0, M + 1, 2))
+        lo, hi = oracle.ring_bounds(b, c)
+        for a in (lo - 1, lo, lo + 1, hi - 1, hi, hi + 1,
+                  int(rng.integers(0, 2 * M))):
+            if a < 0:
+                continue
+            assert (lo <= a <= hi) == in_ring_exact(a, b, c), (a, b, c)
+
+
+# ---------------------------------------------------------------- tables
+def test_tables_hand():
+    g = _gold()
+    ref = np.array([g[f"r{i}"] for i in range(4)], np.uint8)
+    t = oracle.Tables(ref, np.array(g["keys"], np.int32))
+    for r in range(4):
+        assert list(t.Piv[r]) == g[f"piv{r}"]
+    assert list(t.T[0]) == g["T0"] and list(t.P[0]) == g["P0"]
+    assert list(t.T[1]) == g["T1"] and list(t.P[1]) == g["P1"]
+
+
+def test_tables_match_numpy_sort():
+    _, ref, keys, _ = small_case(7, n=257, K=5, dup=20)
+    t = oracle.Tables(ref, keys)
+    d = cdist(ref.astype(np.float64), ref[keys].astype(np.float64), "sqeuclidean")
+    np.testing.assert_array_equal(t.Piv, d.astype(np.uint32))
+    for k in range(len(keys)):
+        order = np.lexsort((np.arange(len(ref)), d[:, k]))   # by value, then index
+        np.testing.assert_array_equal(t.P[k], order)
+        np.testing.assert_array_equal(t.T[k], d[order, k].astype(np.uint32))
+
+
+# ---------------------------------------------------------------- RIANN
+def test_riann_hand():
+    g = _gold()
+    f = np.array(g["frame"], np.uint8).reshape(3, 3, 1)
+    P = oracle.extract(f, 2, 1)
+    ref = np.array([g[f"r{i}"] for i in range(4)], np.uint8)
+    t = oracle.Tables(ref, np.array(g["keys"], np.int32))
+    out = t.riann(P[1:2], np.array([0], np.int32))
+    want = g["riann_q1_prev0"]
+    for k in ("idx", "ssd", "mstar", "kstar", "nsurv"):
+        assert int(out[k][0]) == want[k], k
+
+
+@pytest.mark.parametrize("seed,K,mode", [(10, 6, "random"), (11, 1, "random"),
+                                         (12, 0, "random"), (13, 6, "noprior"),
+                                         (14, 6, "exact"), (15, 6, "mixed"),
+                                         (16, 96, "random"), (17, 3, "dups")])
+def test_riann_equals_brute_force(seed, K, mode):
+    frame, ref, keys, rng = small_case(seed, n=96, K=K, dup=12 if mode == "dups" else 0)
+    if K == 96:
+        keys = np.arange(96, dtype=np.int32)
+    P = oracle.extract(frame, 4, 1)
+    bi, bd = oracle.brute_force(P, ref)
+    hq, wq = oracle.field_shape(frame.shape[0], frame.shape[1], 4, 1)
+    if mode == "noprior":
+        prev = np.full(len(P), -1, np.int32)
+    elif mode == "exact":
+        prev = bi.copy()
+    elif mode == "mixed":
+        prev = gen.random_field(hq, wq, len(ref), rng, no_prior_p=0.3).reshape(-1)
+        prev[rng.random(len(P)) < 0.2] = len(ref) + 5          # out of range
+    else:
+        prev = gen.random_field(hq, wq, len(ref), rng).reshape(-1)
+    t = oracle.Tables(ref, keys)
+    out = t.riann(P, prev)
+    np.testing.assert_array_equal(out["idx"], bi)
+    np.testing.assert_array_equal(out["ssd"], bd)
+    bad = (prev < 0) | (prev >= len(ref))
+    np.testing.assert_array_equal(out["noprior"].astype(bool), bad)
+    if K == 0:
+        assert (out["nsurv"] == len(ref)).all() and (out["mstar"] == len(ref)).all()
+    assert (out["nsurv"] <= out["mstar"]).all()
+    assert (out["nsurv"] >= 1).all()
+
+
+def test_containment_and_prev_in_candidates():
+    frame, ref, keys, rng = small_case(20, n=128, K=8, dup=8)
+    P = oracle.extract(frame, 4, 1)
+    t = oracle.Tables(ref, keys)
+    D = cdist(P.astype(np.float64), ref.astype(np.float64), "sqeuclidean")
+    for i in rng.choice(len(P), 60, replace=False):
+        pv = int(rng.integers(0, len(ref)))
+        S = set(t.candidates(P[i], pv).tolist())
+        c = D[i, pv]
+        # every reference within the radius is a candidate; so is r_prev
+        within = set(np.nonzero(D[i] <= c)[0].tolist())
+        assert within <= S
+        assert pv in S
+        # and every candidate lies in every key ring (exact sqrt-free test)
+        for r in S:
+            for k, kk in enumerate(keys):
+                assert in_ring_exact(int(t.Piv[r, k]), int(D[i, kk]), int(c))
+
+
+def test_riann_zero_radius():
+    # previous match is an exact copy of the query: S = references at the
+    # same key distances as the query (R = 0), and the answer has ssd 0
+    frame, ref, keys, rng = small_case(21, n=80, K=5)
+    P = oracle.extract(frame, 4, 1)
+    ref = ref.copy()
+    ref[17] = P[33]
+    ref[50] = P[33]
+    t = oracle.Tables(ref, keys)
+    out = t.riann(P[33:34], np.array([50], np.int32))
+    assert out["idx"][0] == 17 and out["ssd"][0] == 0
+    S = t.candidates(P[33], 50)
+    for r in S:
+        assert (t.Piv[r] == t.Piv[17]).all()
+
+
+def test_riann_workload_tiny_frames():
+    wl = gen.make_workload("tiny")
+    t = oracle.Tables(wl.ref, wl.keys)
+    hq, wq = oracle.field_shape(64, 64, 8, 1)
+    prev = np.full(hq * wq, -1, np.int32)
+    for fr in range(3):
+        P = oracle.extract(wl.frame(fr), 8, 1)
+        assert len(P) == 3249
+        bi, bd = oracle.brute_force(P, wl.ref)
+        out = t.riann(P, prev)
+        np.testing.assert_array_equal(out["idx"], bi)
+        np.testing.assert_array_equal(out["ssd"], bd)
+        prev = out["idx"]
+
+
+# ---------------------------------------------------------------- planted faults
+def _pins_pass():
+    """Cheap versions of the pins above; True when all hold."""
+    try:
+        test_extract_position_code()
+        test_extract_matches_numpy_windows(13, 10, 3, 3, 2)
+        test_hand_example_extract_and_nn()
+        test_bf_matches_pure_python()
+        test_ring_bounds_hand()
+        test_ring_bounds_exhaustive_small()
+        test_tables_hand()
+        test_riann_hand()
+        test_riann_equals_brute_force(10, 6, "random")
+    except AssertionError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7])
+def test_planted_faults(fault):
+    assert _pins_pass()
+    oracle.set_fault(fault)
+    try:
+        caught = not _pins_pass()
+    finally:
+        oracle.set_fault(0)
+    assert caught, f"planted fault {fault} was not caught by any pin"
+    assert _pins_pass()
