@@ -1,0 +1,235 @@
+/*
+ * riann.h -- C ABI of libriann: RIANN ANN fields on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: Ben-Zrihem & Zelnik-Manor, "Approximate Nearest Neighbor Fields in
+ * Video" (arXiv 1508.07953).  Problem statement (Sec. 1 and Fig. 1): a
+ * reference set R of n patches is fixed for the whole video; for every frame,
+ * every query patch q_{x,y,t} (Sec. 3.1) is matched to a reference patch,
+ * giving a dense ANN field per frame.
+ *
+ * This library computes the field EXACTLY: idx(x,y) is the lowest reference
+ * index among those at minimum squared L2 distance (SSD over raw uint8
+ * values) from the query, and ssd(x,y) is that distance.  It gets there with
+ * the paper's ring intersection (Sec. 3.2-3.4, Algorithm 1) in exact mode:
+ * the radius R is the distance to the previous frame's match and is not
+ * capped, and rings are drawn around K key points chosen from R.  Every
+ * reference within R of the query lies in every ring (triangle inequality),
+ * so the result never depends on the previous field; a poor or missing
+ * previous match only costs time.  Queries whose smallest ring is large are
+ * answered by an exact int8 matrix-core search instead.
+ *
+ * Conventions
+ *   patches   p x p x C windows, flattened in (dy, dx, c) order; D = p*p*C,
+ *             1 <= D <= 256.
+ *   frames    H x W x C uint8, channels last, rows `pitch` bytes apart
+ *             (pitch >= W*C), device memory.
+ *   fields    Hq x Wq row-major, Hq = (H-p)/s + 1, Wq = (W-p)/s + 1; the query
+ *             at field position (i, j) has its top-left corner at pixel
+ *             (x, y) = (s*j, s*i).  Indices are 0-based int32.
+ *   prev      previous frame's field (device, Hq x Wq int32).  An entry of -1
+ *             or outside [0, n) means "no prior": that query's rings are the
+ *             whole set.  prev may be NULL (every query without prior).
+ *             prev must not alias out.
+ *   streams   `hip_stream` is a hipStream_t (NULL = the default stream).
+ *             match / full_search / batch calls only enqueue work on that
+ *             stream and return; argument errors are reported synchronously;
+ *             a device fault surfaces as RIANN_E_DEVICE from the next call
+ *             that synchronises (riann_get_stats, riann_save, riann_destroy).
+ *   ownership the index owns device copies of the reference set and its
+ *             tables; the caller owns frames and fields.
+ *   threads   one index may be used from several host threads and streams at
+ *             once; each stream gets its own scratch space.
+ *   errors    no exceptions cross this ABI; every call returns a status and
+ *             riann_last_error() gives a message for the calling thread.
+ */
+#ifndef RIANN_H
+#define RIANN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct riann_index *riann_index_t;
+
+typedef enum {
+    RIANN_OK = 0,
+    RIANN_E_INVALID = -1,      /* bad argument, shape, alias or state        */
+    RIANN_E_NOMEM = -2,        /* device or host allocation failed           */
+    RIANN_E_DEVICE = -3,       /* HIP runtime / kernel error                  */
+    RIANN_E_UNSUPPORTED = -4,  /* valid request this build does not support  */
+    RIANN_E_IO = -5            /* file error in save / load                   */
+} riann_status_t;
+
+typedef struct riann_params {
+    int32_t patch;             /* p, patch side in pixels (Sec. 4 uses 8)     */
+    int32_t channels;          /* C, 1 (gray) or 3 (RGB)                       */
+    int32_t stride;            /* s, step between query windows (>= 1)        */
+    int32_t n_keys;            /* K, number of key points (0 <= K <= 64)      */
+    int64_t n_ref;             /* n, number of reference patches (>= 1)       */
+    int64_t dense_threshold;   /* queries whose smallest ring holds more than
+                                  this many candidates use the dense search;
+                                  < 0 selects the library default             */
+    uint32_t flags;            /* reserved, must be 0                          */
+    uint32_t reserved;         /* must be 0                                    */
+} riann_params_t;
+
+/* One frame of a batch (riann_match_batch). */
+typedef struct riann_frame_desc {
+    const uint8_t *frame;      /* device, H x W x C, row pitch `pitch`         */
+    int32_t H, W;
+    int64_t pitch;
+    const int32_t *prev;       /* device Hq x Wq, or NULL (no prior); ignored
+                                  when mode == RIANN_MODE_FULL                 */
+    int32_t *out;              /* device Hq x Wq                               */
+    uint32_t *ssd;             /* device Hq x Wq (may be NULL)                 */
+    int32_t mode;              /* RIANN_MODE_RING or RIANN_MODE_FULL           */
+    int32_t reserved;
+} riann_frame_desc_t;
+
+#define RIANN_MODE_RING 0
+#define RIANN_MODE_FULL 1
+
+/* Counters accumulated by every match call since build/load or the last
+ * riann_reset_stats.  Ring statistics follow the paper's observation that
+ * more temporal change means larger rings and more work (Sec. 3.3, Fig. 4). */
+typedef struct riann_stats {
+    uint64_t frames;           /* frames processed                             */
+    uint64_t queries;          /* query patches processed                      */
+    uint64_t ring_queries;     /* queries answered by the ring scan            */
+    uint64_t dense_queries;    /* queries answered by the dense search         */
+    uint64_t no_prior;         /* queries whose prev entry was -1/out of range  */
+    uint64_t sum_mstar;        /* sum over ring-phase queries of the smallest
+                                  ring size m* (all queries of RING frames)    */
+    uint64_t sum_survivors;    /* sum over ring-scanned queries of |S|, the
+                                  number of references inside all K rings     */
+    uint64_t sum_mstar_ring;   /* sum of m* over ring-scanned queries only     */
+} riann_stats_t;
+
+/*
+ * riann_build -- pre-processing (Sec. 3.3 and Sec. 3.4 "Building a reference
+ * model"): copy the reference set to the device and build, for each key
+ * point k, the ascending list of distances SSD(r, k) over all references r
+ * (with the matching reference indices; ties ordered by index), plus the
+ * n x K table SSD(r, k).  The paper sorts the full n x n matrix; this library
+ * keeps only K columns of it, so memory is O(K n) instead of O(n^2).
+ *
+ *   ref_host   host, n x D uint8, row-major, (dy, dx, c) patch order
+ *   key_idx    host, K distinct indices in [0, n) (the key points)
+ *   p          shapes and options (see riann_params_t)
+ *   hip_stream stream used for the uploads (the call synchronises it)
+ *   out        receives the new index; unchanged on error
+ * Returns RIANN_E_INVALID for bad shapes or duplicate/out-of-range keys,
+ * RIANN_E_NOMEM if device memory is short.
+ */
+riann_status_t riann_build(const uint8_t *ref_host, const int32_t *key_idx,
+                           const riann_params_t *p, void *hip_stream,
+                           riann_index_t *out);
+
+/*
+ * riann_match_frame -- the online search of Algorithm 1 for one frame, in
+ * exact mode.  For every query patch q of `frame`:
+ *   c   = SSD(q, R[prev])            radius^2 from the previous match
+ *   b_k = SSD(q, key_k)              distance to each key point
+ *   ring k = { r : |d(r,k) - d(q,k)| <= sqrt(c) }, closed, found by two
+ *            binary searches in key k's sorted list (Sec. 3.3)
+ *   S   = references in every ring, scanned from the smallest ring
+ *   out = arg min over S of SSD(q, r) (lowest index on ties), ssd = the min.
+ * Queries whose smallest ring is larger than the dense threshold are answered
+ * by the exact dense search instead (same result).
+ *
+ *   frame_dev  device H x W x C uint8 with row pitch `pitch` bytes
+ *   prev_dev   device Hq x Wq int32 or NULL; must not overlap out_dev
+ *   out_dev    device Hq x Wq int32 (written)
+ *   ssd_dev    device Hq x Wq uint32 (written) or NULL
+ * Asynchronous on hip_stream.
+ */
+riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev,
+                                 int32_t H, int32_t W, int64_t pitch,
+                                 const int32_t *prev_dev, int32_t *out_dev,
+                                 uint32_t *ssd_dev, void *hip_stream);
+
+/*
+ * riann_full_search -- exact nearest neighbour of every query by exhaustive
+ * search (the exact NN the paper uses for its analyses, Sec. 3.1), used for
+ * the first frame (Algorithm 1 starts from a random field instead) and at
+ * scene cuts.  Runs as an int8 matrix-core GEMM on 128-shifted patches with
+ * int32 accumulation; all distances are exact integers.
+ * Arguments as riann_match_frame without prev.  Asynchronous on hip_stream.
+ */
+riann_status_t riann_full_search(riann_index_t h, const uint8_t *frame_dev,
+                                 int32_t H, int32_t W, int64_t pitch,
+                                 int32_t *out_dev, uint32_t *ssd_dev,
+                                 void *hip_stream);
+
+/*
+ * riann_match_batch -- several frames of possibly different sizes (one per
+ * live stream) matched in one submission; each descriptor is processed as
+ * riann_match_frame (mode RING) or riann_full_search (mode FULL).
+ *   descs  host array of n descriptors (copied before return)
+ * Asynchronous on hip_stream.  Output fields of different descriptors must
+ * not overlap.
+ */
+riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *descs,
+                                 int32_t n, void *hip_stream);
+
+/*
+ * riann_footprint -- device bytes an index with parameters p needs, plus the
+ * per-stream scratch for frames of H x W (H = W = 0: index only).
+ */
+riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W,
+                               int64_t *bytes);
+
+/* riann_get_stats -- synchronises the device and copies the counters. */
+riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s);
+riann_status_t riann_reset_stats(riann_index_t h);
+
+/* riann_get_params -- the parameters the index was built with, with the
+ * dense threshold resolved to the value in use. */
+riann_status_t riann_get_params(riann_index_t h, riann_params_t *p);
+
+/*
+ * riann_save / riann_load -- write / read the index (reference set, keys and
+ * tables) to / from a file, so the pre-processing is paid once
+ * (Sec. 4: a single pre-processed global model serves many videos).
+ * riann_save synchronises the device.  riann_load uploads on hip_stream and
+ * synchronises it.  Format: little-endian binary, versioned header.
+ */
+riann_status_t riann_save(riann_index_t h, const char *path);
+riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out);
+
+/* riann_destroy -- synchronises the device and frees the index. */
+riann_status_t riann_destroy(riann_index_t h);
+
+/*
+ * Kernel timing (diagnostics).  While enabled, every kernel the index
+ * launches is bracketed by two HIP events recorded on the launch stream;
+ * riann_get_profile synchronises, converts the pending event pairs into
+ * milliseconds and returns the totals per kernel since profiling was enabled.
+ * Kernels: RIANN_K_RING (ring phase), RIANN_K_SCAN (ring scan and
+ * verification), RIANN_K_DENSE (dense search of routed queries),
+ * RIANN_K_FULL (dense search of whole frames).
+ */
+#define RIANN_K_RING 0
+#define RIANN_K_SCAN 1
+#define RIANN_K_DENSE 2
+#define RIANN_K_FULL 3
+#define RIANN_K_COUNT 4
+typedef struct riann_profile {
+    uint64_t launches[RIANN_K_COUNT];
+    double ms[RIANN_K_COUNT];
+} riann_profile_t;
+riann_status_t riann_set_profiling(riann_index_t h, int enable);
+riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *riann_last_error(void);
+
+/* ABI version, (major << 16) | minor. */
+uint32_t riann_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIANN_H */

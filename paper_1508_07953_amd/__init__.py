@@ -1,0 +1,269 @@
+"""RIANN exact ANN fields on AMD Instinct MI355X -- Python binding.
+
+Thin ctypes layer over libriann.so (C ABI in include/riann.h).  It only
+marshals arguments: every step of the search runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.
+
+    idx = Index.build(ref, keys, patch=8, channels=1, stride=1)
+    out, ssd = idx.full_search(frame0)                 # frame 0 / scene cut
+    out, ssd = idx.match_frame(frame1, prev=out)       # ring-intersection search
+
+Frames are CUDA (HIP) uint8 tensors of shape (H, W) or (H, W, C); fields are
+int32 (Hq, Wq) with Hq = (H - p) // s + 1, Wq = (W - p) // s + 1.
+
+The library must be built (``__graft_entry__.build()`` or
+``python -m paper_1508_07953_amd._build``); importing this package without it
+raises ImportError -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libriann.so")
+
+RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, RIANN_E_IO = (
+    0, -1, -2, -3, -4, -5)
+MODE_RING, MODE_FULL = 0, 1
+
+# every symbol include/riann.h declares
+EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
+           "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
+           "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
+           "riann_set_profiling", "riann_get_profile"]
+KERNELS = ["ring", "scan", "dense", "full"]
+
+
+class RiannError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"riann status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("patch", C.c_int32), ("channels", C.c_int32), ("stride", C.c_int32),
+                ("n_keys", C.c_int32), ("n_ref", C.c_int64), ("dense_threshold", C.c_int64),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class FrameDesc(C.Structure):
+    _fields_ = [("frame", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32),
+                ("pitch", C.c_int64), ("prev", C.c_void_p), ("out", C.c_void_p),
+                ("ssd", C.c_void_p), ("mode", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in
+                ("frames", "queries", "ring_queries", "dense_queries", "no_prior",
+                 "sum_mstar", "sum_survivors", "sum_mstar_ring")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.riann_build.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.riann_match_frame.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp]
+    L.riann_full_search.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp]
+    L.riann_match_batch.argtypes = [vp, C.POINTER(FrameDesc), i32, vp]
+    L.riann_footprint.argtypes = [C.POINTER(Params), i32, i32, C.POINTER(i64)]
+    L.riann_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.riann_reset_stats.argtypes = [vp]
+    L.riann_get_params.argtypes = [vp, C.POINTER(Params)]
+    L.riann_save.argtypes = [vp, C.c_char_p]
+    L.riann_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
+    L.riann_destroy.argtypes = [vp]
+    L.riann_set_profiling.argtypes = [vp, C.c_int]
+    L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
+    L.riann_last_error.argtypes = []
+    L.riann_last_error.restype = C.c_char_p
+    L.riann_version.argtypes = []
+    L.riann_version.restype = C.c_uint32
+    for name in EXPORTS:
+        if name not in ("riann_last_error", "riann_version"):
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != RIANN_OK:
+        raise RiannError(status, _lib.riann_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+def field_shape(H: int, W: int, patch: int, stride: int) -> Tuple[int, int]:
+    return (H - patch) // stride + 1, (W - patch) // stride + 1
+
+
+def make_params(n_ref: int, n_keys: int, patch: int, channels: int, stride: int,
+                dense_threshold: int = -1) -> Params:
+    return Params(patch, channels, stride, n_keys, n_ref, dense_threshold, 0, 0)
+
+
+def footprint(n_ref: int, n_keys: int, patch: int, channels: int, stride: int,
+              H: int = 0, W: int = 0) -> int:
+    """Device bytes of an index plus one stream's scratch for H x W frames."""
+    b = C.c_int64()
+    p = make_params(n_ref, n_keys, patch, channels, stride)
+    _check(_lib.riann_footprint(C.byref(p), H, W, C.byref(b)))
+    return int(b.value)
+
+
+def _frame_geom(frame, channels: int):
+    """(H, W, pitch) of a uint8 device tensor (H, W) or (H, W, C)."""
+    import torch
+    if frame.dtype != torch.uint8 or not frame.is_cuda:
+        raise TypeError("frame must be a uint8 device tensor")
+    if frame.dim() == 2:
+        frame = frame.unsqueeze(-1)
+    if frame.dim() != 3 or frame.shape[2] != channels:
+        raise ValueError(f"frame must be (H, W, {channels})")
+    if frame.stride(2) != 1 or frame.stride(1) != channels:
+        raise ValueError("frame rows must be contiguous (H, W, C) with C innermost")
+    return int(frame.shape[0]), int(frame.shape[1]), int(frame.stride(0))
+
+
+class Index:
+    """A built reference index (owns device tables)."""
+
+    def __init__(self, handle: int, params: Params):
+        self._h = C.c_void_p(handle)
+        self.params = params
+
+    # ---------------------------------------------------------------- build
+    @classmethod
+    def build(cls, ref: np.ndarray, keys: Sequence[int], patch: int, channels: int = 1,
+              stride: int = 1, dense_threshold: int = -1, stream=None) -> "Index":
+        ref = np.ascontiguousarray(ref, dtype=np.uint8)
+        keys = np.ascontiguousarray(np.asarray(keys, dtype=np.int32))
+        if ref.ndim != 2 or ref.shape[1] != patch * patch * channels:
+            raise ValueError("ref must be (n, patch*patch*channels) uint8")
+        p = make_params(ref.shape[0], len(keys), patch, channels, stride, dense_threshold)
+        h = C.c_void_p()
+        _check(_lib.riann_build(ref.ctypes.data, keys.ctypes.data if len(keys) else None,
+                                C.byref(p), _stream_ptr(stream), C.byref(h)))
+        q = Params()
+        _check(_lib.riann_get_params(h, C.byref(q)))
+        return cls(h.value, q)
+
+    @classmethod
+    def load(cls, path: str, stream=None) -> "Index":
+        h = C.c_void_p()
+        _check(_lib.riann_load(path.encode(), _stream_ptr(stream), C.byref(h)))
+        q = Params()
+        _check(_lib.riann_get_params(h, C.byref(q)))
+        return cls(h.value, q)
+
+    def save(self, path: str) -> None:
+        _check(_lib.riann_save(self._h, path.encode()))
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(_lib.riann_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- queries
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def field_shape(self, H: int, W: int) -> Tuple[int, int]:
+        return field_shape(H, W, self.params.patch, self.params.stride)
+
+    def _outputs(self, H, W, device, out, ssd):
+        import torch
+        hq, wq = self.field_shape(H, W)
+        if hq <= 0 or wq <= 0:
+            # let the library report the shape error; nothing is written
+            hq, wq = 1, 1
+        if out is None:
+            out = torch.empty((hq, wq), dtype=torch.int32, device=device)
+        if ssd is None:
+            ssd = torch.empty((hq, wq), dtype=torch.int32, device=device)
+        for t in (out, ssd):
+            if t.numel() != hq * wq or not t.is_contiguous() or t.element_size() != 4:
+                raise ValueError("out/ssd must be contiguous 4-byte (Hq, Wq) tensors")
+        return out, ssd
+
+    def match_frame(self, frame, prev=None, out=None, ssd=None, stream=None):
+        """Ring-intersection search of one frame given the previous field."""
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        out, ssd = self._outputs(H, W, frame.device, out, ssd)
+        if prev is not None:
+            if prev.numel() != out.numel() or not prev.is_contiguous() or prev.element_size() != 4:
+                raise ValueError("prev must be a contiguous int32 (Hq, Wq) tensor")
+        _check(_lib.riann_match_frame(self._h, frame.data_ptr(), H, W, pitch,
+                                      prev.data_ptr() if prev is not None else None,
+                                      out.data_ptr(), ssd.data_ptr(), _stream_ptr(stream)))
+        return out, ssd
+
+    def full_search(self, frame, out=None, ssd=None, stream=None):
+        """Exact exhaustive search of one frame (first frame, scene cuts)."""
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        out, ssd = self._outputs(H, W, frame.device, out, ssd)
+        _check(_lib.riann_full_search(self._h, frame.data_ptr(), H, W, pitch, out.data_ptr(),
+                                      ssd.data_ptr(), _stream_ptr(stream)))
+        return out, ssd
+
+    def match_batch(self, items: List[dict], stream=None) -> None:
+        """items: dicts with frame, out, ssd (optional), prev (optional), mode."""
+        arr = (FrameDesc * len(items))()
+        for i, it in enumerate(items):
+            H, W, pitch = _frame_geom(it["frame"], self.params.channels)
+            prev = it.get("prev")
+            ssd = it.get("ssd")
+            arr[i] = FrameDesc(it["frame"].data_ptr(), H, W, pitch,
+                               prev.data_ptr() if prev is not None else None,
+                               it["out"].data_ptr(), ssd.data_ptr() if ssd is not None else None,
+                               int(it.get("mode", MODE_RING)), 0)
+        _check(_lib.riann_match_batch(self._h, arr, len(items), _stream_ptr(stream)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.riann_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self) -> None:
+        _check(_lib.riann_reset_stats(self._h))
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(_lib.riann_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        """Per-kernel launch counts and total milliseconds (HIP events)."""
+        p = Profile()
+        _check(_lib.riann_get_profile(self._h, C.byref(p)))
+        return {k: dict(launches=int(p.launches[i]), ms=float(p.ms[i]))
+                for i, k in enumerate(KERNELS)}

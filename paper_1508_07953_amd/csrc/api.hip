@@ -1,0 +1,643 @@
+// api.hip -- host side of libriann: argument checking, the pre-processing
+// (sorted key-distance tables, Sec. 3.3), per-stream scratch and the launch
+// sequence of each entry point declared in include/riann.h.
+#include "riann.h"
+#include "riann_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace riann;
+
+struct riann_index {
+    riann_params_t prm{};
+    int D = 0, Dp = 0, K = 0;
+    int64_t n = 0, n_pad = 0;
+    int64_t threshold = 0;
+    int device = 0;
+    // host copies (kept for riann_save)
+    std::vector<uint8_t> ref;
+    std::vector<int32_t> keys;
+    std::vector<uint32_t> T;
+    std::vector<int32_t> P;
+    std::vector<uint32_t> Piv;
+    // device
+    void *dmem = nullptr;
+    DevIndex dix{};
+    unsigned long long *dstats = nullptr;
+    std::atomic<uint64_t> frames{0}, full_queries{0};
+    std::mutex mu;
+    std::map<hipStream_t, Work> work;
+    // kernel timing (riann_set_profiling)
+    std::atomic<bool> profiling{false};
+    std::mutex pmu;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    uint64_t prof_launches[RIANN_K_COUNT] = {0, 0, 0, 0};
+    double prof_ms[RIANN_K_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+riann_status_t fail(riann_status_t st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+riann_status_t hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return RIANN_E_DEVICE;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+riann_status_t check_params(const riann_params_t *p) {
+    if (!p) return fail(RIANN_E_INVALID, "params is NULL");
+    if (p->patch < 1 || p->channels < 1 || p->stride < 1)
+        return fail(RIANN_E_INVALID, "patch, channels and stride must be >= 1");
+    const int64_t D = (int64_t)p->patch * p->patch * p->channels;
+    if (D > 256) return fail(RIANN_E_UNSUPPORTED, "patch dimension p*p*C must be <= 256");
+    if (p->n_ref < 1 || p->n_ref > (int64_t)0x7FFFFF00)
+        return fail(RIANN_E_INVALID, "n_ref must be in [1, 2^31 - 256]");
+    if (p->n_keys < 0 || p->n_keys > kMaxKeys)
+        return fail(RIANN_E_INVALID, "n_keys must be in [0, 64]");
+    if (p->n_keys > p->n_ref) return fail(RIANN_E_INVALID, "n_keys exceeds n_ref");
+    if (p->flags != 0 || p->reserved != 0)
+        return fail(RIANN_E_INVALID, "flags and reserved must be 0");
+    return RIANN_OK;
+}
+
+int64_t default_threshold(int64_t n) {
+    // ring scan while the smallest ring is below ~1/16 of the set: a scanned
+    // candidate costs about 16x a dense (query, reference) pair
+    int64_t t = n / 16;
+    return t < 64 ? 64 : t;
+}
+
+int64_t index_bytes(int64_t n, int D, int K) {
+    const int Dp = (int)round_up(D, 32);
+    const int64_t n_pad = round_up(n, kTile);
+    return n_pad * Dp + n_pad * 4 + (int64_t)K * n * 8 + n * (int64_t)std::max(K, 1) * 4 +
+           (int64_t)K * 4 + ST_COUNT * 8 + 4096;
+}
+
+int64_t work_bytes(int64_t Q) { return Q * 16 + Q * 8 + 64 + 1024; }
+
+// host pre-processing: pivot table and sorted per-key lists
+void build_tables(riann_index *h) {
+    const int64_t n = h->n;
+    const int D = h->D, K = h->K;
+    h->Piv.assign((size_t)n * std::max(K, 1), 0);
+    h->T.assign((size_t)K * n, 0);
+    h->P.assign((size_t)K * n, 0);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto piv_rows = [&](int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r) {
+            const uint8_t *a = &h->ref[(size_t)r * D];
+            for (int k = 0; k < K; ++k) {
+                const uint8_t *b = &h->ref[(size_t)h->keys[k] * D];
+                uint32_t s = 0;
+                for (int i = 0; i < D; ++i) {
+                    int d = (int)a[i] - (int)b[i];
+                    s += (uint32_t)(d * d);
+                }
+                h->Piv[(size_t)r * K + k] = s;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back(piv_rows, n * t / nt, n * (t + 1) / nt);
+    for (auto &x : th) x.join();
+    th.clear();
+    auto sort_keys = [&](int k0, int k1) {
+        std::vector<int32_t> idx((size_t)n);
+        for (int k = k0; k < k1; ++k) {
+            for (int64_t r = 0; r < n; ++r) idx[(size_t)r] = (int32_t)r;
+            std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+                return h->Piv[(size_t)x * K + k] < h->Piv[(size_t)y * K + k];
+            });
+            for (int64_t j = 0; j < n; ++j) {
+                h->P[(size_t)k * n + j] = idx[(size_t)j];
+                h->T[(size_t)k * n + j] = h->Piv[(size_t)idx[(size_t)j] * K + k];
+            }
+        }
+    };
+    for (unsigned t = 0; t < nt && (int)t < K; ++t)
+        th.emplace_back(sort_keys, (int)(K * (int64_t)t / std::min<int64_t>(nt, K)),
+                        (int)(K * (int64_t)(t + 1) / std::min<int64_t>(nt, K)));
+    for (auto &x : th) x.join();
+}
+
+// device upload of everything an index needs
+riann_status_t upload(riann_index *h, hipStream_t st) {
+    const int64_t n = h->n, n_pad = h->n_pad;
+    const int D = h->D, Dp = h->Dp, K = h->K;
+    std::vector<int8_t> Rv((size_t)n_pad * Dp, 0);
+    std::vector<int32_t> Rc((size_t)n_pad, kRcPad);
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t s = 0;
+        for (int i = 0; i < D; ++i) {
+            const int v = (int)h->ref[(size_t)r * D + i] - 128;
+            Rv[(size_t)r * Dp + i] = (int8_t)v;
+            s += v * (v + 2);
+        }
+        Rc[(size_t)r] = s;
+    }
+    const size_t szRv = (size_t)n_pad * Dp, szRc = (size_t)n_pad * 4,
+                 szT = (size_t)K * n * 4, szP = (size_t)K * n * 4,
+                 szPiv = (size_t)n * std::max(K, 1) * 4, szK = (size_t)std::max(K, 1) * 4,
+                 szS = ST_COUNT * 8;
+    size_t off[8], tot = 0;
+    const size_t sz[7] = {szRv, szRc, szT, szP, szPiv, szK, szS};
+    for (int i = 0; i < 7; ++i) {
+        off[i] = tot;
+        tot += round_up((int64_t)sz[i], 256);
+    }
+    hipError_t e = hipMalloc(&h->dmem, tot);
+    if (e != hipSuccess) {
+        h->dmem = nullptr;
+        return fail(RIANN_E_NOMEM, std::string("hipMalloc of the index failed: ") +
+                                       hipGetErrorString(e));
+    }
+    char *b = (char *)h->dmem;
+    h->dix.Rv = (const int8_t *)(b + off[0]);
+    h->dix.Rc = (const int32_t *)(b + off[1]);
+    h->dix.T = (const uint32_t *)(b + off[2]);
+    h->dix.P = (const int32_t *)(b + off[3]);
+    h->dix.Piv = (const uint32_t *)(b + off[4]);
+    h->dix.keys = (const int32_t *)(b + off[5]);
+    h->dstats = (unsigned long long *)(b + off[6]);
+    h->dix.n = n;
+    h->dix.n_pad = n_pad;
+    h->dix.D = D;
+    h->dix.Dp = Dp;
+    h->dix.K = K;
+    h->dix.p = h->prm.patch;
+    h->dix.C = h->prm.channels;
+    h->dix.s = h->prm.stride;
+    struct { void *dst; const void *src; size_t n; } cp[] = {
+        {b + off[0], Rv.data(), szRv},          {b + off[1], Rc.data(), szRc},
+        {b + off[2], h->T.data(), szT},         {b + off[3], h->P.data(), szP},
+        {b + off[4], h->Piv.data(), (size_t)n * K * 4},
+        {b + off[5], h->keys.data(), (size_t)K * 4},
+    };
+    for (auto &c : cp) {
+        if (c.n == 0) continue;
+        e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "index upload");
+    }
+    e = hipMemsetAsync(h->dstats, 0, szS, st);
+    if (e != hipSuccess) return hip_fail(e, "stats clear");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "index upload sync");
+    return RIANN_OK;
+}
+
+void free_index(riann_index *h) {
+    if (!h) return;
+    DeviceGuard g(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto &p : h->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto &kv : h->work) (void)hipFree(kv.second.rec);
+    if (h->dmem) (void)hipFree(h->dmem);
+    delete h;
+}
+
+riann_status_t finish_build(riann_index *h, hipStream_t st, riann_index_t *out) {
+    riann_status_t s = upload(h, st);
+    if (s != RIANN_OK) {
+        free_index(h);
+        return s;
+    }
+    *out = h;
+    return RIANN_OK;
+}
+
+riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = h->work.find(st);
+    if (it != h->work.end() && it->second.capacity >= Q) {
+        *w = it->second;
+        return RIANN_OK;
+    }
+    if (it != h->work.end()) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "scratch resize sync");
+        (void)hipFree(it->second.rec);
+        h->work.erase(it);
+    }
+    const int64_t cap = std::max<int64_t>(Q, 4096);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)work_bytes(cap));
+    if (e != hipSuccess) return fail(RIANN_E_NOMEM, "hipMalloc of frame scratch failed");
+    char *b = (char *)p;
+    Work nw;
+    nw.rec = (uint4 *)b;
+    nw.ring_list = (uint32_t *)(b + cap * 16);
+    nw.dense_list = (uint32_t *)(b + cap * 20);
+    nw.counters = (uint32_t *)(b + round_up(cap * 24, 256));
+    nw.capacity = cap;
+    h->work[st] = nw;
+    *w = nw;
+    return RIANN_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b) return false;
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+riann_status_t frame_args(const riann_index *h, const uint8_t *frame, int32_t H, int32_t W,
+                          int64_t pitch, FrameArgs *fa) {
+    const int p = h->prm.patch, C = h->prm.channels, s = h->prm.stride;
+    if (!frame) return fail(RIANN_E_INVALID, "frame is NULL");
+    if (H < p || W < p) return fail(RIANN_E_INVALID, "frame smaller than one patch");
+    if (pitch < (int64_t)W * C) return fail(RIANN_E_INVALID, "pitch < W * channels");
+    fa->frame = frame;
+    fa->pitch = pitch;
+    fa->H = H;
+    fa->W = W;
+    fa->Hq = (H - p) / s + 1;
+    fa->Wq = (W - p) / s + 1;
+    if ((int64_t)fa->Hq * fa->Wq >= (int64_t)0xFFFFFFFFu)
+        return fail(RIANN_E_UNSUPPORTED, "too many queries in one frame");
+    return RIANN_OK;
+}
+
+// Records a start event when profiling is on; the matching stop() records
+// the end event and queues the pair for riann_get_profile.
+struct KTimer {
+    riann_index *h;
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    KTimer(riann_index *h_, int kind_, hipStream_t st_) : h(h_), kind(kind_), st(st_) {
+        if (!h->profiling.load()) return;
+        if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    void stop() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); a = nullptr; return; }
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(h->pmu);
+        h->pending.push_back({kind, a, b});
+        a = nullptr;
+    }
+};
+
+riann_status_t do_match(riann_index *h, const FrameArgs &fa, const int32_t *prev,
+                        int32_t *out, uint32_t *ssd, hipStream_t st) {
+    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
+    const size_t qb = (size_t)Q * 4;
+    if (!out) return fail(RIANN_E_INVALID, "out is NULL");
+    if (overlap(prev, qb, out, qb)) return fail(RIANN_E_INVALID, "prev overlaps out");
+    if (overlap(ssd, qb, out, qb)) return fail(RIANN_E_INVALID, "ssd overlaps out");
+    if (overlap(prev, qb, ssd, qb)) return fail(RIANN_E_INVALID, "prev overlaps ssd");
+    Work w;
+    riann_status_t s = get_work(h, st, Q, &w);
+    if (s != RIANN_OK) return s;
+    hipError_t e = launch_zero_u32(w.counters, 4, st);
+    if (e != hipSuccess) return hip_fail(e, "counter clear");
+    {
+        KTimer t(h, RIANN_K_RING, st);
+        e = launch_ring(h->dix, fa, prev, w, h->dstats, h->threshold, st);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_ring launch");
+    }
+    {
+        KTimer t(h, RIANN_K_SCAN, st);
+        e = launch_scan(h->dix, fa, w, out, ssd, h->dstats, st);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_scan launch");
+    }
+    {
+        KTimer t(h, RIANN_K_DENSE, st);
+        e = launch_dense(h->dix, fa, w.dense_list, w.counters + 1, (uint32_t)Q, out, ssd, st);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_dense launch");
+    }
+    h->frames.fetch_add(1);
+    return RIANN_OK;
+}
+
+riann_status_t do_full(riann_index *h, const FrameArgs &fa, int32_t *out, uint32_t *ssd,
+                       hipStream_t st) {
+    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
+    if (!out) return fail(RIANN_E_INVALID, "out is NULL");
+    if (overlap(ssd, (size_t)Q * 4, out, (size_t)Q * 4))
+        return fail(RIANN_E_INVALID, "ssd overlaps out");
+    KTimer t(h, RIANN_K_FULL, st);
+    hipError_t e = launch_dense(h->dix, fa, nullptr, nullptr, (uint32_t)Q, out, ssd, st);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "k_dense launch");
+    h->frames.fetch_add(1);
+    h->full_queries.fetch_add((uint64_t)Q);
+    return RIANN_OK;
+}
+
+const char kMagic[8] = {'R', 'I', 'A', 'N', 'N', 'I', 'D', 'X'};
+const uint32_t kFileVersion = 1;
+
+}  // namespace
+
+extern "C" {
+
+uint32_t riann_version(void) { return (1u << 16) | 0u; }
+
+const char *riann_last_error(void) { return g_err.c_str(); }
+
+riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W, int64_t *bytes) {
+    riann_status_t s = check_params(p);
+    if (s != RIANN_OK) return s;
+    if (!bytes) return fail(RIANN_E_INVALID, "bytes is NULL");
+    int64_t b = index_bytes(p->n_ref, p->patch * p->patch * p->channels, p->n_keys);
+    if (H > 0 && W > 0) {
+        if (H < p->patch || W < p->patch) return fail(RIANN_E_INVALID, "frame smaller than patch");
+        const int64_t Q = (int64_t)((H - p->patch) / p->stride + 1) *
+                          ((W - p->patch) / p->stride + 1);
+        b += work_bytes(std::max<int64_t>(Q, 4096));
+    }
+    *bytes = b;
+    return RIANN_OK;
+}
+
+riann_status_t riann_build(const uint8_t *ref_host, const int32_t *key_idx,
+                           const riann_params_t *p, void *hip_stream, riann_index_t *out) {
+    riann_status_t s = check_params(p);
+    if (s != RIANN_OK) return s;
+    if (!ref_host || !out) return fail(RIANN_E_INVALID, "ref or out is NULL");
+    if (p->n_keys > 0 && !key_idx) return fail(RIANN_E_INVALID, "key_idx is NULL");
+    std::vector<char> seen((size_t)p->n_ref, 0);
+    for (int k = 0; k < p->n_keys; ++k) {
+        const int32_t v = key_idx[k];
+        if (v < 0 || (int64_t)v >= p->n_ref) return fail(RIANN_E_INVALID, "key index out of range");
+        if (seen[(size_t)v]) return fail(RIANN_E_INVALID, "duplicate key index");
+        seen[(size_t)v] = 1;
+    }
+    riann_index *h = new (std::nothrow) riann_index();
+    if (!h) return fail(RIANN_E_NOMEM, "host allocation failed");
+    h->prm = *p;
+    h->D = p->patch * p->patch * p->channels;
+    h->Dp = (int)round_up(h->D, 32);
+    h->K = p->n_keys;
+    h->n = p->n_ref;
+    h->n_pad = round_up(h->n, kTile);
+    h->threshold = p->dense_threshold >= 0 ? p->dense_threshold : default_threshold(h->n);
+    h->prm.dense_threshold = h->threshold;
+    (void)hipGetDevice(&h->device);
+    try {
+        h->ref.assign(ref_host, ref_host + (size_t)h->n * h->D);
+        h->keys.assign(key_idx, key_idx + h->K);
+        build_tables(h);
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(RIANN_E_NOMEM, "host allocation failed");
+    }
+    return finish_build(h, (hipStream_t)hip_stream, out);
+}
+
+riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
+                                 int64_t pitch, const int32_t *prev_dev, int32_t *out_dev,
+                                 uint32_t *ssd_dev, void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    FrameArgs fa;
+    riann_status_t s = frame_args(h, frame_dev, H, W, pitch, &fa);
+    if (s != RIANN_OK) return s;
+    DeviceGuard g(h->device);
+    return do_match(h, fa, prev_dev, out_dev, ssd_dev, (hipStream_t)hip_stream);
+}
+
+riann_status_t riann_full_search(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
+                                 int64_t pitch, int32_t *out_dev, uint32_t *ssd_dev,
+                                 void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    FrameArgs fa;
+    riann_status_t s = frame_args(h, frame_dev, H, W, pitch, &fa);
+    if (s != RIANN_OK) return s;
+    DeviceGuard g(h->device);
+    return do_full(h, fa, out_dev, ssd_dev, (hipStream_t)hip_stream);
+}
+
+riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *descs, int32_t n,
+                                 void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (n < 0 || (n > 0 && !descs)) return fail(RIANN_E_INVALID, "bad descriptor array");
+    std::vector<FrameArgs> fas((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        riann_status_t s = frame_args(h, descs[i].frame, descs[i].H, descs[i].W, descs[i].pitch,
+                                      &fas[(size_t)i]);
+        if (s != RIANN_OK) return s;
+        if (descs[i].mode != RIANN_MODE_RING && descs[i].mode != RIANN_MODE_FULL)
+            return fail(RIANN_E_INVALID, "bad descriptor mode");
+        if (!descs[i].out) return fail(RIANN_E_INVALID, "descriptor out is NULL");
+    }
+    DeviceGuard g(h->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int i = 0; i < n; ++i) {
+        const riann_frame_desc_t &d = descs[i];
+        riann_status_t s = d.mode == RIANN_MODE_FULL
+                               ? do_full(h, fas[(size_t)i], d.out, d.ssd, st)
+                               : do_match(h, fas[(size_t)i], d.prev, d.out, d.ssd, st);
+        if (s != RIANN_OK) return s;
+    }
+    return RIANN_OK;
+}
+
+riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
+    if (!h || !s) return fail(RIANN_E_INVALID, "NULL argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device sync");
+    unsigned long long v[ST_COUNT];
+    e = hipMemcpy(v, h->dstats, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stats copy");
+    const uint64_t fq = h->full_queries.load();
+    s->frames = h->frames.load();
+    s->queries = v[ST_QUERIES] + fq;
+    s->ring_queries = v[ST_RING];
+    s->dense_queries = v[ST_DENSE] + fq;
+    s->no_prior = v[ST_NOPRIOR];
+    s->sum_mstar = v[ST_MSTAR];
+    s->sum_survivors = v[ST_SURV];
+    s->sum_mstar_ring = v[ST_MSTAR_RING];
+    return RIANN_OK;
+}
+
+riann_status_t riann_reset_stats(riann_index_t h) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    DeviceGuard g(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device sync");
+    e = hipMemset(h->dstats, 0, ST_COUNT * 8);
+    if (e != hipSuccess) return hip_fail(e, "stats clear");
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device sync");
+    h->frames.store(0);
+    h->full_queries.store(0);
+    return RIANN_OK;
+}
+
+riann_status_t riann_get_params(riann_index_t h, riann_params_t *p) {
+    if (!h || !p) return fail(RIANN_E_INVALID, "NULL argument");
+    *p = h->prm;
+    return RIANN_OK;
+}
+
+riann_status_t riann_save(riann_index_t h, const char *path) {
+    if (!h || !path) return fail(RIANN_E_INVALID, "NULL argument");
+    {
+        DeviceGuard g(h->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "device sync");
+    }
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(RIANN_E_IO, std::string("cannot open for writing: ") + path);
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 &&
+              std::fwrite(&kFileVersion, 4, 1, f) == 1 &&
+              std::fwrite(&h->prm, sizeof(riann_params_t), 1, f) == 1;
+    auto put = [&](const void *d, size_t n) {
+        if (ok && n) ok = std::fwrite(d, 1, n, f) == n;
+    };
+    put(h->ref.data(), h->ref.size());
+    put(h->keys.data(), h->keys.size() * 4);
+    put(h->T.data(), h->T.size() * 4);
+    put(h->P.data(), h->P.size() * 4);
+    put(h->Piv.data(), (size_t)h->n * h->K * 4);
+    if (std::fclose(f) != 0) ok = false;
+    if (!ok) return fail(RIANN_E_IO, std::string("write failed: ") + path);
+    return RIANN_OK;
+}
+
+riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out) {
+    if (!path || !out) return fail(RIANN_E_INVALID, "NULL argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(RIANN_E_IO, std::string("cannot open: ") + path);
+    char magic[8];
+    uint32_t ver = 0;
+    riann_params_t prm;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(&ver, 4, 1, f) == 1 && ver == kFileVersion &&
+              std::fread(&prm, sizeof(prm), 1, f) == 1;
+    if (!ok) {
+        std::fclose(f);
+        return fail(RIANN_E_IO, "not a riann index file (or wrong version)");
+    }
+    riann_status_t s = check_params(&prm);
+    if (s != RIANN_OK) {
+        std::fclose(f);
+        return s;
+    }
+    riann_index *h = new (std::nothrow) riann_index();
+    if (!h) {
+        std::fclose(f);
+        return fail(RIANN_E_NOMEM, "host allocation failed");
+    }
+    h->prm = prm;
+    h->D = prm.patch * prm.patch * prm.channels;
+    h->Dp = (int)round_up(h->D, 32);
+    h->K = prm.n_keys;
+    h->n = prm.n_ref;
+    h->n_pad = round_up(h->n, kTile);
+    h->threshold = prm.dense_threshold >= 0 ? prm.dense_threshold : default_threshold(h->n);
+    (void)hipGetDevice(&h->device);
+    try {
+        h->ref.resize((size_t)h->n * h->D);
+        h->keys.resize((size_t)h->K);
+        h->T.resize((size_t)h->K * h->n);
+        h->P.resize((size_t)h->K * h->n);
+        h->Piv.assign((size_t)h->n * std::max(h->K, 1), 0);
+    } catch (const std::bad_alloc &) {
+        std::fclose(f);
+        delete h;
+        return fail(RIANN_E_NOMEM, "host allocation failed");
+    }
+    auto get = [&](void *d, size_t n) {
+        if (ok && n) ok = std::fread(d, 1, n, f) == n;
+    };
+    get(h->ref.data(), h->ref.size());
+    get(h->keys.data(), h->keys.size() * 4);
+    get(h->T.data(), h->T.size() * 4);
+    get(h->P.data(), h->P.size() * 4);
+    get(h->Piv.data(), (size_t)h->n * h->K * 4);
+    std::fclose(f);
+    if (!ok) {
+        delete h;
+        return fail(RIANN_E_IO, "truncated index file");
+    }
+    for (int k = 0; k < h->K; ++k)
+        if (h->keys[(size_t)k] < 0 || h->keys[(size_t)k] >= h->n) {
+            delete h;
+            return fail(RIANN_E_IO, "corrupt key index in file");
+        }
+    for (size_t i = 0; i < h->P.size(); ++i)
+        if (h->P[i] < 0 || h->P[i] >= h->n) {
+            delete h;
+            return fail(RIANN_E_IO, "corrupt table in file");
+        }
+    return finish_build(h, (hipStream_t)hip_stream, out);
+}
+
+riann_status_t riann_set_profiling(riann_index_t h, int enable) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    h->profiling.store(enable != 0);
+    return RIANN_OK;
+}
+
+riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
+    if (!h || !out) return fail(RIANN_E_INVALID, "NULL argument");
+    DeviceGuard g(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device sync");
+    std::lock_guard<std::mutex> lk(h->pmu);
+    for (auto &p : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->prof_ms[p.kind] += ms;
+            h->prof_launches[p.kind] += 1;
+        }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    h->pending.clear();
+    for (int k = 0; k < RIANN_K_COUNT; ++k) {
+        out->launches[k] = h->prof_launches[k];
+        out->ms[k] = h->prof_ms[k];
+    }
+    return RIANN_OK;
+}
+
+riann_status_t riann_destroy(riann_index_t h) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    free_index(h);
+    return RIANN_OK;
+}
+
+}  // extern "C"

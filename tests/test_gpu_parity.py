@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Fields and SSDs must match the oracle's exact nearest neighbours bit for bit
+(integer work: no tolerance).  Ring statistics must equal the oracle's
+per-query counts summed the same way.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def riann():
+    import paper_1508_07953_amd as r
+    return r
+
+
+def to_dev(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def host(t):
+    return t.cpu().numpy().reshape(-1)
+
+
+def check_exact(out, ssd, P, ref, what=""):
+    bi, bd = oracle.brute_force(P, ref)
+    gi, gd = host(out), host(ssd).astype(np.uint32)
+    bad = np.nonzero((gi != bi) | (gd != bd))[0]
+    assert bad.size == 0, (f"{what}: {bad.size}/{bi.size} differ; first q={bad[0]} "
+                           f"got ({gi[bad[0]]},{gd[bad[0]]}) want ({bi[bad[0]]},{bd[bad[0]]})")
+    return bi, bd
+
+
+def print_case(name):
+    print(f"[gpu case] {name}", flush=True)
+
+
+# ------------------------------------------------------------------ tiny video
+def test_tiny_sequence_exact_and_stats(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("tiny sequence")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    tabs = oracle.Tables(wl.ref, wl.keys)
+    thr = idx.params.dense_threshold
+    prev = None
+    want = dict(queries=0, ring=0, mstar=0, surv=0, mstar_ring=0, noprior=0)
+    for t in range(wl.frames):
+        f = wl.frame(t)
+        P = oracle.extract(f, 8, 1)
+        fd = to_dev(torch, dev, f)
+        if prev is None:
+            out, ssd = idx.full_search(fd)
+            want["queries"] += len(P)
+        else:
+            out, ssd = idx.match_frame(fd, prev=prev)
+            o = tabs.riann(P, host(prev))
+            ring = (o["mstar"] <= thr) & (o["noprior"] == 0)
+            want["queries"] += len(P)
+            want["ring"] += int(ring.sum())
+            want["mstar"] += int(o["mstar"].sum())
+            want["surv"] += int(o["nsurv"][ring].sum())
+            want["mstar_ring"] += int(o["mstar"][ring].sum())
+            want["noprior"] += int(o["noprior"].sum())
+        torch.cuda.synchronize()
+        check_exact(out, ssd, P, wl.ref, f"frame {t}")
+        prev = out.clone()
+    st = idx.stats()
+    assert st["frames"] == wl.frames
+    assert st["queries"] == want["queries"]
+    assert st["ring_queries"] == want["ring"]
+    assert st["dense_queries"] == want["queries"] - want["ring"]
+    assert st["sum_mstar"] == want["mstar"]
+    assert st["sum_survivors"] == want["surv"]
+    assert st["sum_mstar_ring"] == want["mstar_ring"]
+    assert st["no_prior"] == want["noprior"]
+    idx.close()
+
+
+@pytest.mark.parametrize("thr", [0, 64, 1 << 30])
+@pytest.mark.parametrize("prev_kind", ["random", "noprior", "mixed", "exact"])
+def test_tiny_routes_and_prev(torch_dev, riann, thr, prev_kind):
+    torch, dev = torch_dev
+    print_case(f"tiny thr={thr} prev={prev_kind}")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1,
+                            dense_threshold=thr)
+    f = wl.frame(3)
+    P = oracle.extract(f, 8, 1)
+    rng = np.random.default_rng(99)
+    if prev_kind == "random":
+        prev = gen.random_field(57, 57, len(wl.ref), rng)
+    elif prev_kind == "noprior":
+        prev = np.full((57, 57), -1, np.int32)
+    elif prev_kind == "mixed":
+        prev = gen.random_field(57, 57, len(wl.ref), rng, no_prior_p=0.2)
+        prev[rng.random((57, 57)) < 0.1] = len(wl.ref) + 7
+    else:
+        prev = oracle.brute_force(P, wl.ref)[0].reshape(57, 57)
+    out, ssd = idx.match_frame(to_dev(torch, dev, f), prev=to_dev(torch, dev, prev))
+    torch.cuda.synchronize()
+    check_exact(out, ssd, P, wl.ref, f"thr={thr} prev={prev_kind}")
+    idx.close()
+
+
+# ------------------------------------------------------------------ shapes
+SHAPES = [
+    # p, C, s, n, K, H, W
+    (3, 1, 1, 100, 4, 19, 23),
+    (8, 3, 1, 500, 8, 40, 37),
+    (12, 1, 2, 777, 12, 50, 61),
+    (5, 2, 3, 64, 0, 30, 30),
+    (16, 1, 1, 300, 5, 40, 40),
+    (2, 1, 1, 33, 3, 9, 10),
+    (8, 1, 1, 1, 1, 8, 8),
+    (4, 3, 1, 2100, 64, 23, 29),
+]
+
+
+@pytest.mark.parametrize("p,C,s,n,K,H,W", SHAPES)
+def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W):
+    torch, dev = torch_dev
+    print_case(f"shape p={p} C={C} s={s} n={n} K={K} H={H} W={W}")
+    rng = np.random.default_rng(p * 1000 + n)
+    big = np.clip(np.rint(gen.texture(rng, max(H, p + 40), max(W, p + 40), C)), 0, 255)
+    big = big.astype(np.uint8)
+    hq0, wq0 = oracle.field_shape(big.shape[0], big.shape[1], p, 1)
+    n_eff = min(n, hq0 * wq0)
+    ref = gen.reference_from_frame(big, n_eff, p, 1, rng)
+    keys = gen.choose_keys(n_eff, min(K, n_eff), rng)
+    f = np.clip(np.rint(gen.texture(rng, H, W, C) + rng.normal(0, 3, (H, W, C))), 0, 255)
+    f = f.astype(np.uint8)
+    P = oracle.extract(f, p, s)
+    hq, wq = oracle.field_shape(H, W, p, s)
+    for thr in (-1, 1 << 30):
+        idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=s, dense_threshold=thr)
+        fd = to_dev(torch, dev, f)
+        out, ssd = idx.full_search(fd)
+        torch.cuda.synchronize()
+        bi, _ = check_exact(out, ssd, P, ref, "full")
+        prev = gen.random_field(hq, wq, n_eff, rng, no_prior_p=0.1)
+        out2, ssd2 = idx.match_frame(fd, prev=to_dev(torch, dev, prev))
+        torch.cuda.synchronize()
+        check_exact(out2, ssd2, P, ref, f"ring thr={thr}")
+        out3, ssd3 = idx.match_frame(fd, prev=out)
+        torch.cuda.synchronize()
+        check_exact(out3, ssd3, P, ref, f"ring(prev=exact) thr={thr}")
+        out4, ssd4 = idx.match_frame(fd, prev=None)
+        torch.cuda.synchronize()
+        check_exact(out4, ssd4, P, ref, f"ring(no prev) thr={thr}")
+        idx.close()
+
+
+def test_ties_and_constant_frame(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("ties")
+    rng = np.random.default_rng(5)
+    ref = rng.integers(0, 256, (300, 64), dtype=np.uint8)
+    ref[[7, 100, 250]] = 90               # three identical constant patches
+    ref[[3, 200]] = ref[150]              # duplicates of a textured patch
+    f = np.full((20, 24, 1), 90, np.uint8)
+    f[10:18, 14:22, 0] = ref[150].reshape(8, 8)
+    P = oracle.extract(f, 8, 1)
+    for thr in (-1, 0, 1 << 30):
+        idx = riann.Index.build(ref, [150, 7, 42, 250], patch=8, channels=1, stride=1,
+                                dense_threshold=thr)
+        fd = to_dev(torch, dev, f)
+        out, ssd = idx.full_search(fd)
+        torch.cuda.synchronize()
+        bi, bd = check_exact(out, ssd, P, ref, "full ties")
+        assert bi[0] == 7 and bd[0] == 0
+        hq, wq = oracle.field_shape(20, 24, 8, 1)
+        assert bi[10 * wq + 14] == 3 and bd[10 * wq + 14] == 0   # lowest of 3, 150, 200
+        prev = np.full((hq, wq), 250, np.int32)
+        out2, ssd2 = idx.match_frame(fd, prev=to_dev(torch, dev, prev))
+        torch.cuda.synchronize()
+        check_exact(out2, ssd2, P, ref, "ring ties")
+        idx.close()
+
+
+def test_pitched_frame(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("pitch")
+    wl = gen.make_workload("tiny")
+    f = wl.frame(2)
+    wide = np.zeros((64, 100, 1), np.uint8)
+    wide[:, 10:74] = f
+    wd = to_dev(torch, dev, wide)
+    view = wd[:, 10:74]
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    out, ssd = idx.full_search(view)
+    out2, ssd2 = idx.match_frame(view, prev=out)
+    torch.cuda.synchronize()
+    P = oracle.extract(f, 8, 1)
+    check_exact(out, ssd, P, wl.ref, "pitched full")
+    check_exact(out2, ssd2, P, wl.ref, "pitched ring")
+    idx.close()
+
+
+def test_repeat_determinism(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("determinism")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    fd = to_dev(torch, dev, wl.frame(4))
+    rng = np.random.default_rng(3)
+    prev = to_dev(torch, dev, gen.random_field(57, 57, 1024, rng))
+    res = []
+    for _ in range(5):
+        o, s = idx.match_frame(fd, prev=prev)
+        res.append((host(o).copy(), host(s).copy()))
+    for o, s in res[1:]:
+        assert np.array_equal(o, res[0][0]) and np.array_equal(s, res[0][1])
+    idx.close()
+
+
+def test_errors(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("errors")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    fd = to_dev(torch, dev, wl.frame(0))
+    buf = torch.zeros((57, 57), dtype=torch.int32, device=dev)
+    with pytest.raises(riann.RiannError) as e:
+        idx.match_frame(fd, prev=buf, out=buf)
+    assert e.value.status == riann.RIANN_E_INVALID
+    small = torch.zeros((4, 4), dtype=torch.uint8, device=dev)
+    with pytest.raises(riann.RiannError):
+        idx.full_search(small)
+    with pytest.raises(riann.RiannError):
+        riann.Index.build(wl.ref, [1, 1], patch=8)
+    with pytest.raises(riann.RiannError):
+        riann.Index.build(wl.ref, [5000], patch=8)
+    idx.close()
+
+
+def test_save_load_roundtrip(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("save/load")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    fd = to_dev(torch, dev, wl.frame(5))
+    rng = np.random.default_rng(8)
+    prev = to_dev(torch, dev, gen.random_field(57, 57, 1024, rng))
+    o1, s1 = idx.match_frame(fd, prev=prev)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "idx.bin")
+        idx.save(path)
+        idx2 = riann.Index.load(path)
+        o2, s2 = idx2.match_frame(fd, prev=prev)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(o1), host(o2)) and np.array_equal(host(s1), host(s2))
+        assert idx2.params.n_ref == 1024 and idx2.params.n_keys == len(wl.keys)
+        idx2.close()
+    idx.close()
+
+
+def test_batch_matches_single(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("batch")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    rng = np.random.default_rng(4)
+    frames = [wl.frame(t) for t in range(3)]
+    frames.append(np.ascontiguousarray(frames[1][:40, :50]))
+    items, singles = [], []
+    for i, f in enumerate(frames):
+        fd = to_dev(torch, dev, f)
+        hq, wq = oracle.field_shape(f.shape[0], f.shape[1], 8, 1)
+        prev = to_dev(torch, dev, gen.random_field(hq, wq, 1024, rng, no_prior_p=0.2))
+        out = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+        ssd = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+        mode = riann.MODE_FULL if i == 0 else riann.MODE_RING
+        items.append(dict(frame=fd, prev=prev, out=out, ssd=ssd, mode=mode))
+        if mode == riann.MODE_FULL:
+            singles.append(idx.full_search(fd))
+        else:
+            singles.append(idx.match_frame(fd, prev=prev))
+    idx.match_batch(items)
+    torch.cuda.synchronize()
+    for it, (o, s), f in zip(items, singles, frames):
+        assert np.array_equal(host(it["out"]), host(o))
+        assert np.array_equal(host(it["ssd"]), host(s))
+        check_exact(it["out"], it["ssd"], oracle.extract(f, 8, 1), wl.ref, "batch")
+    idx.close()
+
+
+# ------------------------------------------------------------------ full size, sampled
+def test_hd720_sampled(torch_dev, riann):
+    torch, dev = torch_dev
+    print_case("hd720 sampled")
+    wl = gen.make_workload("hd720", frames=3)
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    rng = np.random.default_rng(11)
+    prev = None
+    for t in range(3):
+        f = wl.frame(t)
+        fd = to_dev(torch, dev, f)
+        if prev is None:
+            out, ssd = idx.full_search(fd)
+        else:
+            out, ssd = idx.match_frame(fd, prev=prev)
+        torch.cuda.synchronize()
+        P = oracle.extract(f, 8, 1)
+        assert len(P) == 907_649
+        sel = np.sort(rng.choice(len(P), 3000, replace=False))
+        sel = np.concatenate([sel, [0, len(P) - 1]])
+        bi, bd = oracle.brute_force(P[sel], wl.ref)
+        gi, gd = host(out)[sel], host(ssd)[sel].astype(np.uint32)
+        assert np.array_equal(gi, bi) and np.array_equal(gd, bd), f"frame {t}"
+        prev = out.clone()
+    idx.close()
