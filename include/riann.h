@@ -209,13 +209,15 @@ riann_status_t riann_destroy(riann_index_t h);
  * milliseconds and returns the totals per kernel since profiling was enabled.
  * Kernels: RIANN_K_RING (ring phase), RIANN_K_SCAN (ring scan and
  * verification), RIANN_K_DENSE (dense search of routed queries),
- * RIANN_K_FULL (dense search of whole frames).
+ * RIANN_K_FULL (dense search of whole frames), RIANN_K_EXTRACT (patch
+ * extraction, run first for every frame).
  */
 #define RIANN_K_RING 0
 #define RIANN_K_SCAN 1
 #define RIANN_K_DENSE 2
 #define RIANN_K_FULL 3
-#define RIANN_K_COUNT 4
+#define RIANN_K_EXTRACT 4
+#define RIANN_K_COUNT 5
 typedef struct riann_profile {
     uint64_t launches[RIANN_K_COUNT];
     double ms[RIANN_K_COUNT];

@@ -35,7 +35,7 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile"]
-KERNELS = ["ring", "scan", "dense", "full"]
+KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
 class RiannError(RuntimeError):
@@ -57,7 +57,7 @@ class FrameDesc(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4)]
+    _fields_ = [("launches", C.c_uint64 * 5), ("ms", C.c_double * 5)]
 
 
 class Stats(C.Structure):

@@ -41,8 +41,8 @@ struct riann_index {
     std::mutex pmu;
     struct Pending { int kind; hipEvent_t a, b; };
     std::vector<Pending> pending;
-    uint64_t prof_launches[RIANN_K_COUNT] = {0, 0, 0, 0};
-    double prof_ms[RIANN_K_COUNT] = {0, 0, 0, 0};
+    uint64_t prof_launches[RIANN_K_COUNT] = {};
+    double prof_ms[RIANN_K_COUNT] = {};
 };
 
 namespace {
@@ -97,12 +97,13 @@ int64_t default_threshold(int64_t n) {
 
 int64_t index_bytes(int64_t n, int D, int K) {
     const int Dp = (int)round_up(D, 32);
-    const int64_t n_pad = round_up(n, kTile);
-    return n_pad * Dp + n_pad * 4 + (int64_t)K * n * 8 + n * (int64_t)std::max(K, 1) * 4 +
-           (int64_t)K * 4 + ST_COUNT * 8 + 4096;
+    const int64_t n_pad = round_up(n, kRefAlign);
+    const int64_t n16 = round_up(n, 16), Kp = round_up(std::max(K, 1), 4);
+    return 2 * (n_pad * Dp + n_pad * 4) + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
+           (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q) { return Q * 16 + Q * 8 + 64 + 1024; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 16 + 8) + 4096; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -154,8 +155,15 @@ void build_tables(riann_index *h) {
 riann_status_t upload(riann_index *h, hipStream_t st) {
     const int64_t n = h->n, n_pad = h->n_pad;
     const int D = h->D, Dp = h->Dp, K = h->K;
-    std::vector<int8_t> Rv((size_t)n_pad * Dp, 0);
-    std::vector<int32_t> Rc((size_t)n_pad, kRcPad);
+    // dense key layout: X = SSD - Qc + bias < 2^(32 - jb) - 1 for every pair
+    const int64_t bias = (int64_t)D * 16384;
+    const int64_t xmax = (int64_t)D * 65025 + bias;
+    int xbits = 1;
+    while (((int64_t)1 << xbits) < xmax + 2) ++xbits;
+    const int jb = 32 - xbits;
+    std::vector<int8_t> Rv((size_t)n_pad * Dp, 0), Rf((size_t)n_pad * Dp, 0);
+    std::vector<int32_t> Rc((size_t)n_pad, 0);
+    std::vector<uint32_t> Rk((size_t)n_pad, (uint32_t)(((uint64_t)1 << 32) - ((uint64_t)1 << jb)));
     for (int64_t r = 0; r < n; ++r) {
         int32_t s = 0;
         for (int i = 0; i < D; ++i) {
@@ -164,14 +172,38 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
             s += v * (v + 2);
         }
         Rc[(size_t)r] = s;
+        Rk[(size_t)r] = (uint32_t)(s + bias) << jb;
     }
+    const int KB = Dp / 32;
+    for (int64_t r = 0; r < n_pad; ++r)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int g = 0; g < 2; ++g) {
+                const int64_t t = r / kTile, l = (r % kTile) + 32 * g;
+                std::memcpy(&Rf[(size_t)(((t * KB + kb) * 64 + l) * 16)],
+                            &Rv[(size_t)(r * Dp + kb * 32 + 16 * g)], 16);
+            }
+    // ring-phase tables: T padded to 16-entry lines, LDS samples, padded Piv
+    const int64_t n16 = round_up(n, 16);
+    int64_t s0l = 1;   // sample stride in lines: samples of all keys fit 64 KB
+    while ((int64_t)K * ((n + 16 * s0l - 1) / (16 * s0l)) * 4 > 65536) s0l *= 2;
+    const int64_t ns = (n + 16 * s0l - 1) / (16 * s0l);
+    const int Kp = (int)round_up(std::max(K, 1), 4);
+    std::vector<uint32_t> Tl((size_t)K * n16, 0xFFFFFFFFu), Ts((size_t)std::max<int64_t>(K * ns, 1));
+    std::vector<uint32_t> Pv((size_t)n * Kp, 0u);
+    for (int k = 0; k < K; ++k) {
+        std::memcpy(&Tl[(size_t)k * n16], &h->T[(size_t)k * n], (size_t)n * 4);
+        for (int64_t i = 0; i < ns; ++i) Ts[(size_t)(k * ns + i)] = h->T[(size_t)(k * n + i * 16 * s0l)];
+    }
+    for (int64_t r = 0; r < n; ++r)
+        for (int k = 0; k < K; ++k) Pv[(size_t)(r * Kp + k)] = h->Piv[(size_t)(r * K + k)];
     const size_t szRv = (size_t)n_pad * Dp, szRc = (size_t)n_pad * 4,
-                 szT = (size_t)K * n * 4, szP = (size_t)K * n * 4,
-                 szPiv = (size_t)n * std::max(K, 1) * 4, szK = (size_t)std::max(K, 1) * 4,
-                 szS = ST_COUNT * 8;
-    size_t off[8], tot = 0;
-    const size_t sz[7] = {szRv, szRc, szT, szP, szPiv, szK, szS};
-    for (int i = 0; i < 7; ++i) {
+                 szT = (size_t)std::max<int64_t>(K * n16, 1) * 4,
+                 szP = (size_t)std::max<int64_t>(K * n, 1) * 4,
+                 szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
+                 szS = ST_COUNT * 8, szTs = Ts.size() * 4;
+    size_t off[11], tot = 0;
+    const size_t sz[10] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs};
+    for (int i = 0; i < 10; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -189,6 +221,15 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.Piv = (const uint32_t *)(b + off[4]);
     h->dix.keys = (const int32_t *)(b + off[5]);
     h->dstats = (unsigned long long *)(b + off[6]);
+    h->dix.Rf = (const int8_t *)(b + off[7]);
+    h->dix.Rk = (const uint32_t *)(b + off[8]);
+    h->dix.jb = jb;
+    h->dix.bias = (int32_t)bias;
+    h->dix.Ts = (const uint32_t *)(b + off[9]);
+    h->dix.n16 = (int32_t)n16;
+    h->dix.ns = (int32_t)ns;
+    h->dix.s0l = (int32_t)s0l;
+    h->dix.Kp = Kp;
     h->dix.n = n;
     h->dix.n_pad = n_pad;
     h->dix.D = D;
@@ -199,9 +240,11 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.s = h->prm.stride;
     struct { void *dst; const void *src; size_t n; } cp[] = {
         {b + off[0], Rv.data(), szRv},          {b + off[1], Rc.data(), szRc},
-        {b + off[2], h->T.data(), szT},         {b + off[3], h->P.data(), szP},
-        {b + off[4], h->Piv.data(), (size_t)n * K * 4},
+        {b + off[2], Tl.data(), (size_t)K * n16 * 4}, {b + off[3], h->P.data(), (size_t)K * n * 4},
+        {b + off[4], Pv.data(), szPiv},
         {b + off[5], h->keys.data(), (size_t)K * 4},
+        {b + off[7], Rf.data(), szRv},          {b + off[8], Rk.data(), szRc},
+        {b + off[9], Ts.data(), (size_t)K * ns * 4},
     };
     for (auto &c : cp) {
         if (c.n == 0) continue;
@@ -223,7 +266,7 @@ void free_index(riann_index *h) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
-    for (auto &kv : h->work) (void)hipFree(kv.second.rec);
+    for (auto &kv : h->work) (void)hipFree(kv.second.patches);
     if (h->dmem) (void)hipFree(h->dmem);
     delete h;
 }
@@ -239,6 +282,7 @@ riann_status_t finish_build(riann_index *h, hipStream_t st, riann_index_t *out) 
 }
 
 riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
+    const int Dp = h->Dp;
     std::lock_guard<std::mutex> lk(h->mu);
     auto it = h->work.find(st);
     if (it != h->work.end() && it->second.capacity >= Q) {
@@ -248,19 +292,22 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     if (it != h->work.end()) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "scratch resize sync");
-        (void)hipFree(it->second.rec);
+        (void)hipFree(it->second.patches);
         h->work.erase(it);
     }
     const int64_t cap = std::max<int64_t>(Q, 4096);
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, (size_t)work_bytes(cap));
+    hipError_t e = hipMalloc(&p, (size_t)work_bytes(cap, Dp));
     if (e != hipSuccess) return fail(RIANN_E_NOMEM, "hipMalloc of frame scratch failed");
     char *b = (char *)p;
     Work nw;
-    nw.rec = (uint4 *)b;
-    nw.ring_list = (uint32_t *)(b + cap * 16);
-    nw.dense_list = (uint32_t *)(b + cap * 20);
-    nw.counters = (uint32_t *)(b + round_up(cap * 24, 256));
+    int64_t o = 0;
+    nw.patches = (uint8_t *)(b + o);  o = round_up(o + cap * Dp, 256);
+    nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
+    nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
+    nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
+    nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
+    nw.counters = (uint32_t *)(b + o);
     nw.capacity = cap;
     h->work[st] = nw;
     *w = nw;
@@ -327,6 +374,12 @@ riann_status_t do_match(riann_index *h, const FrameArgs &fa, const int32_t *prev
     hipError_t e = launch_zero_u32(w.counters, 4, st);
     if (e != hipSuccess) return hip_fail(e, "counter clear");
     {
+        KTimer t(h, RIANN_K_EXTRACT, st);
+        e = launch_extract(h->dix, fa, w.patches, w.qc, st);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_extract launch");
+    }
+    {
         KTimer t(h, RIANN_K_RING, st);
         e = launch_ring(h->dix, fa, prev, w, h->dstats, h->threshold, st);
         t.stop();
@@ -340,7 +393,7 @@ riann_status_t do_match(riann_index *h, const FrameArgs &fa, const int32_t *prev
     }
     {
         KTimer t(h, RIANN_K_DENSE, st);
-        e = launch_dense(h->dix, fa, w.dense_list, w.counters + 1, (uint32_t)Q, out, ssd, st);
+        e = launch_dense(h->dix, w, w.dense_list, w.counters + 1, (uint32_t)Q, out, ssd, st);
         t.stop();
         if (e != hipSuccess) return hip_fail(e, "k_dense launch");
     }
@@ -354,8 +407,18 @@ riann_status_t do_full(riann_index *h, const FrameArgs &fa, int32_t *out, uint32
     if (!out) return fail(RIANN_E_INVALID, "out is NULL");
     if (overlap(ssd, (size_t)Q * 4, out, (size_t)Q * 4))
         return fail(RIANN_E_INVALID, "ssd overlaps out");
+    Work w;
+    riann_status_t s = get_work(h, st, Q, &w);
+    if (s != RIANN_OK) return s;
+    hipError_t e;
+    {
+        KTimer t(h, RIANN_K_EXTRACT, st);
+        e = launch_extract(h->dix, fa, w.patches, w.qc, st);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_extract launch");
+    }
     KTimer t(h, RIANN_K_FULL, st);
-    hipError_t e = launch_dense(h->dix, fa, nullptr, nullptr, (uint32_t)Q, out, ssd, st);
+    e = launch_dense(h->dix, w, nullptr, nullptr, (uint32_t)Q, out, ssd, st);
     t.stop();
     if (e != hipSuccess) return hip_fail(e, "k_dense launch");
     h->frames.fetch_add(1);
@@ -383,7 +446,8 @@ riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W, in
         if (H < p->patch || W < p->patch) return fail(RIANN_E_INVALID, "frame smaller than patch");
         const int64_t Q = (int64_t)((H - p->patch) / p->stride + 1) *
                           ((W - p->patch) / p->stride + 1);
-        b += work_bytes(std::max<int64_t>(Q, 4096));
+        b += work_bytes(std::max<int64_t>(Q, 4096),
+                        (int)round_up((int64_t)p->patch * p->patch * p->channels, 32));
     }
     *bytes = b;
     return RIANN_OK;
@@ -409,7 +473,7 @@ riann_status_t riann_build(const uint8_t *ref_host, const int32_t *key_idx,
     h->Dp = (int)round_up(h->D, 32);
     h->K = p->n_keys;
     h->n = p->n_ref;
-    h->n_pad = round_up(h->n, kTile);
+    h->n_pad = round_up(h->n, kRefAlign);
     h->threshold = p->dense_threshold >= 0 ? p->dense_threshold : default_threshold(h->n);
     h->prm.dense_threshold = h->threshold;
     (void)hipGetDevice(&h->device);
@@ -565,7 +629,7 @@ riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out
     h->Dp = (int)round_up(h->D, 32);
     h->K = prm.n_keys;
     h->n = prm.n_ref;
-    h->n_pad = round_up(h->n, kTile);
+    h->n_pad = round_up(h->n, kRefAlign);
     h->threshold = prm.dense_threshold >= 0 ? prm.dense_threshold : default_threshold(h->n);
     (void)hipGetDevice(&h->device);
     try {

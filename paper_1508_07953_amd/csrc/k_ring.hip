@@ -40,27 +40,6 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
-// Loads the D patch bytes of the window with top-left pixel (x, y) into
-// packed words, each byte XOR-ed with `xorv`; bytes k >= D are 0.
-template <int DP>
-__device__ __forceinline__ void load_patch(const uint8_t *__restrict__ frame, int64_t pitch,
-                                           int x, int y, int C, int rowlen, int D,
-                                           uint32_t xorv, uint32_t (&w)[DP / 4]) {
-    const uint8_t *row = frame + (int64_t)y * pitch + (int64_t)x * C;
-    int rem = 0;
-#pragma unroll
-    for (int i = 0; i < DP / 4; ++i) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int k = 4 * i + b;
-            if (k < D) word |= ((uint32_t)row[rem] ^ xorv) << (8 * b);
-            if (++rem == rowlen) { rem = 0; row += pitch; }
-        }
-        w[i] = word;
-    }
-}
-
 // <a, v> over DP bytes: a in registers, v a 16-byte aligned reference row.
 template <int DP>
 __device__ __forceinline__ int dot_row(const uint32_t (&a)[DP / 4], const int8_t *__restrict__ v) {
@@ -92,28 +71,53 @@ __device__ __forceinline__ void ring_bounds(uint32_t b, uint32_t c, uint32_t &lo
     hi = (uint32_t)((uint64_t)b + c + s);
 }
 
-// first j in [0, n) with t[j] >= v
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ t, uint32_t n,
-                                                    uint32_t v) {
-    uint32_t lo = 0, len = n;
+// Positions in a key's sorted list: the number of entries with x < v
+// (LE = false, the lower_bound of v) or x <= v (LE = true, the upper_bound).
+// sample_count searches the list's samples in LDS (S[i] = T[16 s0l i], ns of
+// them) and returns how many satisfy the predicate; that brackets the
+// position (pos_bracket).  exact_pos finishes the search in global memory:
+// a binary search over the first entries of 16-entry lines, then one
+// aligned 64-byte line is read and counted.
+template <bool LE>
+__device__ __forceinline__ bool pred(uint32_t x, uint32_t v) { return LE ? x <= v : x < v; }
+
+template <bool LE>
+__device__ __forceinline__ int sample_count(const uint32_t *S, int ns, uint32_t v) {
+    int lo = 0, len = ns;
     while (len > 0) {
-        uint32_t half = len >> 1;
-        if (t[lo + half] < v) { lo += half + 1; len -= half + 1; }
+        const int half = len >> 1;
+        if (pred<LE>(S[lo + half], v)) { lo += half + 1; len -= half + 1; }
         else len = half;
     }
     return lo;
 }
 
-// first j in [0, n) with t[j] > v
-__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t *__restrict__ t, uint32_t n,
-                                                    uint32_t v) {
-    uint32_t lo = 0, len = n;
-    while (len > 0) {
-        uint32_t half = len >> 1;
-        if (t[lo + half] <= v) { lo += half + 1; len -= half + 1; }
-        else len = half;
+// position range [pl, ph] implied by the sample count i
+__device__ __forceinline__ void pos_bracket(int i, int ns, int s0l, uint32_t n, uint32_t &pl,
+                                            uint32_t &ph) {
+    if (i == 0) { pl = ph = 0; return; }
+    pl = 16u * (uint32_t)((i - 1) * s0l) + 1u;
+    ph = i < ns ? min(16u * (uint32_t)(i * s0l), n) : n;
+}
+
+template <bool LE>
+__device__ __forceinline__ uint32_t exact_pos(int i, const uint32_t *__restrict__ T, int nlines,
+                                              int s0l, uint32_t v) {
+    if (i == 0) return 0;
+    int L = (i - 1) * s0l, H = min(i * s0l, nlines);
+    while (H - L > 1) {
+        const int mid = (L + H) >> 1;
+        if (pred<LE>(T[16 * mid], v)) L = mid;
+        else H = mid;
     }
-    return lo;
+    const uint4 *line = reinterpret_cast<const uint4 *>(T + 16 * L);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 x = line[q];
+        cnt += pred<LE>(x.x, v) + pred<LE>(x.y, v) + pred<LE>(x.z, v) + pred<LE>(x.w, v);
+    }
+    return 16u * (uint32_t)L + cnt;
 }
 
 __device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
@@ -127,27 +131,50 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
 }
 
 // ---------------------------------------------------------------- k_ring
+// One lane per query, 1024 queries per block.  Each block first copies the
+// binary-search samples of all K lists (at most 64 KB) into LDS.  For every
+// key the LDS samples bracket the ring size m_k to an interval [ml, mh]; the
+// exact size (two line reads in global memory) is computed only for keys
+// that can still be the smallest ring: key k is skipped when ml > min over
+// earlier keys of mh (some earlier ring is strictly smaller) or ml >= the
+// smallest exact size so far (an earlier key wins the tie).  The result --
+// the exact smallest ring m*, its key k* (lowest on ties) and its range --
+// is the same as evaluating every key exactly.
+// List appends and statistics are aggregated per block: one atomic per list
+// and per counter per block.
+constexpr int kRingBlock = 1024;
+constexpr int kRingWaves = kRingBlock / 64;
+
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_ring(DevIndex ix, FrameArgs fa,
-                                                  const int32_t *__restrict__ prev, Work w,
-                                                  unsigned long long *__restrict__ stats,
-                                                  int64_t threshold) {
+__global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
+                                                      const int32_t *__restrict__ prev, Work w,
+                                                      unsigned long long *__restrict__ stats,
+                                                      int64_t threshold) {
+    extern __shared__ uint32_t s_samp[];
+    __shared__ uint32_t s_wcnt[kRingWaves][2];
+    __shared__ uint32_t s_base[2];
+    __shared__ unsigned long long s_st[kRingWaves][4];
+    const int nsamp = ix.K * ix.ns;
+    for (int i = threadIdx.x; i < nsamp; i += kRingBlock) s_samp[i] = ix.Ts[i];
+    __syncthreads();
+
     const int64_t Q = (int64_t)fa.Hq * fa.Wq;
-    const int64_t qid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t n = (uint32_t)ix.n;
+    const int nlines = ix.n16 / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t qid = (int64_t)blockIdx.x * kRingBlock + threadIdx.x;
     const bool valid = qid < Q;
     const int64_t qq = valid ? qid : Q - 1;
-    const int qi = (int)(qq / fa.Wq), qj = (int)(qq % fa.Wq);
     uint32_t a[DP / 4];
-    load_patch<DP>(fa.frame, fa.pitch, qj * ix.s, qi * ix.s, ix.C, ix.p * ix.C, ix.D, 0x7Fu, a);
-    // Qc = sum (a+1)^2 = sum a^2 + 2 sum a + D
-    int sa2 = 0, sa = 0;
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + qq * DP);
 #pragma unroll
-    for (int i = 0; i < DP / 4; ++i) {
-        sa2 = __builtin_amdgcn_sdot4((int)a[i], (int)a[i], sa2, false);
-        sa = __builtin_amdgcn_sdot4((int)a[i], 0x01010101, sa, false);
+        for (int i = 0; i < DP / 16; ++i) {
+            const uint4 v = src[i];
+            a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
+        }
     }
-    const int Qc = sa2 + 2 * sa + ix.D;
-
+    const int Qc = w.qc[qq];
     const int32_t pv = prev ? prev[qq] : -1;
     const bool noprior = pv < 0 || (int64_t)pv >= ix.n;
     uint32_t c = 0xFFFFFFFFu;
@@ -155,56 +182,85 @@ __global__ __launch_bounds__(kBlock) void k_ring(DevIndex ix, FrameArgs fa,
         int d = dot_row<DP>(a, ix.Rv + (int64_t)pv * ix.Dp);
         c = (uint32_t)(Qc + ix.Rc[pv] + 2 * d);
     }
-    const uint32_t n = (uint32_t)ix.n;
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
-    if (!noprior) {
+    if (!noprior && ix.K > 0) {
+        uint32_t up = 0xFFFFFFFFu;        // min over evaluated keys of mh
+        bool have = false;                // best_m holds an exact size
         for (int k = 0; k < ix.K; ++k) {
             const int key = ix.keys[k];
             int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
             uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
             uint32_t lo, hi;
             ring_bounds(b, c, lo, hi);
-            const uint32_t *t = ix.T + (int64_t)k * n;
-            uint32_t st = lower_bound_u32(t, n, lo);
-            uint32_t en = upper_bound_u32(t, n, hi);
-            uint32_t m = en - st;
-            if (m < best_m) { best_m = m; best_k = k; best_st = st; best_en = en; }
+            const uint32_t *S = s_samp + k * ix.ns;
+            const int il = sample_count<false>(S, ix.ns, lo);
+            const int ih = sample_count<true>(S, ix.ns, hi);
+            uint32_t sl, sh, el, eh;
+            pos_bracket(il, ix.ns, ix.s0l, n, sl, sh);
+            pos_bracket(ih, ix.ns, ix.s0l, n, el, eh);
+            const uint32_t ml = el > sh ? el - sh : 0u, mh = eh - sl;
+            if (ml > up || (have && ml >= best_m)) continue;
+            up = min(up, mh);
+            const uint32_t *t = ix.T + (int64_t)k * ix.n16;
+            const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo);
+            const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi);
+            const uint32_t m = en - st;
+            if (!have || m < best_m) { best_m = m; best_k = k; best_st = st; best_en = en; have = true; }
         }
     }
     const bool ring = valid && !noprior && ix.K > 0 && (int64_t)best_m <= threshold;
     const bool dense = valid && !ring;
     if (valid) w.rec[qq] = make_uint4(c, best_k, best_st, best_en);
 
-    // append to the ring / dense lists, one atomic per wavefront and list
+    // ---- list appends: per-wave ballots, one atomic per list per block
     const unsigned long long rmask = __ballot(ring), dmask = __ballot(dense);
-    const int lane = threadIdx.x & 63;
-    uint32_t rbase = 0, dbase = 0;
     if (lane == 0) {
-        if (rmask) rbase = atomicAdd(&w.counters[0], (uint32_t)__popcll(rmask));
-        if (dmask) dbase = atomicAdd(&w.counters[1], (uint32_t)__popcll(dmask));
+        s_wcnt[wv][0] = (uint32_t)__popcll(rmask);
+        s_wcnt[wv][1] = (uint32_t)__popcll(dmask);
     }
-    rbase = __shfl(rbase, 0, 64);
-    dbase = __shfl(dbase, 0, 64);
-    if (ring) w.ring_list[rbase + lane_prefix(rmask)] = (uint32_t)qq;
-    if (dense) w.dense_list[dbase + lane_prefix(dmask)] = (uint32_t)qq;
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint32_t tot = 0;
+        for (int i = 0; i < kRingWaves; ++i) {
+            const uint32_t c0 = s_wcnt[i][threadIdx.x];
+            s_wcnt[i][threadIdx.x] = tot;
+            tot += c0;
+        }
+        s_base[threadIdx.x] = tot ? atomicAdd(&w.counters[threadIdx.x], tot) : 0u;
+    }
+    __syncthreads();
+    if (ring) w.ring_list[s_base[0] + s_wcnt[wv][0] + lane_prefix(rmask)] = (uint32_t)qq;
+    if (dense) w.dense_list[s_base[1] + s_wcnt[wv][1] + lane_prefix(dmask)] = (uint32_t)qq;
 
-    unsigned long long ms = valid ? best_m : 0, np = (valid && noprior) ? 1 : 0;
-    ms = wave_sum_u64(ms);
-    np = wave_sum_u64(np);
-    const unsigned long long nv = __popcll(__ballot(valid));
+    // ---- statistics: wave sums, then one atomic per counter per block
+    const unsigned long long v0 = wave_sum_u64(valid ? best_m : 0);
+    const unsigned long long v1 = wave_sum_u64(valid && noprior ? 1 : 0);
     if (lane == 0) {
-        atomicAdd(&stats[ST_QUERIES], nv);
-        atomicAdd(&stats[ST_RING], (unsigned long long)__popcll(rmask));
-        atomicAdd(&stats[ST_DENSE], (unsigned long long)__popcll(dmask));
-        atomicAdd(&stats[ST_NOPRIOR], np);
-        atomicAdd(&stats[ST_MSTAR], ms);
+        s_st[wv][0] = v0;
+        s_st[wv][1] = v1;
+        s_st[wv][2] = (unsigned long long)__popcll(rmask);
+        s_st[wv][3] = (unsigned long long)__popcll(dmask);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kRingWaves; ++i) tot += s_st[i][threadIdx.x];
+        const int slot[4] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE};
+        if (tot) atomicAdd(&stats[slot[threadIdx.x]], tot);
+        if (threadIdx.x == 3) {
+            const int64_t nv = min<int64_t>(kRingBlock, Q - (int64_t)blockIdx.x * kRingBlock);
+            atomicAdd(&stats[ST_QUERIES], (unsigned long long)nv);
+        }
     }
 }
 
 // ---------------------------------------------------------------- k_scan
 // One wavefront per routed query; grid-strides over the ring list.  Every
-// lane holds the query; lane k < K computes key k's ring bounds, which the
-// filter reads back with readlane (uniform k), so no LDS or barrier is used.
+// lane holds the query; lane k < K computes key k's ring bounds (lanes >= K
+// hold [0, 2^32-1], which the zero padding of the pivot rows always meets);
+// the filter reads them back with readlane at compile-time lane indices, so
+// no LDS or barrier is used.  Each candidate's pivot row is read as Kp/4
+// 16-byte loads issued together.
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work w,
                                                   int32_t *__restrict__ out,
@@ -213,25 +269,21 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t count = w.counters[0];
     const uint32_t n = (uint32_t)ix.n;
-    const int K = ix.K;
+    const int K = ix.K, kq = ix.Kp / 4;
     unsigned long long surv_tot = 0, mstar_tot = 0;
     for (uint32_t item = blockIdx.x * (kBlock / 64) + wv; item < count;
          item += gridDim.x * (kBlock / 64)) {
         const uint32_t qid = w.ring_list[item];
         const uint4 rec = w.rec[qid];
         const uint32_t c = rec.x, ks = rec.y, st = rec.z, en = rec.w;
-        const int qi = (int)(qid / (uint32_t)fa.Wq), qj = (int)(qid % (uint32_t)fa.Wq);
+        // lane i < DP/4 loads patch word i; readlane makes the words uniform
+        const uint32_t mine = lane < DP / 4
+            ? reinterpret_cast<const uint32_t *>(w.patches + (int64_t)qid * DP)[lane] : 0u;
         uint32_t a[DP / 4];
-        load_patch<DP>(fa.frame, fa.pitch, qj * ix.s, qi * ix.s, ix.C, ix.p * ix.C, ix.D,
-                       0x7Fu, a);
-        int sa2 = 0, sa = 0;
 #pragma unroll
-        for (int i = 0; i < DP / 4; ++i) {
-            sa2 = __builtin_amdgcn_sdot4((int)a[i], (int)a[i], sa2, false);
-            sa = __builtin_amdgcn_sdot4((int)a[i], 0x01010101, sa, false);
-        }
-        const int Qc = sa2 + 2 * sa + ix.D;
-        uint32_t lo = 0, hi = 0;
+        for (int i = 0; i < DP / 4; ++i) a[i] = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+        const int Qc = w.qc[qid];
+        uint32_t lo = 0, hi = 0xFFFFFFFFu;
         if (lane < K) {
             const int key = ix.keys[lane];
             int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
@@ -243,13 +295,23 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work
         const int32_t *Pk = ix.P + (int64_t)ks * n;
         for (uint32_t j = st + lane; j < en; j += 64) {
             const int32_t r = Pk[j];
-            const uint32_t *row = ix.Piv + (int64_t)r * K;
+            const uint4 *row = reinterpret_cast<const uint4 *>(ix.Piv + (int64_t)r * ix.Kp);
+            uint4 pv[kMaxKeys / 4];
+#pragma unroll
+            for (int q = 0; q < kMaxKeys / 4; ++q)
+                if (q < kq) pv[q] = row[q];
             bool in = true;
-            for (int k = 0; k < K; ++k) {
-                const uint32_t v = row[k];
-                const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, k);
-                const uint32_t hk = (uint32_t)__builtin_amdgcn_readlane((int)hi, k);
-                in = in && v >= lk && v <= hk;
+#pragma unroll
+            for (int q = 0; q < kMaxKeys / 4; ++q) {
+                if (q < kq) {
+                    const uint32_t x[4] = {pv[q].x, pv[q].y, pv[q].z, pv[q].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, 4 * q + e);
+                        const uint32_t hk = (uint32_t)__builtin_amdgcn_readlane((int)hi, 4 * q + e);
+                        in = in && x[e] >= lk && x[e] <= hk;
+                    }
+                }
             }
             if (in) {
                 ++cnt;
@@ -268,9 +330,14 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work
             mstar_tot += en - st;
         }
     }
-    if (lane == 0 && (surv_tot | mstar_tot)) {
-        atomicAdd(&stats[ST_SURV], surv_tot);
-        atomicAdd(&stats[ST_MSTAR_RING], mstar_tot);
+    // one atomic per counter per block
+    __shared__ unsigned long long s_acc[kBlock / 64][2];
+    if (lane == 0) { s_acc[wv][0] = surv_tot; s_acc[wv][1] = mstar_tot; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
+        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
     }
 }
 
@@ -279,9 +346,10 @@ hipError_t launch_ring_t(const DevIndex &ix, const FrameArgs &fa, const int32_t 
                          const Work &w, unsigned long long *stats, int64_t threshold,
                          hipStream_t st) {
     const int64_t Q = (int64_t)fa.Hq * fa.Wq;
-    const int blocks = (int)((Q + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP>), dim3(blocks), dim3(kBlock), 0, st, ix, fa,
-                       prev, w, stats, threshold);
+    const int64_t blocks = (Q + kRingBlock - 1) / kRingBlock;
+    const size_t lds = (size_t)ix.K * ix.ns * 4;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP>), dim3((unsigned)blocks), dim3(kRingBlock),
+                       lds, st, ix, fa, prev, w, stats, threshold);
     return hipGetLastError();
 }
 

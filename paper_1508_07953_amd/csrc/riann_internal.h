@@ -13,20 +13,44 @@ namespace riann {
 //   SSD(q, r) = Qc(q) + Rc(r) + 2 <a, v>
 //   Qc = sum (a + 1)^2,   Rc = sum v (v + 2).
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
-constexpr int32_t kBias = 1 << 22;                 // >= max Qc for D <= 256
-constexpr int32_t kRcPad = (1 << 26) - 1 - kBias;  // Rc of padding rows: never wins
-constexpr int kTile = 32;                           // references per dense tile
+constexpr int kTile = 32;        // references per dense tile (MFMA columns)
+constexpr int kStageTiles = 4;   // tiles per LDS stage of the dense search
+constexpr int kRefAlign = kTile * kStageTiles;   // n is padded to this
 constexpr int kMaxKeys = 64;
+
+// Dense-search key of a (query, reference) pair, unsigned 32-bit:
+//   X   = SSD - Qc + bias = Rc + 2<a, v> + bias,  bias = D * 16384 >= max Qc
+//   key = (X << jb) | j,   j = the reference's tile number inside a segment
+// X < 2^(32 - jb) - 1 for every real reference (jb chosen per D), so the
+// unsigned minimum of the keys is the lexicographic (SSD, index) minimum.
+// Rk[r] = (Rc[r] + bias) << jb; padding rows get 2^32 - 2^jb, above every
+// real key.  In the kernel key = (Rk[r] | j) + (acc << (jb + 1)).
 
 struct DevIndex {
     const int8_t *Rv;     // n_pad x Dp, reference rows (v bytes), 16-B aligned rows
-    const int32_t *Rc;    // n_pad, Rc per row (kRcPad for rows >= n)
-    const uint32_t *T;    // K x n, SSD(key_k, r) ascending
+    const int32_t *Rc;    // n_pad, Rc per row (0 for padding rows)
+    const int8_t *Rf;     // n_pad x Dp, the same bytes in MFMA fragment order:
+                          // tile t, k-block kb, lane l -> 16 bytes of row
+                          // 32t + (l & 31), columns 32kb + 16(l >> 5) .. +16,
+                          // at byte offset ((t * Dp/32 + kb) * 64 + l) * 16
+    const uint32_t *Rk;   // n_pad dense key bases (see above)
+    const uint32_t *T;    // K x n16, SSD(key_k, r) ascending; each key's list is
+                          // padded to whole 16-entry (64-byte) lines with
+                          // 0xFFFFFFFF, above every ring bound
     const int32_t *P;     // K x n, reference index of each T entry
-    const uint32_t *Piv;  // n x K, SSD(r, key_k)
+    const uint32_t *Piv;  // n x Kp, SSD(r, key_k); rows padded to Kp = 4*ceil(K/4)
+                          // with zeros (padding keys get the bounds [0, 2^32-1])
+    const uint32_t *Ts;   // K x ns binary-search samples Ts[k][i] = T[k][i * 16 * s0l],
+                          // copied to LDS by the ring phase
     const int32_t *keys;  // K key indices
     int64_t n, n_pad;
     int32_t D, Dp, K, p, C, s;
+    int32_t jb;           // index bits of a dense key
+    int32_t bias;         // D * 16384
+    int32_t n16;          // per-key stride of T (n rounded up to 16)
+    int32_t ns;           // samples per key
+    int32_t s0l;          // sample stride in 16-entry lines
+    int32_t Kp;           // Piv row stride
 };
 
 struct FrameArgs {
@@ -37,6 +61,8 @@ struct FrameArgs {
 
 // per-stream scratch of one frame
 struct Work {
+    uint8_t *patches;    // Q x Dp encoded query patches (a = q ^ 0x7F, zero padded)
+    int32_t *qc;         // Q, Qc of each query
     uint4 *rec;          // Q records {c, kstar, st, en}
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
@@ -51,14 +77,17 @@ enum StatSlot {
 };
 
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
+hipError_t launch_extract(const DevIndex &ix, const FrameArgs &fa, uint8_t *patches, int32_t *qc,
+                          hipStream_t st);
 hipError_t launch_ring(const DevIndex &ix, const FrameArgs &fa, const int32_t *prev,
                        const Work &w, unsigned long long *stats, int64_t threshold,
                        hipStream_t st);
 hipError_t launch_scan(const DevIndex &ix, const FrameArgs &fa, const Work &w,
                        int32_t *out, uint32_t *ssd, unsigned long long *stats,
                        hipStream_t st);
-// list == nullptr: all Q queries (count_static); otherwise list/count_dev
-hipError_t launch_dense(const DevIndex &ix, const FrameArgs &fa, const uint32_t *list,
+// list == nullptr: all Q queries (count_static); otherwise list/count_dev.
+// Reads the query patches written by launch_extract.
+hipError_t launch_dense(const DevIndex &ix, const Work &w, const uint32_t *list,
                         const uint32_t *count_dev, uint32_t count_static, int32_t *out,
                         uint32_t *ssd, hipStream_t st);
 
