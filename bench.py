@@ -34,6 +34,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def dense_traffic_bytes():
+    """HBM bytes per k_dense dispatch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "hd720_k_dense_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1508_07953_amd", "csrc", "k_dense.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec["bytes_per_dispatch"] if rec.get("k_dense_source_sha256") == sha else None
+
+
 def cpu_baseline(wl, f0, f1, target_s):
     """Oracle exact-mode RIANN timed on the host's cores on a sample of one
     frame's queries; its previous field is the oracle's own brute force."""
@@ -72,6 +86,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="after the timed region, run one plain device copy of this many "
+                         "MiB (reference point for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the search shards by frames/streams "
@@ -160,11 +177,21 @@ def main():
         achieved = ops / (ms_per_launch * 1e-3) / 1e12
         result["roofline"] = {"bound": "mfma", "kernel": "k_dense (int8 MFMA, routed queries)",
                               "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                              "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                              "frac": achieved / INT8_PEAK_TOPS,
+                              "traffic": dense_traffic_bytes(),
                               "ms_per_launch": ms_per_launch,
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
                                           for k, v in prof.items() if v["launches"]}
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nb
+        del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, frames_h[0], frames_h[1], args.cpu_seconds)
     idx.close()

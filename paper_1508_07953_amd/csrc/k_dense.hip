@@ -4,20 +4,25 @@
 //
 // With a = 127 - q and v = r - 128 (both int8), SSD(q, r) = Qc + Rc + 2<a, v>
 // (encodings in riann_internal.h); the GEMM gives <a, v> exactly in int32.
-// Work split: a block of 4 wavefronts owns 256 queries (64 per wavefront, as
+// Work split: a block of 8 wavefronts owns 512 queries (64 per wavefront, as
 // two 32-row MFMA A operands held in registers for the whole pass) and
-// streams the reference set through LDS in stages of 4 tiles x 32 references,
-// double buffered; the stage copy is a straight coalesced copy because the
-// references are stored in MFMA fragment order.  Per tile each wavefront
-// reads its B fragments from LDS (conflict-free, 16 consecutive bytes per
-// lane) and runs 2 x Dp/32 MFMAs.  Epilogue per (query, reference) pair: one
-// v_lshl_add forms the key (X << jb | j) and a v_min3 keeps the running
-// unsigned minimum per query row and lane column, which is the (SSD, index)
-// argmin over that column.  When the tile count exceeds the key's j range,
-// tiles are processed in segments: at a segment end the winner's index is
-// saved and the j bits of the running key are cleared, so an equal X in a
-// later segment (a higher index) never displaces it.  A cross-lane
-// reduction over the 32 columns finishes each query.
+// streams the reference set through LDS in stages of ST tiles x 32
+// references.  The references are stored in MFMA fragment order, so a stage
+// is a straight copy: each wavefront moves 1-KB chunks with global-to-LDS
+// DMA (global_load_lds_dwordx4), no registers involved.  Two distinct LDS
+// buffers alternate (the stage loop is unrolled by two so each buffer's role
+// is static): the DMA of stage s+1 runs while stage s is computed, and the
+// one barrier per stage both publishes the new stage and retires the old.
+// Per tile each wavefront reads its B fragments from LDS (conflict-free, 16
+// consecutive bytes per lane) and runs 2 x Dp/32 MFMAs.  Epilogue per
+// (query, reference) pair: one v_lshl_add forms the key (X << jb | j) and a
+// v_min3 (two tiles per step) keeps the running unsigned minimum per query
+// row and lane column, which is the (SSD, index) argmin over that column.
+// When the tile count exceeds the key's j range, tiles are processed in
+// segments: at a segment end the winner's index is saved and the j bits of
+// the running key are cleared, so an equal X in a later segment (a higher
+// index) never displaces it.  A cross-lane reduction over the 32 columns
+// finishes each query.
 #include "riann_internal.h"
 
 namespace riann {
@@ -26,11 +31,15 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
 
-constexpr int kBlock = 256;                 // 4 wavefronts
+constexpr int kWaves = 8;                   // wavefronts per block
+constexpr int kBlock = 64 * kWaves;
 constexpr int kQB = 2;                      // 32-query row blocks per wavefront
 constexpr int kWaveQ = 32 * kQB;
-constexpr int kBlockQ = kWaveQ * (kBlock / 64);
+constexpr int kBlockQ = kWaveQ * kWaves;
+static_assert(kRefAlign % (kTile * 8) == 0, "reference padding must cover 8-tile stages");
 
 __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
     unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
@@ -39,88 +48,41 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     return ((unsigned long long)hi << 32) | lo;
 }
 
-template <int DP, bool SEG, int TPS>
-__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
-                                                   const uint32_t *__restrict__ list,
-                                                   const uint32_t *__restrict__ count_dev,
-                                                   uint32_t count_static,
-                                                   int32_t *__restrict__ out,
-                                                   uint32_t *__restrict__ ssd) {
-    constexpr int KB = DP / 32;
-    constexpr int FRAG = KB * 1024;               // fragment bytes of one tile
-    constexpr int STAGE = kStageTiles * FRAG;     // fragment bytes of one stage
-    constexpr int PIECES = STAGE / 16 / kBlock;   // 16-byte copies per thread
-    static_assert(PIECES * 16 * kBlock == STAGE, "stage copy must divide evenly");
-    static_assert(kStageTiles % TPS == 0, "tiles per step must divide a stage");
-    __shared__ __attribute__((aligned(16))) int8_t s_frag[2][STAGE];
-    __shared__ __attribute__((aligned(16))) uint32_t s_rk[2][kStageTiles * kTile];
-
-    const uint32_t count = count_dev ? *count_dev : count_static;
-    const uint32_t qbase = blockIdx.x * kBlockQ;
-    if (qbase >= count) return;                   // whole block exits together
-
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int col = lane & 31, grp = lane >> 5;
-    const int nstages = (int)(ix.n_pad / (kTile * kStageTiles));
-    const uint32_t jb = (uint32_t)ix.jb, ash = jb + 1;
-    // SEG: j runs 1..seglen, seglen a multiple of TPS, so a segment always
-    // ends on the last tile of a step (segments start on step boundaries)
-    const uint32_t seglen = (1u << jb) - TPS;
-    const uint4 *gfrag = reinterpret_cast<const uint4 *>(ix.Rf);
-    const uint4 *grk = reinterpret_cast<const uint4 *>(ix.Rk);
-
-    // ---- stage 0 copy first, so its latency overlaps the query loads
+// DMA of stage `sg` (ST tiles of fragments plus their ST*32 key bases) into
+// one LDS buffer.  Each 1-KB chunk is one wavefront-wide 16-byte-per-lane copy.
+template <int KB, int ST>
+__device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
+                                          const uint32_t *__restrict__ gr, int sg, int8_t *lf,
+                                          uint32_t *lr, int wv, int lane) {
+    constexpr int CH = ST * KB;
+    const int8_t *src = gf + (int64_t)sg * CH * 1024;
 #pragma unroll
-    for (int k = 0; k < PIECES; ++k)
-        reinterpret_cast<uint4 *>(s_frag[0])[tid + k * kBlock] = gfrag[tid + k * kBlock];
-    if (tid < kStageTiles * kTile / 4) reinterpret_cast<uint4 *>(s_rk[0])[tid] = grk[tid];
-
-    // ---- A operands: rows `col` of the wavefront's two 32-query blocks,
-    // 16 aligned bytes per k-block from the extracted patches
-    v4i A[kQB][KB];
-    uint32_t qid[kQB];
-    int qc[kQB];
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
-        qid[qb] = list ? list[slot] : slot;
-        const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) + (int64_t)qid[qb] * DP +
-                            grp * 16;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) A[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
-        qc[qb] = w.qc[qid[qb]];
+    for (int i = 0; i < (CH + kWaves - 1) / kWaves; ++i) {
+        const int c = wv + kWaves * i;
+        if (c < CH)
+            __builtin_amdgcn_global_load_lds((glb_void *)(src + c * 1024 + lane * 16),
+                                             (lds_void *)(lf + c * 1024), 16, 0, 0);
     }
+    if (wv == kWaves - 1 && lane < ST * 8)
+        __builtin_amdgcn_global_load_lds((glb_void *)(gr + (int64_t)sg * ST * kTile + lane * 4),
+                                         (lds_void *)lr, 16, 0, 0);
+}
 
+template <int DP, bool SEG, int TPS, int ST>
+struct DenseState {
+    static constexpr int KB = DP / 32;
+    v4i A[kQB][KB];
     uint32_t best[kQB][16];
     uint32_t gI[SEG ? kQB : 1][16];
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) best[qb][i] = ~0u;
-    if (SEG) {
-#pragma unroll
-        for (int qb = 0; qb < (SEG ? kQB : 1); ++qb)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) gI[qb][i] = 0;
-    }
-    __syncthreads();
+    uint32_t segbase;
 
-    uint32_t segbase = 0;   // first tile of the current segment (SEG)
-    for (int sg = 0; sg < nstages; ++sg) {
-        const int buf = sg & 1;
-        const bool more = sg + 1 < nstages;
-        // prefetch the next stage into registers (the last stage re-reads
-        // itself, harmlessly, so the loads are unconditional)
-        const int nx = more ? sg + 1 : sg;
-        uint4 pf[PIECES];
-        const uint4 *src = gfrag + (int64_t)nx * (STAGE / 16);
-#pragma unroll
-        for (int k = 0; k < PIECES; ++k) pf[k] = src[tid + k * kBlock];
-        const uint4 pr = grk[(int64_t)nx * (kStageTiles * kTile / 4) + (tid & 31)];
+    // all tiles of one LDS stage; tile t0 = sg * ST is its first
+    __device__ __forceinline__ void stage(const int8_t *lf, const uint32_t *lr, uint32_t t0s,
+                                          int lane, int col, uint32_t jb, uint32_t ash,
+                                          uint32_t seglen, int64_t ntiles) {
 #pragma unroll 1
-        for (int tp = 0; tp < kStageTiles; tp += TPS) {
-            // TPS tiles per step: with two, each best[] update is one v_min3
-            const uint32_t t0 = (uint32_t)(sg * kStageTiles + tp);
+        for (int tp = 0; tp < ST; tp += TPS) {
+            const uint32_t t0 = t0s + (uint32_t)tp;
             const uint32_t j0 = SEG ? (t0 - segbase + 1) : t0;
             v4i B[TPS][KB];
             uint32_t rnj[TPS];
@@ -128,9 +90,9 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
             for (int u = 0; u < TPS; ++u) {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb)
-                    B[u][kb] = *reinterpret_cast<const v4i *>(
-                        &s_frag[buf][((tp + u) * KB + kb) * 1024 + lane * 16]);
-                rnj[u] = s_rk[buf][(tp + u) * kTile + col] | (j0 + u);
+                    B[u][kb] = *reinterpret_cast<const v4i *>(lf + ((tp + u) * KB + kb) * 1024 +
+                                                              lane * 16);
+                rnj[u] = lr[(tp + u) * kTile + col] | (j0 + u);
             }
 #pragma unroll
             for (int qb = 0; qb < kQB; ++qb) {
@@ -152,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
                     best[qb][i] = m;
                 }
             }
-            if (SEG && (j0 + TPS - 1 == seglen || (int64_t)t0 + TPS == ix.n_pad / kTile)) {
+            if (SEG && (j0 + TPS - 1 == seglen || (int64_t)t0 + TPS == ntiles)) {
                 const uint32_t jm = (1u << jb) - 1;
 #pragma unroll
                 for (int qb = 0; qb < (SEG ? kQB : 1); ++qb)
@@ -167,13 +129,74 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
                 segbase = t0 + TPS;
             }
         }
-        if (more) {
+    }
+};
+
+template <int DP, bool SEG, int TPS, int ST>
+__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ count_dev,
+                                                   uint32_t count_static,
+                                                   int32_t *__restrict__ out,
+                                                   uint32_t *__restrict__ ssd) {
+    constexpr int KB = DP / 32;
+    constexpr int STAGE = ST * KB * 1024;         // fragment bytes of one stage
+    static_assert(ST % TPS == 0, "tiles per step must divide a stage");
+    __shared__ __attribute__((aligned(16))) int8_t s_f0[STAGE];
+    __shared__ __attribute__((aligned(16))) int8_t s_f1[STAGE];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r0[ST * kTile];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r1[ST * kTile];
+
+    const uint32_t count = count_dev ? *count_dev : count_static;
+    const uint32_t qbase = blockIdx.x * kBlockQ;
+    if (qbase >= count) return;                   // whole block exits together
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col = lane & 31, grp = lane >> 5;
+    const int nstages = (int)(ix.n_pad / (kTile * ST));
+    const int64_t ntiles = ix.n_pad / kTile;
+    const uint32_t jb = (uint32_t)ix.jb, ash = jb + 1;
+    // SEG: j runs 1..seglen, seglen a multiple of TPS, so a segment always
+    // ends on the last tile of a step (segments start on step boundaries)
+    const uint32_t seglen = (1u << jb) - TPS;
+
+    // stage 0 DMA first, so it overlaps the query loads
+    stage_dma<KB, ST>(ix.Rf, ix.Rk, 0, s_f0, s_r0, wv, lane);
+
+    // ---- A operands: rows `col` of the wavefront's two 32-query blocks,
+    // 16 aligned bytes per k-block from the extracted patches
+    DenseState<DP, SEG, TPS, ST> S;
+    uint32_t qid[kQB];
+    int qc[kQB];
 #pragma unroll
-            for (int k = 0; k < PIECES; ++k)
-                reinterpret_cast<uint4 *>(s_frag[buf ^ 1])[tid + k * kBlock] = pf[k];
-            if (tid < kStageTiles * kTile / 4) reinterpret_cast<uint4 *>(s_rk[buf ^ 1])[tid] = pr;
+    for (int qb = 0; qb < kQB; ++qb) {
+        const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
+        qid[qb] = list ? list[slot] : slot;
+        const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) + (int64_t)qid[qb] * DP +
+                            grp * 16;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) S.A[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
+        qc[qb] = w.qc[qid[qb]];
+    }
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            S.best[qb][i] = ~0u;
+            S.gI[SEG ? qb : 0][i] = 0;
         }
+    S.segbase = 0;
+    __syncthreads();
+
+    for (int sg = 0; sg < nstages; sg += 2) {
+        if (sg + 1 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Rk, sg + 1, s_f1, s_r1, wv, lane);
+        S.stage(s_f0, s_r0, (uint32_t)(sg * ST), lane, col, jb, ash, seglen, ntiles);
         __syncthreads();
+        if (sg + 1 < nstages) {
+            if (sg + 2 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Rk, sg + 2, s_f0, s_r0, wv, lane);
+            S.stage(s_f1, s_r1, (uint32_t)((sg + 1) * ST), lane, col, jb, ash, seglen, ntiles);
+            __syncthreads();
+        }
     }
 
     // ---- per 32-query block: transpose-reduce over the 32 columns.  Four
@@ -189,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
         unsigned long long v[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const uint32_t b = best[qb][i];
-            const uint32_t idx = SEG ? gI[SEG ? qb : 0][i] : (b & jm) * kTile + col;
+            const uint32_t b = S.best[qb][i];
+            const uint32_t idx = SEG ? S.gI[SEG ? qb : 0][i] : (b & jm) * kTile + col;
             v[i] = ((unsigned long long)(b >> jb) << 32) | idx;
         }
 #pragma unroll
@@ -222,15 +245,17 @@ hipError_t launch_dense_t(const DevIndex &ix, const Work &w, const uint32_t *lis
                           uint32_t *ssd, hipStream_t st) {
     int64_t blocks = ((int64_t)count_static + kBlockQ - 1) / kBlockQ;
     if (blocks < 1) blocks = 1;
-    // tile pairs (one v_min3 per update) while the epilogue is the bound;
-    // single tiles for wide patches, where the matrix cores are
+    // tile pairs (one v_min3 per update) while the epilogue is the bound,
+    // single tiles for wide patches, where the matrix cores are; 8-tile
+    // stages while they fit two blocks per CU in LDS
     constexpr int TPS = DP <= 96 ? 2 : 1;
+    constexpr int ST = DP <= 64 ? 8 : 4;
     const bool seg = (ix.n_pad / kTile) > (int64_t)(1u << ix.jb);
     if (seg)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, true, TPS>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, true, TPS, ST>), dim3((unsigned)blocks),
                            dim3(kBlock), 0, st, ix, w, list, count_dev, count_static, out, ssd);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, false, TPS>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, false, TPS, ST>), dim3((unsigned)blocks),
                            dim3(kBlock), 0, st, ix, w, list, count_dev, count_static, out, ssd);
     return hipGetLastError();
 }

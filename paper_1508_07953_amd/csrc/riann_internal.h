@@ -14,8 +14,7 @@ namespace riann {
 //   Qc = sum (a + 1)^2,   Rc = sum v (v + 2).
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
-constexpr int kStageTiles = 4;   // tiles per LDS stage of the dense search
-constexpr int kRefAlign = kTile * kStageTiles;   // n is padded to this
+constexpr int kRefAlign = 256;   // n is padded to whole 8-tile dense stages
 constexpr int kMaxKeys = 64;
 
 // Dense-search key of a (query, reference) pair, unsigned 32-bit:
