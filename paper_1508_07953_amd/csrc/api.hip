@@ -103,7 +103,7 @@ int64_t index_bytes(int64_t n, int D, int K) {
            (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 16 + 8) + 4096; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 16 + 8) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -304,6 +304,7 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     int64_t o = 0;
     nw.patches = (uint8_t *)(b + o);  o = round_up(o + cap * Dp, 256);
     nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
+    nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
     nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
@@ -320,20 +321,33 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-riann_status_t frame_args(const riann_index *h, const uint8_t *frame, int32_t H, int32_t W,
-                          int64_t pitch, FrameArgs *fa) {
+// Checks one frame and fills its descriptor (qbase/tbase are set later).
+riann_status_t frame_desc(const riann_index *h, const uint8_t *frame, int32_t H, int32_t W,
+                          int64_t pitch, const int32_t *prev, int32_t *out, uint32_t *ssd,
+                          int32_t mode, FrameDesc *fd) {
     const int p = h->prm.patch, C = h->prm.channels, s = h->prm.stride;
     if (!frame) return fail(RIANN_E_INVALID, "frame is NULL");
+    if (!out) return fail(RIANN_E_INVALID, "out is NULL");
+    if (mode != RIANN_MODE_RING && mode != RIANN_MODE_FULL)
+        return fail(RIANN_E_INVALID, "bad frame mode");
     if (H < p || W < p) return fail(RIANN_E_INVALID, "frame smaller than one patch");
     if (pitch < (int64_t)W * C) return fail(RIANN_E_INVALID, "pitch < W * channels");
-    fa->frame = frame;
-    fa->pitch = pitch;
-    fa->H = H;
-    fa->W = W;
-    fa->Hq = (H - p) / s + 1;
-    fa->Wq = (W - p) / s + 1;
-    if ((int64_t)fa->Hq * fa->Wq >= (int64_t)0xFFFFFFFFu)
-        return fail(RIANN_E_UNSUPPORTED, "too many queries in one frame");
+    fd->frame = frame;
+    fd->pitch = pitch;
+    fd->H = H;
+    fd->W = W;
+    fd->Hq = (H - p) / s + 1;
+    fd->Wq = (W - p) / s + 1;
+    fd->mode = mode;
+    fd->prev = mode == RIANN_MODE_RING ? prev : nullptr;
+    fd->out = out;
+    fd->ssd = ssd;
+    const int64_t Q = (int64_t)fd->Hq * fd->Wq;
+    if (Q >= (int64_t)0x7FFFFFFF) return fail(RIANN_E_UNSUPPORTED, "too many queries in one frame");
+    const size_t qb = (size_t)Q * 4;
+    if (overlap(fd->prev, qb, out, qb)) return fail(RIANN_E_INVALID, "prev overlaps out");
+    if (overlap(ssd, qb, out, qb)) return fail(RIANN_E_INVALID, "ssd overlaps out");
+    if (overlap(fd->prev, qb, ssd, qb)) return fail(RIANN_E_INVALID, "prev overlaps ssd");
     return RIANN_OK;
 }
 
@@ -360,69 +374,59 @@ struct KTimer {
     }
 };
 
-riann_status_t do_match(riann_index *h, const FrameArgs &fa, const int32_t *prev,
-                        int32_t *out, uint32_t *ssd, hipStream_t st) {
-    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
-    const size_t qb = (size_t)Q * 4;
-    if (!out) return fail(RIANN_E_INVALID, "out is NULL");
-    if (overlap(prev, qb, out, qb)) return fail(RIANN_E_INVALID, "prev overlaps out");
-    if (overlap(ssd, qb, out, qb)) return fail(RIANN_E_INVALID, "ssd overlaps out");
-    if (overlap(prev, qb, ssd, qb)) return fail(RIANN_E_INVALID, "prev overlaps ssd");
+// One launch sequence over up to kMaxBatch frames (descriptors validated).
+riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
+    int64_t q = 0;
+    int32_t t = 0;
+    bool all_full = true;
+    for (int i = 0; i < fb.n; ++i) {
+        FrameDesc &fd = fb.f[i];
+        fd.qbase = q;
+        fd.tbase = t;
+        q += (int64_t)fd.Hq * fd.Wq;
+        t += ((fd.Wq + kExtTX - 1) / kExtTX) * ((fd.Hq + kExtTY - 1) / kExtTY);
+        all_full = all_full && fd.mode == RIANN_MODE_FULL;
+    }
+    if (q >= (int64_t)0x7FFFFFFF) return fail(RIANN_E_UNSUPPORTED, "too many queries in one batch");
+    fb.Q = q;
+    fb.ntiles = t;
+    fb.all_full = all_full ? 1 : 0;
     Work w;
-    riann_status_t s = get_work(h, st, Q, &w);
-    if (s != RIANN_OK) return s;
-    hipError_t e = launch_zero_u32(w.counters, 4, st);
-    if (e != hipSuccess) return hip_fail(e, "counter clear");
-    {
-        KTimer t(h, RIANN_K_EXTRACT, st);
-        e = launch_extract(h->dix, fa, w.patches, w.qc, st);
-        t.stop();
-        if (e != hipSuccess) return hip_fail(e, "k_extract launch");
-    }
-    {
-        KTimer t(h, RIANN_K_RING, st);
-        e = launch_ring(h->dix, fa, prev, w, h->dstats, h->threshold, st);
-        t.stop();
-        if (e != hipSuccess) return hip_fail(e, "k_ring launch");
-    }
-    {
-        KTimer t(h, RIANN_K_SCAN, st);
-        e = launch_scan(h->dix, fa, w, out, ssd, h->dstats, st);
-        t.stop();
-        if (e != hipSuccess) return hip_fail(e, "k_scan launch");
-    }
-    {
-        KTimer t(h, RIANN_K_DENSE, st);
-        e = launch_dense(h->dix, w, w.dense_list, w.counters + 1, (uint32_t)Q, out, ssd, st);
-        t.stop();
-        if (e != hipSuccess) return hip_fail(e, "k_dense launch");
-    }
-    h->frames.fetch_add(1);
-    return RIANN_OK;
-}
-
-riann_status_t do_full(riann_index *h, const FrameArgs &fa, int32_t *out, uint32_t *ssd,
-                       hipStream_t st) {
-    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
-    if (!out) return fail(RIANN_E_INVALID, "out is NULL");
-    if (overlap(ssd, (size_t)Q * 4, out, (size_t)Q * 4))
-        return fail(RIANN_E_INVALID, "ssd overlaps out");
-    Work w;
-    riann_status_t s = get_work(h, st, Q, &w);
+    riann_status_t s = get_work(h, st, q, &w);
     if (s != RIANN_OK) return s;
     hipError_t e;
+    if (!all_full) {
+        e = launch_zero_u32(w.counters, 4, st);
+        if (e != hipSuccess) return hip_fail(e, "counter clear");
+    }
     {
-        KTimer t(h, RIANN_K_EXTRACT, st);
-        e = launch_extract(h->dix, fa, w.patches, w.qc, st);
-        t.stop();
+        KTimer tm(h, RIANN_K_EXTRACT, st);
+        e = launch_extract(h->dix, fb, w, st);
+        tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     }
-    KTimer t(h, RIANN_K_FULL, st);
-    e = launch_dense(h->dix, w, nullptr, nullptr, (uint32_t)Q, out, ssd, st);
-    t.stop();
-    if (e != hipSuccess) return hip_fail(e, "k_dense launch");
-    h->frames.fetch_add(1);
-    h->full_queries.fetch_add((uint64_t)Q);
+    if (!all_full) {
+        {
+            KTimer tm(h, RIANN_K_RING, st);
+            e = launch_ring(h->dix, fb, w, h->dstats, h->threshold, st);
+            tm.stop();
+            if (e != hipSuccess) return hip_fail(e, "k_ring launch");
+        }
+        {
+            KTimer tm(h, RIANN_K_SCAN, st);
+            e = launch_scan(h->dix, fb, w, h->dstats, st);
+            tm.stop();
+            if (e != hipSuccess) return hip_fail(e, "k_scan launch");
+        }
+    }
+    {
+        KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
+        e = launch_dense(h->dix, fb, w, st);
+        tm.stop();
+        if (e != hipSuccess) return hip_fail(e, "k_dense launch");
+    }
+    h->frames.fetch_add((uint64_t)fb.n);
+    if (all_full) h->full_queries.fetch_add((uint64_t)q);
     return RIANN_OK;
 }
 
@@ -492,44 +496,56 @@ riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev, int3
                                  int64_t pitch, const int32_t *prev_dev, int32_t *out_dev,
                                  uint32_t *ssd_dev, void *hip_stream) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
-    FrameArgs fa;
-    riann_status_t s = frame_args(h, frame_dev, H, W, pitch, &fa);
+    FrameBatch fb;
+    fb.n = 1;
+    riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, prev_dev, out_dev, ssd_dev,
+                                  RIANN_MODE_RING, &fb.f[0]);
     if (s != RIANN_OK) return s;
     DeviceGuard g(h->device);
-    return do_match(h, fa, prev_dev, out_dev, ssd_dev, (hipStream_t)hip_stream);
+    return run_batch(h, fb, (hipStream_t)hip_stream);
 }
 
 riann_status_t riann_full_search(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
                                  int64_t pitch, int32_t *out_dev, uint32_t *ssd_dev,
                                  void *hip_stream) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
-    FrameArgs fa;
-    riann_status_t s = frame_args(h, frame_dev, H, W, pitch, &fa);
+    FrameBatch fb;
+    fb.n = 1;
+    riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, nullptr, out_dev, ssd_dev,
+                                  RIANN_MODE_FULL, &fb.f[0]);
     if (s != RIANN_OK) return s;
     DeviceGuard g(h->device);
-    return do_full(h, fa, out_dev, ssd_dev, (hipStream_t)hip_stream);
+    return run_batch(h, fb, (hipStream_t)hip_stream);
 }
 
 riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *descs, int32_t n,
                                  void *hip_stream) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
     if (n < 0 || (n > 0 && !descs)) return fail(RIANN_E_INVALID, "bad descriptor array");
-    std::vector<FrameArgs> fas((size_t)n);
-    for (int i = 0; i < n; ++i) {
-        riann_status_t s = frame_args(h, descs[i].frame, descs[i].H, descs[i].W, descs[i].pitch,
-                                      &fas[(size_t)i]);
-        if (s != RIANN_OK) return s;
-        if (descs[i].mode != RIANN_MODE_RING && descs[i].mode != RIANN_MODE_FULL)
-            return fail(RIANN_E_INVALID, "bad descriptor mode");
-        if (!descs[i].out) return fail(RIANN_E_INVALID, "descriptor out is NULL");
-    }
-    DeviceGuard g(h->device);
-    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<FrameDesc> fds((size_t)n);
     for (int i = 0; i < n; ++i) {
         const riann_frame_desc_t &d = descs[i];
-        riann_status_t s = d.mode == RIANN_MODE_FULL
-                               ? do_full(h, fas[(size_t)i], d.out, d.ssd, st)
-                               : do_match(h, fas[(size_t)i], d.prev, d.out, d.ssd, st);
+        riann_status_t s = frame_desc(h, d.frame, d.H, d.W, d.pitch, d.prev, d.out, d.ssd, d.mode,
+                                      &fds[(size_t)i]);
+        if (s != RIANN_OK) return s;
+    }
+    // outputs of different frames must not overlap
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const size_t qi = (size_t)fds[(size_t)i].Hq * fds[(size_t)i].Wq * 4;
+            const size_t qj = (size_t)fds[(size_t)j].Hq * fds[(size_t)j].Wq * 4;
+            const FrameDesc &a = fds[(size_t)i], &b = fds[(size_t)j];
+            if (overlap(a.out, qi, b.out, qj) || overlap(a.out, qi, b.ssd, qj) ||
+                overlap(a.ssd, qi, b.out, qj) || overlap(a.ssd, qi, b.ssd, qj))
+                return fail(RIANN_E_INVALID, "output fields of two frames overlap");
+        }
+    DeviceGuard g(h->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+        FrameBatch fb;
+        fb.n = std::min(kMaxBatch, n - i0);
+        for (int i = 0; i < fb.n; ++i) fb.f[i] = fds[(size_t)(i0 + i)];
+        riann_status_t s = run_batch(h, fb, st);
         if (s != RIANN_OK) return s;
     }
     return RIANN_OK;

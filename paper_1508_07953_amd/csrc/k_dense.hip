@@ -133,12 +133,7 @@ struct DenseState {
 };
 
 template <int DP, bool SEG, int TPS, int ST>
-__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
-                                                   const uint32_t *__restrict__ list,
-                                                   const uint32_t *__restrict__ count_dev,
-                                                   uint32_t count_static,
-                                                   int32_t *__restrict__ out,
-                                                   uint32_t *__restrict__ ssd) {
+__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Work w) {
     constexpr int KB = DP / 32;
     constexpr int STAGE = ST * KB * 1024;         // fragment bytes of one stage
     static_assert(ST % TPS == 0, "tiles per step must divide a stage");
@@ -147,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
     __shared__ __attribute__((aligned(16))) uint32_t s_r0[ST * kTile];
     __shared__ __attribute__((aligned(16))) uint32_t s_r1[ST * kTile];
 
-    const uint32_t count = count_dev ? *count_dev : count_static;
+    // whole-frame batches search every query; otherwise the dense list
+    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
+    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
     const uint32_t qbase = blockIdx.x * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
@@ -233,17 +230,18 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, Work w,
         const int Qc_m = __shfl(qc[qb], m_own, 64);
         if ((col >> 4) == qb && qbase + (uint32_t)(wv * kWaveQ + qb * 32 + m_own) < count) {
             const uint32_t X = (uint32_t)(res >> 32);
-            out[qm] = (int32_t)(uint32_t)res;
-            if (ssd) ssd[qm] = (uint32_t)((int)X - ix.bias + Qc_m);
+            const FrameDesc *fdp = &fb.f[w.fid[qm]];
+            const int64_t ql = (int64_t)qm - fdp->qbase;
+            fdp->out[ql] = (int32_t)(uint32_t)res;
+            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)((int)X - ix.bias + Qc_m);
         }
     }
 }
 
 template <int DP>
-hipError_t launch_dense_t(const DevIndex &ix, const Work &w, const uint32_t *list,
-                          const uint32_t *count_dev, uint32_t count_static, int32_t *out,
-                          uint32_t *ssd, hipStream_t st) {
-    int64_t blocks = ((int64_t)count_static + kBlockQ - 1) / kBlockQ;
+hipError_t launch_dense_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                          hipStream_t st) {
+    int64_t blocks = (fb.Q + kBlockQ - 1) / kBlockQ;
     if (blocks < 1) blocks = 1;
     // tile pairs (one v_min3 per update) while the epilogue is the bound,
     // single tiles for wide patches, where the matrix cores are; 8-tile
@@ -253,27 +251,26 @@ hipError_t launch_dense_t(const DevIndex &ix, const Work &w, const uint32_t *lis
     const bool seg = (ix.n_pad / kTile) > (int64_t)(1u << ix.jb);
     if (seg)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, true, TPS, ST>), dim3((unsigned)blocks),
-                           dim3(kBlock), 0, st, ix, w, list, count_dev, count_static, out, ssd);
+                           dim3(kBlock), 0, st, ix, fb, w);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, false, TPS, ST>), dim3((unsigned)blocks),
-                           dim3(kBlock), 0, st, ix, w, list, count_dev, count_static, out, ssd);
+                           dim3(kBlock), 0, st, ix, fb, w);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_dense(const DevIndex &ix, const Work &w, const uint32_t *list,
-                        const uint32_t *count_dev, uint32_t count_static, int32_t *out,
-                        uint32_t *ssd, hipStream_t st) {
+hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                        hipStream_t st) {
     switch (ix.Dp) {
-    case 32: return launch_dense_t<32>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 64: return launch_dense_t<64>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 96: return launch_dense_t<96>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 128: return launch_dense_t<128>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 160: return launch_dense_t<160>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 192: return launch_dense_t<192>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 224: return launch_dense_t<224>(ix, w, list, count_dev, count_static, out, ssd, st);
-    case 256: return launch_dense_t<256>(ix, w, list, count_dev, count_static, out, ssd, st);
+    case 32: return launch_dense_t<32>(ix, fb, w, st);
+    case 64: return launch_dense_t<64>(ix, fb, w, st);
+    case 96: return launch_dense_t<96>(ix, fb, w, st);
+    case 128: return launch_dense_t<128>(ix, fb, w, st);
+    case 160: return launch_dense_t<160>(ix, fb, w, st);
+    case 192: return launch_dense_t<192>(ix, fb, w, st);
+    case 224: return launch_dense_t<224>(ix, fb, w, st);
+    case 256: return launch_dense_t<256>(ix, fb, w, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,7 +1,8 @@
 // k_extract.hip -- LDS-tiled patch extraction (the query patches q_{x,y,t}
 // of one frame, every p x p x C window at stride s).
 //
-// A block owns a tile of 4 x 64 query positions.  It copies the frame region
+// A block owns a tile of 4 x 64 query positions of one frame of the launch's
+// batch (tiles of all frames are numbered consecutively).  It copies the frame region
 // those windows cover into LDS with coalesced byte loads (each frame byte is
 // read from HBM once per tile and reused from LDS by up to (p/s)^2 windows),
 // then each thread assembles one query's patch in (dy, dx, c) order, encodes
@@ -14,15 +15,19 @@ namespace riann {
 
 namespace {
 
-constexpr int kTX = 64, kTY = 4;     // query columns x rows per block
+constexpr int kTX = kExtTX, kTY = kExtTY;     // query columns x rows per block
 
 template <int DP>
-__global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameArgs fa,
-                                                       uint8_t *__restrict__ patches,
-                                                       int32_t *__restrict__ qc) {
+__global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb, Work w) {
     extern __shared__ uint8_t s_tile[];
     const int p = ix.p, C = ix.C, s = ix.s, D = ix.D;
-    const int qx0 = blockIdx.x * kTX, qy0 = blockIdx.y * kTY;
+    // frame of this tile (tile ranges are consecutive per frame)
+    int f = 0;
+    while (f + 1 < fb.n && (int)blockIdx.x >= fb.f[f + 1].tbase) ++f;
+    const FrameDesc &fa = fb.f[f];
+    const int lt = (int)blockIdx.x - fa.tbase;
+    const int tiles_x = (fa.Wq + kTX - 1) / kTX;
+    const int qx0 = (lt % tiles_x) * kTX, qy0 = (lt / tiles_x) * kTY;
     const int nqx = min(kTX, fa.Wq - qx0), nqy = min(kTY, fa.Hq - qy0);
     // frame region covered by this block's windows
     const int rw = ((nqx - 1) * s + p) * C;     // bytes per region row
@@ -39,7 +44,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameArgs fa,
     if (tx >= nqx || ty >= nqy) return;
     const uint8_t *win = s_tile + (ty * s) * ldw + (tx * s) * C;
     const int rowlen = p * C;
-    uint32_t w[DP / 4];
+    uint32_t wd[DP / 4];
     int dy = 0, rem = 0;
     int sa2 = 0, sa = 0;
 #pragma unroll
@@ -56,42 +61,42 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameArgs fa,
             dy = wrap ? dy + 1 : dy;
             if (dy >= p) dy = p - 1;             // k >= D: stay inside the window
         }
-        w[i] = word;
+        wd[i] = word;
         sa2 = __builtin_amdgcn_sdot4((int)word, (int)word, sa2, false);
         sa = __builtin_amdgcn_sdot4((int)word, 0x01010101, sa, false);
     }
-    const int64_t q = (int64_t)(qy0 + ty) * fa.Wq + (qx0 + tx);
-    uint4 *dst = reinterpret_cast<uint4 *>(patches + q * DP);
+    const int64_t q = fa.qbase + (int64_t)(qy0 + ty) * fa.Wq + (qx0 + tx);
+    uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
 #pragma unroll
     for (int i = 0; i < DP / 16; ++i)
-        dst[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+        dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
     // padding bytes are a = 0 and add nothing to the sums
-    qc[q] = sa2 + 2 * sa + D;
+    w.qc[q] = sa2 + 2 * sa + D;
+    w.fid[q] = (uint8_t)f;
 }
 
 template <int DP>
-hipError_t launch_extract_t(const DevIndex &ix, const FrameArgs &fa, uint8_t *patches,
-                            int32_t *qc, hipStream_t st) {
-    dim3 grid((fa.Wq + kTX - 1) / kTX, (fa.Hq + kTY - 1) / kTY);
+hipError_t launch_extract_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                            hipStream_t st) {
     const size_t lds = (size_t)((kTY - 1) * ix.s + ix.p) * ((kTX - 1) * ix.s + ix.p) * ix.C;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), grid, dim3(kTX * kTY), lds, st, ix, fa,
-                       patches, qc);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), dim3((unsigned)fb.ntiles),
+                       dim3(kTX * kTY), lds, st, ix, fb, w);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_extract(const DevIndex &ix, const FrameArgs &fa, uint8_t *patches, int32_t *qc,
+hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                           hipStream_t st) {
     switch (ix.Dp) {
-    case 32: return launch_extract_t<32>(ix, fa, patches, qc, st);
-    case 64: return launch_extract_t<64>(ix, fa, patches, qc, st);
-    case 96: return launch_extract_t<96>(ix, fa, patches, qc, st);
-    case 128: return launch_extract_t<128>(ix, fa, patches, qc, st);
-    case 160: return launch_extract_t<160>(ix, fa, patches, qc, st);
-    case 192: return launch_extract_t<192>(ix, fa, patches, qc, st);
-    case 224: return launch_extract_t<224>(ix, fa, patches, qc, st);
-    case 256: return launch_extract_t<256>(ix, fa, patches, qc, st);
+    case 32: return launch_extract_t<32>(ix, fb, w, st);
+    case 64: return launch_extract_t<64>(ix, fb, w, st);
+    case 96: return launch_extract_t<96>(ix, fb, w, st);
+    case 128: return launch_extract_t<128>(ix, fb, w, st);
+    case 160: return launch_extract_t<160>(ix, fb, w, st);
+    case 192: return launch_extract_t<192>(ix, fb, w, st);
+    case 224: return launch_extract_t<224>(ix, fb, w, st);
+    case 256: return launch_extract_t<256>(ix, fb, w, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -146,8 +146,7 @@ constexpr int kRingBlock = 1024;
 constexpr int kRingWaves = kRingBlock / 64;
 
 template <int DP>
-__global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
-                                                      const int32_t *__restrict__ prev, Work w,
+__global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb, Work w,
                                                       unsigned long long *__restrict__ stats,
                                                       int64_t threshold) {
     extern __shared__ uint32_t s_samp[];
@@ -158,13 +157,17 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
     for (int i = threadIdx.x; i < nsamp; i += kRingBlock) s_samp[i] = ix.Ts[i];
     __syncthreads();
 
-    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
+    const int64_t Q = fb.Q;
     const uint32_t n = (uint32_t)ix.n;
     const int nlines = ix.n16 / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t qid = (int64_t)blockIdx.x * kRingBlock + threadIdx.x;
     const bool valid = qid < Q;
     const int64_t qq = valid ? qid : Q - 1;
+    const FrameDesc *fdp = &fb.f[w.fid[qq]];
+    const bool full = fdp->mode == kModeFull;
+    const int32_t *prev = full ? nullptr : fdp->prev;
+    const int64_t ql = qq - fdp->qbase;
     uint32_t a[DP / 4];
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + qq * DP);
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
         }
     }
     const int Qc = w.qc[qq];
-    const int32_t pv = prev ? prev[qq] : -1;
+    const int32_t pv = prev ? prev[ql] : -1;
     const bool noprior = pv < 0 || (int64_t)pv >= ix.n;
     uint32_t c = 0xFFFFFFFFu;
     if (!noprior) {
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
         c = (uint32_t)(Qc + ix.Rc[pv] + 2 * d);
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
-    if (!noprior && ix.K > 0) {
+    if (!full && !noprior && ix.K > 0) {
         uint32_t up = 0xFFFFFFFFu;        // min over evaluated keys of mh
         bool have = false;                // best_m holds an exact size
         for (int k = 0; k < ix.K; ++k) {
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
             if (!have || m < best_m) { best_m = m; best_k = k; best_st = st; best_en = en; have = true; }
         }
     }
-    const bool ring = valid && !noprior && ix.K > 0 && (int64_t)best_m <= threshold;
+    const bool ring = valid && !full && !noprior && ix.K > 0 && (int64_t)best_m <= threshold;
     const bool dense = valid && !ring;
     if (valid) w.rec[qq] = make_uint4(c, best_k, best_st, best_en);
 
@@ -233,8 +236,9 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
     if (dense) w.dense_list[s_base[1] + s_wcnt[wv][1] + lane_prefix(dmask)] = (uint32_t)qq;
 
     // ---- statistics: wave sums, then one atomic per counter per block
-    const unsigned long long v0 = wave_sum_u64(valid ? best_m : 0);
-    const unsigned long long v1 = wave_sum_u64(valid && noprior ? 1 : 0);
+    // full-search frames count as queries and dense queries only
+    const unsigned long long v0 = wave_sum_u64(valid && !full ? best_m : 0);
+    const unsigned long long v1 = wave_sum_u64(valid && !full && noprior ? 1 : 0);
     if (lane == 0) {
         s_st[wv][0] = v0;
         s_st[wv][1] = v1;
@@ -262,9 +266,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameArgs fa,
 // no LDS or barrier is used.  Each candidate's pivot row is read as Kp/4
 // 16-byte loads issued together.
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work w,
-                                                  int32_t *__restrict__ out,
-                                                  uint32_t *__restrict__ ssd,
+__global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameBatch fb, Work w,
                                                   unsigned long long *__restrict__ stats) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t count = w.counters[0];
@@ -324,8 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work
         best = wave_min_u64(best);
         const unsigned long long tot = wave_sum_u64(cnt);
         if (lane == 0) {
-            out[qid] = (int32_t)(uint32_t)best;
-            if (ssd) ssd[qid] = (uint32_t)(best >> 32);
+            const FrameDesc *fdp = &fb.f[w.fid[qid]];
+            const int64_t ql = (int64_t)qid - fdp->qbase;
+            fdp->out[ql] = (int32_t)(uint32_t)best;
+            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
             surv_tot += tot;
             mstar_tot += en - st;
         }
@@ -342,22 +346,20 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameArgs fa, Work
 }
 
 template <int DP>
-hipError_t launch_ring_t(const DevIndex &ix, const FrameArgs &fa, const int32_t *prev,
-                         const Work &w, unsigned long long *stats, int64_t threshold,
-                         hipStream_t st) {
-    const int64_t Q = (int64_t)fa.Hq * fa.Wq;
-    const int64_t blocks = (Q + kRingBlock - 1) / kRingBlock;
+hipError_t launch_ring_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                         unsigned long long *stats, int64_t threshold, hipStream_t st) {
+    const int64_t blocks = (fb.Q + kRingBlock - 1) / kRingBlock;
     const size_t lds = (size_t)ix.K * ix.ns * 4;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP>), dim3((unsigned)blocks), dim3(kRingBlock),
-                       lds, st, ix, fa, prev, w, stats, threshold);
+                       lds, st, ix, fb, w, stats, threshold);
     return hipGetLastError();
 }
 
 template <int DP>
-hipError_t launch_scan_t(const DevIndex &ix, const FrameArgs &fa, const Work &w, int32_t *out,
-                         uint32_t *ssd, unsigned long long *stats, hipStream_t st) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<DP>), dim3(1024), dim3(kBlock), 0, st, ix, fa, w,
-                       out, ssd, stats);
+hipError_t launch_scan_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                         unsigned long long *stats, hipStream_t st) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<DP>), dim3(1024), dim3(kBlock), 0, st, ix, fb, w,
+                       stats);
     return hipGetLastError();
 }
 
@@ -381,17 +383,16 @@ hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
     default: return hipErrorInvalidValue;          \
     }
 
-hipError_t launch_ring(const DevIndex &ix, const FrameArgs &fa, const int32_t *prev,
-                       const Work &w, unsigned long long *stats, int64_t threshold,
-                       hipStream_t st) {
-#define CALL_RING(D) launch_ring_t<D>(ix, fa, prev, w, stats, threshold, st)
+hipError_t launch_ring(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                       unsigned long long *stats, int64_t threshold, hipStream_t st) {
+#define CALL_RING(D) launch_ring_t<D>(ix, fb, w, stats, threshold, st)
     RIANN_DP_SWITCH(ix.Dp, CALL_RING)
 #undef CALL_RING
 }
 
-hipError_t launch_scan(const DevIndex &ix, const FrameArgs &fa, const Work &w, int32_t *out,
-                       uint32_t *ssd, unsigned long long *stats, hipStream_t st) {
-#define CALL_SCAN(D) launch_scan_t<D>(ix, fa, w, out, ssd, stats, st)
+hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                       unsigned long long *stats, hipStream_t st) {
+#define CALL_SCAN(D) launch_scan_t<D>(ix, fb, w, stats, st)
     RIANN_DP_SWITCH(ix.Dp, CALL_SCAN)
 #undef CALL_SCAN
 }

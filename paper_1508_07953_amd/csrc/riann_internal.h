@@ -52,16 +52,42 @@ struct DevIndex {
     int32_t Kp;           // Piv row stride
 };
 
-struct FrameArgs {
-    const uint8_t *frame;
+// One frame of a launch.  A launch takes up to kMaxBatch frames of any sizes;
+// their queries are numbered globally, frame f owning [qbase, qbase + Hq*Wq).
+constexpr int kMaxBatch = 40;
+constexpr int kModeRing = 0, kModeFull = 1;
+
+struct FrameDesc {
+    const uint8_t *frame;    // H x W x C bytes, rows `pitch` apart
+    const int32_t *prev;     // Hq x Wq previous field or nullptr (ring mode)
+    int32_t *out;            // Hq x Wq
+    uint32_t *ssd;           // Hq x Wq or nullptr
     int64_t pitch;
+    int64_t qbase;           // first global query id
     int32_t H, W, Hq, Wq;
+    int32_t mode;            // kModeRing / kModeFull
+    int32_t tbase;           // first extraction tile of this frame
 };
 
-// per-stream scratch of one frame
+// Passed by value (kernel arguments), so a launch needs no descriptor copy
+// and can be captured in a graph as is.
+struct FrameBatch {
+    int32_t n;               // frames
+    int32_t ntiles;          // extraction tiles over all frames
+    int64_t Q;               // queries over all frames
+    int32_t all_full;        // every frame in full-search mode
+    int32_t pad;
+    FrameDesc f[kMaxBatch];
+};
+
+// extraction tile: 64 x 4 query positions
+constexpr int kExtTX = 64, kExtTY = 4;
+
+// per-stream scratch of one launch
 struct Work {
     uint8_t *patches;    // Q x Dp encoded query patches (a = q ^ 0x7F, zero padded)
     int32_t *qc;         // Q, Qc of each query
+    uint8_t *fid;        // Q, frame of each query within its launch
     uint4 *rec;          // Q records {c, kstar, st, en}
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
@@ -76,18 +102,15 @@ enum StatSlot {
 };
 
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
-hipError_t launch_extract(const DevIndex &ix, const FrameArgs &fa, uint8_t *patches, int32_t *qc,
+hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                           hipStream_t st);
-hipError_t launch_ring(const DevIndex &ix, const FrameArgs &fa, const int32_t *prev,
-                       const Work &w, unsigned long long *stats, int64_t threshold,
-                       hipStream_t st);
-hipError_t launch_scan(const DevIndex &ix, const FrameArgs &fa, const Work &w,
-                       int32_t *out, uint32_t *ssd, unsigned long long *stats,
-                       hipStream_t st);
-// list == nullptr: all Q queries (count_static); otherwise list/count_dev.
-// Reads the query patches written by launch_extract.
-hipError_t launch_dense(const DevIndex &ix, const Work &w, const uint32_t *list,
-                        const uint32_t *count_dev, uint32_t count_static, int32_t *out,
-                        uint32_t *ssd, hipStream_t st);
+hipError_t launch_ring(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                       unsigned long long *stats, int64_t threshold, hipStream_t st);
+hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                       unsigned long long *stats, hipStream_t st);
+// all_full batches: every query (no list); otherwise the dense list and its
+// device-side count.  Reads the query patches written by launch_extract.
+hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                        hipStream_t st);
 
 }  // namespace riann

@@ -325,3 +325,46 @@ def test_hd720_sampled(torch_dev, riann):
         assert np.array_equal(gi, bi) and np.array_equal(gd, bd), f"frame {t}"
         prev = out.clone()
     idx.close()
+
+
+def test_batch_many_uneven_frames(torch_dev, riann):
+    """More frames than one launch holds, mixed sizes and modes, ssd omitted
+    on some: every field equals the oracle's brute force."""
+    torch, dev = torch_dev
+    print_case("batch many uneven")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    rng = np.random.default_rng(21)
+    base = [wl.frame(t) for t in range(4)]
+    items, frames = [], []
+    for i in range(45):
+        h = int(rng.integers(8, 65))
+        w_ = int(rng.integers(8, 65))
+        y0 = int(rng.integers(0, 65 - h))
+        x0 = int(rng.integers(0, 65 - w_))
+        f = np.ascontiguousarray(base[i % 4][y0:y0 + h, x0:x0 + w_])
+        frames.append(f)
+        hq, wq = oracle.field_shape(h, w_, 8, 1)
+        it = dict(frame=to_dev(torch, dev, f),
+                  out=torch.full((hq, wq), -7, dtype=torch.int32, device=dev),
+                  mode=riann.MODE_FULL if i % 5 == 0 else riann.MODE_RING)
+        if i % 3:
+            it["ssd"] = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+        if i % 4:
+            it["prev"] = to_dev(torch, dev, gen.random_field(hq, wq, 1024, rng, no_prior_p=0.2))
+        items.append(it)
+    idx.match_batch(items)
+    torch.cuda.synchronize()
+    for i, (it, f) in enumerate(zip(items, frames)):
+        P = oracle.extract(f, 8, 1)
+        bi, bd = oracle.brute_force(P, wl.ref)
+        assert np.array_equal(host(it["out"]), bi), f"frame {i}"
+        if "ssd" in it:
+            assert np.array_equal(host(it["ssd"]).astype(np.uint32), bd), f"frame {i}"
+    # overlapping outputs of two frames are rejected before any launch
+    o = items[1]["out"]
+    bad = [dict(frame=items[1]["frame"], out=o, mode=riann.MODE_RING),
+           dict(frame=items[1]["frame"], out=o, mode=riann.MODE_RING)]
+    with pytest.raises(riann.RiannError):
+        idx.match_batch(bad)
+    idx.close()
