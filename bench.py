@@ -77,6 +77,71 @@ def cpu_baseline(wl, f0, f1, target_s):
                       f"{elapsed:.2f} s wall, table build excluded"}
 
 
+def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
+    """Serving (continuous batching) vs plain (one frame at a time) on a
+    scaled serving workload: `streams` RGB streams, stream id mod 3 ->
+    640x360 / 1280x720 / 1920x1080, 8x8x3 patches, one shared reference set
+    of 65,536 patches with 32 key points, Poisson arrivals at 30 fps per
+    stream.  Frames are pre-generated and resident in HBM (each stream cycles
+    through `frames_per_stream` distinct frames; every result is exact, so
+    the cycle only changes ring sizes, not correctness)."""
+    import torch
+    import gen
+    import paper_1508_07953_amd as riann
+    from paper_1508_07953_amd import serve
+
+    wl = gen.make_workload("serving")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=3, stride=1)
+    t0 = time.time()
+    frames = []
+    for s in range(streams):
+        H, W = gen.serving_stream_shape(s)
+        v = gen.make_video("serving", stream=s, H=H, W=W, frames=frames_per_stream)
+        frames.append([torch.from_numpy(v.frame(k)).to(dev) for k in range(frames_per_stream)])
+    log_fn(f"serving: generated {streams} x {frames_per_stream} frames in {time.time() - t0:.1f}s")
+
+    def frame_of(s, k):
+        return frames[s][k % frames_per_stream]
+
+    def run(max_batch, inflight, trace, scale):
+        srv = serve.Server(idx, max_batch=max_batch, inflight=inflight)
+        sids = {s: srv.open_stream(*gen.serving_stream_shape(s)) for s in range(streams)}
+        # warm the per-stream scratch and kernels
+        for s in range(streams):
+            srv.submit(sids[s], frame_of(s, 0), full=True)
+        srv.drain()
+        srv.completed.clear()
+        r = serve.replay(srv, trace, frame_of, sids, time_scale=scale)
+        per_res = {}
+        for c in srv.completed:
+            H, W = gen.serving_stream_shape(c.stream)
+            per_res.setdefault(f"{W}x{H}", []).append(c.latency * 1e3)
+        r["p99_ms_by_resolution"] = {k: float(np.percentile(v, 99)) for k, v in per_res.items()}
+        q = sum(idx.field_shape(*gen.serving_stream_shape(s))[0] *
+                idx.field_shape(*gen.serving_stream_shape(s))[1] for s in range(streams))
+        r["patches_per_s"] = r["frames_per_s"] * q / streams
+        return r
+
+    # throughput at saturation: every frame of the trace is there from the start
+    sat_trace = [(0.0, s, k) for k in range(1, 4) for s in range(streams)]
+    plain_sat = run(1, 1, sat_trace, 1.0)
+    serve_sat = run(40, 2, sat_trace, 1.0)
+    # latency at a sustainable rate: lambda * 30 fps per stream with lambda
+    # set to ~70% of the serving capacity measured above
+    cap_fps = serve_sat["frames_per_s"]
+    lam = min(1.0, 0.7 * cap_fps / (30.0 * streams))
+    trace = gen.poisson_trace(streams, 30.0 * lam, seconds)
+    trace = [(t, s, k + 1) for (t, s, k) in trace]
+    plain_lat = run(1, 1, trace, 1.0)
+    serve_lat = run(40, 2, trace, 1.0)
+    idx.close()
+    return {"workload": f"{streams} RGB streams (360p/720p/1080p by id mod 3), 8x8x3 patches, "
+                        "n=65536, K=32, Poisson arrivals",
+            "saturation": {"plain": plain_sat, "serving": serve_sat},
+            "lambda": lam, "offered_fps": 30.0 * lam * streams, "trace_seconds": seconds,
+            "at_lambda": {"plain": plain_lat, "serving": serve_lat}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +151,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-vs-plain comparison")
+    ap.add_argument("--serving-streams", type=int, default=12)
+    ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="after the timed region, run one plain device copy of this many "
                          "MiB (reference point for hardware byte counters)")
@@ -183,6 +252,9 @@ def main():
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
                                           for k, v in prof.items() if v["launches"]}
+    if not args.no_serving:
+        result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
+                                                     args.serving_seconds, log)
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
         src = torch.ones(nb, dtype=torch.uint8, device=dev)

@@ -1,0 +1,270 @@
+"""Continuous batching of many live video streams over one index.
+
+The paper's setting is a live stream of frames matched in real time against a
+fixed reference set (Sec. 1, Fig. 1); frame t of a stream needs frame t-1's
+field as its previous match (Algorithm 1).  A `Server` keeps every stream's
+previous field resident on the device, admits streams while their device
+memory fits a budget, and forms batches from whatever frames are ready --
+at most one frame per stream in flight, since frame t+1 depends on frame t's
+field.  Each batch is one `riann_match_batch` submission on one of several HIP
+streams, so batches formed while others run overlap on the device.  Every
+result is exact, so a stream's fields are the same alone and in any mix.
+
+`Server(..., max_batch=1, inflight=1)` is the plain mode: one frame at a time,
+each finished before the next starts.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Deque, Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import MODE_FULL, MODE_RING, Index, RiannError, footprint
+
+
+@dataclasses.dataclass
+class Completion:
+    stream: int
+    seq: int            # frame number within the stream
+    arrival: float      # host time the frame was submitted (s)
+    done: float         # host time its completion was observed (s)
+    field: object       # device (Hq, Wq) int32 tensor holding the field (valid
+                        # until the stream's frame after next is launched)
+    ssd: object
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Stream:
+    def __init__(self, sid, H, W, hq, wq, device, torch):
+        self.sid, self.H, self.W = sid, H, W
+        self.fields = [torch.full((hq, wq), -1, dtype=torch.int32, device=device)
+                       for _ in range(2)]
+        self.ssd = [torch.empty((hq, wq), dtype=torch.int32, device=device) for _ in range(2)]
+        self.cur = 0            # fields[cur] holds the latest finished field
+        self.has_field = False
+        self.seq = 0
+        self.queue: Deque[Tuple[object, float, bool]] = collections.deque()
+        self.busy = False
+        self.closing = False
+
+
+class Server:
+    """Continuous-batching front end of an `Index` (see the module doc)."""
+
+    def __init__(self, index: Index, max_batch: int = 40, inflight: int = 2,
+                 memory_budget: Optional[int] = None, device=None):
+        import torch
+        self.torch = torch
+        self.index = index
+        self.max_batch = max(1, int(max_batch))
+        self.device = device if device is not None else torch.device("cuda")
+        self.hip_streams = [torch.cuda.Stream(device=self.device)
+                            for _ in range(max(1, int(inflight)))]
+        self.budget = memory_budget
+        self.used = footprint(index.params.n_ref, index.params.n_keys, index.params.patch,
+                              index.params.channels, index.params.stride)
+        self.streams: Dict[int, _Stream] = {}
+        self.waiting: Deque[Tuple[int, int, int]] = collections.deque()  # (sid, H, W)
+        self._pending_queues: Dict[int, Deque] = {}   # frames of waiting streams
+        self._next_sid = 0
+        self._batches: List[Tuple[object, int, List[Tuple[int, int, float, int]]]] = []
+        self.completed: List[Completion] = []
+
+    # ------------------------------------------------------------ admission
+    def stream_bytes(self, H: int, W: int) -> int:
+        """Device bytes a stream holds: two fields, two distance maps."""
+        hq, wq = self.index.field_shape(H, W)
+        return 4 * 4 * hq * wq
+
+    def open_stream(self, H: int, W: int) -> int:
+        """Returns a stream id.  The stream is active at once if its memory
+        fits the budget, otherwise it waits for memory (frames can be
+        submitted meanwhile; they queue)."""
+        sid = self._next_sid
+        self._next_sid += 1
+        if self._fits(H, W):
+            self._activate(sid, H, W)
+        else:
+            self.waiting.append((sid, H, W))
+            self._pending_queues[sid] = collections.deque()
+        return sid
+
+    def _fits(self, H, W) -> bool:
+        if self.budget is None:
+            return True
+        scratch = footprint(self.index.params.n_ref, self.index.params.n_keys,
+                            self.index.params.patch, self.index.params.channels,
+                            self.index.params.stride, H, W)
+        return self.used + self.stream_bytes(H, W) + scratch <= self.budget
+
+    def _activate(self, sid, H, W):
+        hq, wq = self.index.field_shape(H, W)
+        st = _Stream(sid, H, W, hq, wq, self.device, self.torch)
+        pq = self._pending_queues.pop(sid, None)
+        if pq:
+            st.queue.extend(pq)
+        self.streams[sid] = st
+        self.used += self.stream_bytes(H, W)
+
+    def close_stream(self, sid: int) -> None:
+        """Frees the stream once its in-flight frame (if any) has finished."""
+        st = self.streams.get(sid)
+        if st is None:
+            self.waiting = collections.deque(w for w in self.waiting if w[0] != sid)
+            self._pending_queues.pop(sid, None)
+            return
+        st.closing = True
+        st.queue.clear()
+        if not st.busy:
+            self._free(sid)
+
+    def _free(self, sid):
+        st = self.streams.pop(sid)
+        self.used -= self.stream_bytes(st.H, st.W)
+        while self.waiting and self._fits(self.waiting[0][1], self.waiting[0][2]):
+            w = self.waiting.popleft()
+            self._activate(*w)
+
+    @property
+    def active_streams(self) -> int:
+        return len(self.streams)
+
+    # ------------------------------------------------------------ frames
+    def submit(self, sid: int, frame, arrival: Optional[float] = None,
+               full: bool = False) -> None:
+        """Queue one device frame (H, W, C) uint8 of stream `sid`.  `full`
+        asks for the exhaustive search (first frame, scene cut)."""
+        t = time.perf_counter() if arrival is None else arrival
+        st = self.streams.get(sid)
+        if st is None:
+            pq = self._pending_queues
+            if sid not in pq:
+                raise KeyError(f"unknown stream {sid}")
+            pq[sid].append((frame, t, full))
+            return
+        if st.closing:
+            raise RiannError(-1, f"stream {sid} is closing")
+        st.queue.append((frame, t, full))
+
+    def pending(self) -> int:
+        n = sum(len(s.queue) for s in self.streams.values())
+        n += sum(len(q) for q in self._pending_queues.values())
+        return n + sum(len(b[2]) for b in self._batches)
+
+    def _launch(self) -> bool:
+        if len(self._batches) >= len(self.hip_streams):
+            return False
+        ready = [s for s in self.streams.values() if not s.busy and s.queue]
+        if not ready:
+            return False
+        ready.sort(key=lambda s: s.queue[0][1])          # oldest arrival first
+        ready = ready[:self.max_batch]
+        in_use = {id(b[1]) for b in self._batches}
+        hs = next(x for x in self.hip_streams if id(x) not in in_use)
+        items, meta = [], []
+        for s in ready:
+            frame, t_arr, full = s.queue.popleft()
+            nxt = 1 - s.cur
+            mode = MODE_FULL if (full or not s.has_field) else MODE_RING
+            it = dict(frame=frame, out=s.fields[nxt], ssd=s.ssd[nxt], mode=mode)
+            if mode == MODE_RING:
+                it["prev"] = s.fields[s.cur]
+            items.append(it)
+            meta.append((s.sid, s.seq, t_arr, nxt))
+            s.seq += 1
+            s.busy = True
+        # the frames were produced on the current stream; order the batch after them
+        hs.wait_stream(self.torch.cuda.current_stream(self.device))
+        self.index.match_batch(items, stream=hs)
+        ev = self.torch.cuda.Event()
+        ev.record(hs)
+        self._batches.append((ev, hs, meta))
+        return True
+
+    def _collect(self, block: bool = False) -> int:
+        done = 0
+        keep = []
+        for ev, hs, meta in self._batches:
+            if block and not keep:
+                ev.synchronize()
+            if ev.query():
+                t = time.perf_counter()
+                for sid, seq, t_arr, nxt in meta:
+                    st = self.streams[sid]
+                    st.cur = nxt
+                    st.has_field = True
+                    st.busy = False
+                    self.completed.append(Completion(sid, seq, t_arr, t, st.fields[nxt],
+                                                     st.ssd[nxt]))
+                    if st.closing:
+                        self._free(sid)
+                done += 1
+            else:
+                keep.append((ev, hs, meta))
+        self._batches = keep
+        return done
+
+    def step(self, block: bool = False) -> int:
+        """Collect finished batches, then launch as many batches as there are
+        free HIP streams.  Returns the number of batches launched."""
+        self._collect(block=block and len(self._batches) >= len(self.hip_streams))
+        n = 0
+        while self._launch():
+            n += 1
+        return n
+
+    def drain(self) -> None:
+        while self.pending():
+            if not self.step():
+                self._collect(block=True)
+
+
+def replay(server: Server, trace: List[Tuple[float, int, int]], frame_of: Callable,
+           stream_ids: Dict[int, int], time_scale: float = 1.0,
+           on_done: Optional[Callable[[Completion], None]] = None,
+           full_of: Optional[Callable[[int, int], bool]] = None) -> Dict[str, float]:
+    """Replays an arrival trace [(t, stream, frame_index)] in real time
+    (t / time_scale seconds after start), submitting frame_of(stream, k) to
+    `server` as it arrives.  Returns throughput and latency figures."""
+    torch = server.torch
+    trace = sorted(trace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    n_done0 = len(server.completed)
+    while i < len(trace) or server.pending():
+        now = time.perf_counter() - t0
+        while i < len(trace) and trace[i][0] / time_scale <= now:
+            t_arr, s, k = trace[i]
+            full = full_of(s, k) if full_of else False
+            server.submit(stream_ids[s], frame_of(s, k), arrival=t0 + t_arr / time_scale,
+                          full=full)
+            i += 1
+        launched = server.step()
+        if on_done is not None:
+            for c in server.completed[n_done0:]:
+                on_done(c)
+            n_done0 = len(server.completed)
+        if not launched and i < len(trace):
+            nxt = trace[i][0] / time_scale - (time.perf_counter() - t0)
+            if nxt > 0 and not server._batches:
+                time.sleep(min(nxt, 0.002))
+        elif not launched and server._batches:
+            server._collect(block=False)
+    torch.cuda.synchronize()
+    server._collect(block=False)
+    if on_done is not None:
+        for c in server.completed[n_done0:]:
+            on_done(c)
+    t1 = time.perf_counter()
+    lat = np.array([c.latency for c in server.completed]) * 1e3
+    return {"frames": len(server.completed), "wall_s": t1 - t0,
+            "frames_per_s": len(server.completed) / (t1 - t0),
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else 0.0,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else 0.0}

@@ -1,0 +1,120 @@
+"""GPU tests of the continuous-batching server: each stream's fields are the
+same alone and in the mix (exact, tolerance 0), admission by memory budget,
+closing a stream while a frame is in flight."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1508_07953_amd as riann
+    from paper_1508_07953_amd import serve
+    assert torch.cuda.is_available()
+    return torch, riann, serve, torch.device("cuda:0")
+
+
+def _streams(rng, n):
+    """n small RGB streams of different sizes, 4 frames each."""
+    out = []
+    for i in range(n):
+        H = int(rng.integers(24, 70))
+        W = int(rng.integers(24, 90))
+        v = gen.DriftVideo(4, H, W, 3, 4, speed=0.5, stream=100 + i)
+        out.append([v.frame(t) for t in range(4)])
+    return out
+
+
+def _ref_rgb(rng, n=700, K=12):
+    tex = np.clip(np.rint(gen.texture(rng, 60, 80, 3)), 0, 255).astype(np.uint8)
+    ref = gen.reference_from_frame(tex, n, 8, 1, rng)
+    return ref, gen.choose_keys(n, K, rng)
+
+
+def test_alone_equals_mix(env):
+    torch, riann, serve, dev = env
+    print("[gpu case] serving alone vs mix", flush=True)
+    rng = np.random.default_rng(31)
+    ref, keys = _ref_rgb(rng)
+    idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
+    vids = _streams(rng, 7)
+    dframes = [[torch.from_numpy(f).to(dev) for f in v] for v in vids]
+    # alone: plain per-frame calls, one stream after another
+    alone = []
+    for v in dframes:
+        fields, prev = [], None
+        for t, f in enumerate(v):
+            if prev is None:
+                o, s = idx.full_search(f)
+            else:
+                o, s = idx.match_frame(f, prev=prev)
+            torch.cuda.synchronize()
+            fields.append((o.cpu().numpy().copy(), s.cpu().numpy().copy()))
+            prev = o
+        alone.append(fields)
+    # mix: all streams through the server, frames submitted interleaved
+    # batches of at most 3 frames, two batches in flight at once
+    srv = serve.Server(idx, max_batch=3, inflight=2)
+    sids = [srv.open_stream(v[0].shape[0], v[0].shape[1]) for v in vids]
+    got = {}
+    for t in range(4):
+        n0 = len(srv.completed)
+        for si, v in zip(sids, dframes):
+            srv.submit(si, v[t])
+        srv.drain()
+        for c in srv.completed[n0:]:
+            got[(c.stream, c.seq)] = (c.field.cpu().numpy().copy(), c.ssd.cpu().numpy().copy())
+    for k, si in enumerate(sids):
+        for t in range(4):
+            o, s = got[(si, t)]
+            assert np.array_equal(o, alone[k][t][0]), (k, t)
+            assert np.array_equal(s, alone[k][t][1]), (k, t)
+    # and the fields are the exact NN
+    for k in (0, 3):
+        for t in (0, 2):
+            bi, bd = oracle.brute_force(oracle.extract(vids[k][t], 8, 1), ref)
+            assert np.array_equal(got[(sids[k], t)][0].reshape(-1), bi)
+    idx.close()
+
+
+def test_admission_and_close(env):
+    torch, riann, serve, dev = env
+    print("[gpu case] serving admission", flush=True)
+    rng = np.random.default_rng(32)
+    ref, keys = _ref_rgb(rng, n=300, K=6)
+    idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
+    vids = []
+    for i in range(4):
+        v = gen.DriftVideo(4, 40, 56, 3, 2, speed=0.5, stream=200 + i)
+        vids.append([v.frame(t) for t in range(2)])
+    dframes = [[torch.from_numpy(f).to(dev) for f in v] for v in vids]
+    probe = serve.Server(idx)
+    one = probe.stream_bytes(40, 56)
+    scratch = riann.footprint(300, 6, 8, 3, 1, 40, 56)
+    srv = serve.Server(idx, memory_budget=probe.used + 2 * one + scratch)
+    sids = [srv.open_stream(40, 56) for _ in vids]
+    assert srv.active_streams == 2 and len(srv.waiting) == 2
+    for si, v in zip(sids, dframes):
+        srv.submit(si, v[0])
+        srv.submit(si, v[1])
+    srv.step()                      # frame 0 of streams 0 and 1 in flight
+    srv.close_stream(sids[0])       # freed once its frame finishes; frame 1 dropped
+    for _ in range(1000):
+        srv.step()
+        srv._collect(block=bool(srv._batches))
+        s1 = srv.streams.get(sids[1])
+        if s1 is not None and not s1.busy and not s1.queue:
+            srv.close_stream(sids[1])
+        if srv.pending() == 0:
+            break
+    done = {(c.stream, c.seq) for c in srv.completed}
+    assert (sids[0], 0) in done and (sids[0], 1) not in done
+    for si in sids[1:]:
+        assert (si, 0) in done and (si, 1) in done, si
+    assert srv.active_streams <= 2
+    idx.close()
