@@ -26,6 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "query patches/sec and frames/sec at 720p + p99 frame latency (serving vs plain)"
+WORKLOAD_DESC = {
+    "hd720": "hd720: 1280x720 gray, 8x8 patches stride 1, %d queries/frame, n=16384 reference "
+             "patches, K=16 key points, tiled affine motion, 10%% tiles re-seeded per frame",
+    "fhd_rgb": "fhd_rgb: 1920x1080 RGB, 8x8x3 patches stride 1, %d queries/frame, n=65536, "
+               "K=32, drifting texture, full search at scene cuts",
+    "uhd_mix": "uhd_mix: 3840x2160 gray, 12x12 patches stride 2, %d queries/frame, n=262144, "
+               "K=48, 20%% high-motion tiles, full search at scene cuts",
+}
 INT8_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix peak, tera-ops/s
 HBM_PEAK_GBS = 8000.0
 
@@ -34,10 +42,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def dense_traffic_bytes():
+def dense_traffic_bytes(workload):
     """HBM bytes per k_dense dispatch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
     import hashlib
+    if workload != "hd720":
+        return None
     try:
         with open(os.path.join(ROOT, "profiles", "hd720_k_dense_traffic.json")) as f:
             rec = json.load(f)
@@ -151,6 +161,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
+    ap.add_argument("--workload", default="hd720", choices=["hd720", "fhd_rgb", "uhd_mix"],
+                    help="per-frame workload of the timed loop (hd720 is the headline)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-vs-plain comparison")
     ap.add_argument("--serving-streams", type=int, default=12)
@@ -173,7 +185,7 @@ def main():
     K, W = args.steps, args.warmup
     nframes = W + K + 1
     t0 = time.time()
-    wl = gen.make_workload("hd720", frames=max(nframes, 60))
+    wl = gen.make_workload(args.workload, frames=max(nframes, 60))
     frames_h = [wl.frame(t) for t in range(nframes)]
     log(f"generated {nframes} frames in {time.time() - t0:.1f}s")
     frames = [torch.from_numpy(f).to(dev) for f in frames_h]
@@ -188,8 +200,14 @@ def main():
 
     idx.full_search(frames[0], out=bufs[0], ssd=ssd)
     cur = 0
+    def step(t):
+        if wl.is_cut(t):
+            idx.full_search(frames[t], out=bufs[1 - cur], ssd=ssd)
+        else:
+            idx.match_frame(frames[t], prev=bufs[cur], out=bufs[1 - cur], ssd=ssd)
+
     for t in range(1, W + 1):
-        idx.match_frame(frames[t], prev=bufs[cur], out=bufs[1 - cur], ssd=ssd)
+        step(t)
         cur = 1 - cur
     torch.cuda.synchronize()
     idx.reset_stats()
@@ -202,7 +220,7 @@ def main():
     for i in range(K):
         t = W + 1 + i
         evs[i][0].record(stream)
-        idx.match_frame(frames[t], prev=bufs[cur], out=bufs[1 - cur], ssd=ssd)
+        step(t)
         evs[i][1].record(stream)
         cur = 1 - cur
     torch.cuda.synchronize()
@@ -226,9 +244,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
-        "config": {"workload": "hd720: 1280x720 gray, 8x8 patches stride 1, 907649 "
-                               "queries/frame, n=16384 reference patches, K=16 key points, "
-                               "tiled affine motion, 10% tiles re-seeded per frame",
+        "config": {"workload": WORKLOAD_DESC[args.workload] % Q,
                    "frames_timed": K, "mode": "plain (one frame at a time)"},
         "frames_per_s": K / wall,
         "p50_frame_ms": float(np.percentile(lat, 50)),
@@ -247,7 +263,7 @@ def main():
         result["roofline"] = {"bound": "mfma", "kernel": "k_dense (int8 MFMA, routed queries)",
                               "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                               "frac": achieved / INT8_PEAK_TOPS,
-                              "traffic": dense_traffic_bytes(),
+                              "traffic": dense_traffic_bytes(args.workload),
                               "ms_per_launch": ms_per_launch,
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])

@@ -160,6 +160,10 @@ class TiledVideo:
         span = frames if cut_every is None else min(frames, cut_every)
         vmax = max(slow, fast)
         self.margin = int(np.ceil(vmax * span)) + 4
+        # textures large enough for the whole drift, or (for fast motion over
+        # long shots) a smaller periodic texture sampled with wrap-around
+        self.wrap = self.TILE + 2 * self.margin > 256
+        self.canvas = 128 if self.wrap else self.TILE + 2 * self.margin
         self._state_t = -1
         self._tex: List[np.ndarray] = [None] * nt  # type: ignore
         self._t0 = np.zeros(nt, np.int64)           # frame the texture started
@@ -183,8 +187,13 @@ class TiledVideo:
 
     def _new_texture(self, i: int, key: int) -> None:
         rng = _rng(self.so, P_TEXTURE, (self.stream * 10**7) + key)
-        s = self.TILE + 2 * self.margin
-        self._tex[i] = texture(rng, s, s, 1)[:, :, 0]
+        s = self.canvas
+        if self.wrap:
+            t = rng.uniform(0.0, 255.0, size=(s, s))
+            self._tex[i] = ndimage.gaussian_filter(t, BLUR_SIGMA, mode="wrap",
+                                                   truncate=4.0).astype(np.float32)
+        else:
+            self._tex[i] = texture(rng, s, s, 1)[:, :, 0]
 
     def _advance(self, t: int) -> None:
         """Bring tile state (textures, motions, start frames) up to frame t."""
@@ -221,10 +230,16 @@ class TiledVideo:
                 tl = t - (0 if self.cut_every is None
                           else (t // self.cut_every) * self.cut_every)
                 disp = tl * (rel @ self._A[i].T + self._b[i])
-                cx = self.margin + xx - disp[..., 0]
-                cy = self.margin + yy - disp[..., 1]
-                v = ndimage.map_coordinates(self._tex[i], [cy[:h, :w], cx[:h, :w]],
-                                            order=1, mode="nearest")
+                if self.wrap:
+                    cx = xx - disp[..., 0]
+                    cy = yy - disp[..., 1]
+                    v = ndimage.map_coordinates(self._tex[i], [cy[:h, :w], cx[:h, :w]],
+                                                order=1, mode="grid-wrap")
+                else:
+                    cx = self.margin + xx - disp[..., 0]
+                    cy = self.margin + yy - disp[..., 1]
+                    v = ndimage.map_coordinates(self._tex[i], [cy[:h, :w], cx[:h, :w]],
+                                                order=1, mode="nearest")
                 img[ty * T:ty * T + h, tx * T:tx * T + w] = v
         rng = _rng(self.so, P_NOISE, self.stream * 100000 + t)
         return _finish(img[:, :, None], rng)

@@ -76,45 +76,69 @@ struct DenseState {
     uint32_t gI[SEG ? kQB : 1][16];
     uint32_t segbase;
 
-    // all tiles of one LDS stage; tile t0 = sg * ST is its first
+    // B fragments and key bases of step u (TPS tiles) of an LDS stage
+    __device__ __forceinline__ void load_step(const int8_t *lf, const uint32_t *lr, int u,
+                                              int lane, int col, uint32_t j0, v4i (&B)[TPS][KB],
+                                              uint32_t (&rnj)[TPS]) {
+#pragma unroll
+        for (int v = 0; v < TPS; ++v) {
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                B[v][kb] = *reinterpret_cast<const v4i *>(lf + ((u * TPS + v) * KB + kb) * 1024 +
+                                                          lane * 16);
+            rnj[v] = lr[(u * TPS + v) * kTile + col] | (j0 + v);
+        }
+    }
+
+    __device__ __forceinline__ void mma(int qb, const v4i (&B)[TPS][KB], v16i (&acc)[TPS]) {
+#pragma unroll
+        for (int v = 0; v < TPS; ++v) {
+            acc[v] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                acc[v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[qb][kb], B[v][kb], acc[v], 0, 0,
+                                                               0);
+        }
+    }
+
+    __device__ __forceinline__ void epilogue(int qb, const v16i (&acc)[TPS],
+                                             const uint32_t (&rnj)[TPS], uint32_t ash) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            uint32_t m = best[qb][i];
+#pragma unroll
+            for (int v = 0; v < TPS; ++v) m = min(m, rnj[v] + ((uint32_t)acc[v][i] << ash));
+            best[qb][i] = m;
+        }
+    }
+
+    // All tiles of one LDS stage (tile t0s = sg * ST is its first), software
+    // pipelined across the two query blocks: the MFMAs of block 1 run while
+    // block 0's epilogue executes, and those of block 0 for the next step
+    // while block 1's epilogue executes.
     __device__ __forceinline__ void stage(const int8_t *lf, const uint32_t *lr, uint32_t t0s,
                                           int lane, int col, uint32_t jb, uint32_t ash,
                                           uint32_t seglen, int64_t ntiles) {
-#pragma unroll 1
-        for (int tp = 0; tp < ST; tp += TPS) {
-            const uint32_t t0 = t0s + (uint32_t)tp;
-            const uint32_t j0 = SEG ? (t0 - segbase + 1) : t0;
-            v4i B[TPS][KB];
-            uint32_t rnj[TPS];
+        constexpr int NS = ST / TPS;
+        v4i Bc[TPS][KB], Bn[TPS][KB];
+        uint32_t rc[TPS], rn[TPS];
+        v16i a0[TPS], a1[TPS];
+        uint32_t j0 = SEG ? (t0s - segbase + 1) : t0s;
+        load_step(lf, lr, 0, lane, col, j0, Bc, rc);
+        mma(0, Bc, a0);
 #pragma unroll
-            for (int u = 0; u < TPS; ++u) {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb)
-                    B[u][kb] = *reinterpret_cast<const v4i *>(lf + ((tp + u) * KB + kb) * 1024 +
-                                                              lane * 16);
-                rnj[u] = lr[(tp + u) * kTile + col] | (j0 + u);
+        for (int u = 0; u < NS; ++u) {
+            const uint32_t t0 = t0s + (uint32_t)(u * TPS);
+            mma(1, Bc, a1);
+            epilogue(0, a0, rc, ash);
+            const bool seg_end = SEG && (j0 + TPS - 1 == seglen || (int64_t)t0 + TPS == ntiles);
+            const uint32_t jn = seg_end ? 1u : j0 + TPS;
+            if (u + 1 < NS) {
+                load_step(lf, lr, u + 1, lane, col, SEG ? jn : t0 + TPS, Bn, rn);
+                mma(0, Bn, a0);
             }
-#pragma unroll
-            for (int qb = 0; qb < kQB; ++qb) {
-                v16i acc[TPS];
-#pragma unroll
-                for (int u = 0; u < TPS; ++u) {
-                    acc[u] = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb)
-                        acc[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[qb][kb], B[u][kb],
-                                                                       acc[u], 0, 0, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    uint32_t m = best[qb][i];
-#pragma unroll
-                    for (int u = 0; u < TPS; ++u)
-                        m = min(m, rnj[u] + ((uint32_t)acc[u][i] << ash));
-                    best[qb][i] = m;
-                }
-            }
-            if (SEG && (j0 + TPS - 1 == seglen || (int64_t)t0 + TPS == ntiles)) {
+            epilogue(1, a1, rc, ash);
+            if (seg_end) {
                 const uint32_t jm = (1u << jb) - 1;
 #pragma unroll
                 for (int qb = 0; qb < (SEG ? kQB : 1); ++qb)
@@ -127,6 +151,15 @@ struct DenseState {
                         }
                     }
                 segbase = t0 + TPS;
+            }
+            if (u + 1 < NS) {
+#pragma unroll
+                for (int v = 0; v < TPS; ++v) {
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb) Bc[v][kb] = Bn[v][kb];
+                    rc[v] = rn[v];
+                }
+                j0 = SEG ? jn : t0 + TPS;
             }
         }
     }

@@ -6,8 +6,9 @@ field as its previous match (Algorithm 1).  A `Server` keeps every stream's
 previous field resident on the device, admits streams while their device
 memory fits a budget, and forms batches from whatever frames are ready --
 at most one frame per stream in flight, since frame t+1 depends on frame t's
-field.  Each batch is one `riann_match_batch` submission on one of several HIP
-streams, so batches formed while others run overlap on the device.  Every
+field.  Each batch is one `riann_match_batch` submission; batches formed while
+others run are queued behind them on the device (or, with concurrent=True,
+run side by side on separate HIP streams).  Every
 result is exact, so a stream's fields are the same alone and in any mix.
 
 `Server(..., max_batch=1, inflight=1)` is the plain mode: one frame at a time,
@@ -58,14 +59,25 @@ class Server:
     """Continuous-batching front end of an `Index` (see the module doc)."""
 
     def __init__(self, index: Index, max_batch: int = 40, inflight: int = 2,
-                 memory_budget: Optional[int] = None, device=None):
+                 memory_budget: Optional[int] = None, device=None,
+                 max_batch_queries: Optional[int] = 1_000_000, concurrent: bool = False):
         import torch
         self.torch = torch
         self.index = index
         self.max_batch = max(1, int(max_batch))
+        self.inflight = max(1, int(inflight))
+        # concurrent=False: batches queue back to back on one HIP stream (no
+        # idle gap between them, no sharing slowdown); True: each in-flight
+        # batch gets its own HIP stream and they run side by side
+        self.concurrent = concurrent
+        # a batch completes as a whole, so its size bounds the latency of the
+        # small frames in it: stop adding frames once it holds this many
+        # queries (a lone larger frame still goes alone).  About one 720p
+        # frame fills the GPU; frames that large gain nothing from batching.
+        self.max_batch_queries = max_batch_queries
         self.device = device if device is not None else torch.device("cuda")
         self.hip_streams = [torch.cuda.Stream(device=self.device)
-                            for _ in range(max(1, int(inflight)))]
+                            for _ in range(self.inflight if concurrent else 1)]
         self.budget = memory_budget
         self.used = footprint(index.params.n_ref, index.params.n_keys, index.params.patch,
                               index.params.channels, index.params.stride)
@@ -158,15 +170,27 @@ class Server:
         return n + sum(len(b[2]) for b in self._batches)
 
     def _launch(self) -> bool:
-        if len(self._batches) >= len(self.hip_streams):
+        if len(self._batches) >= self.inflight:
             return False
         ready = [s for s in self.streams.values() if not s.busy and s.queue]
         if not ready:
             return False
         ready.sort(key=lambda s: s.queue[0][1])          # oldest arrival first
-        ready = ready[:self.max_batch]
-        in_use = {id(b[1]) for b in self._batches}
-        hs = next(x for x in self.hip_streams if id(x) not in in_use)
+        picked, q = [], 0
+        for s in ready:
+            hq, wq = self.index.field_shape(s.H, s.W)
+            if picked and (len(picked) >= self.max_batch or
+                           (self.max_batch_queries is not None and
+                            q + hq * wq > self.max_batch_queries)):
+                break
+            picked.append(s)
+            q += hq * wq
+        ready = picked
+        if self.concurrent:
+            in_use = {id(b[1]) for b in self._batches}
+            hs = next(x for x in self.hip_streams if id(x) not in in_use)
+        else:
+            hs = self.hip_streams[0]
         items, meta = [], []
         for s in ready:
             frame, t_arr, full = s.queue.popleft()
@@ -213,7 +237,7 @@ class Server:
     def step(self, block: bool = False) -> int:
         """Collect finished batches, then launch as many batches as there are
         free HIP streams.  Returns the number of batches launched."""
-        self._collect(block=block and len(self._batches) >= len(self.hip_streams))
+        self._collect(block=block and len(self._batches) >= self.inflight)
         n = 0
         while self._launch():
             n += 1

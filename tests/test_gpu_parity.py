@@ -368,3 +368,37 @@ def test_batch_many_uneven_frames(torch_dev, riann):
     with pytest.raises(riann.RiannError):
         idx.match_batch(bad)
     idx.close()
+
+
+@pytest.mark.parametrize("name,nsamp", [("fhd_rgb", 1500), ("uhd_mix", 800)])
+def test_large_workloads_sampled(torch_dev, riann, name, nsamp):
+    """1080p RGB (D=192, n=65,536) and 4K 12x12 stride-2 (D=144, n=262,144):
+    frame 0 full search and frame 1 ring search at full size, with the
+    launch configuration the benchmark uses; sampled queries vs brute force,
+    plus every query of the first and last rows of the field."""
+    torch, dev = torch_dev
+    print_case(f"{name} sampled")
+    wl = gen.make_workload(name, frames=2)
+    idx = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
+                            stride=wl.stride)
+    rng = np.random.default_rng(13)
+    prev = None
+    for t in range(2):
+        f = wl.frame(t)
+        fd = to_dev(torch, dev, f)
+        if prev is None:
+            out, ssd = idx.full_search(fd)
+        else:
+            out, ssd = idx.match_frame(fd, prev=prev)
+        torch.cuda.synchronize()
+        hq, wq = idx.field_shape(f.shape[0], f.shape[1])
+        sel = np.sort(rng.choice(hq * wq, nsamp, replace=False))
+        sel = np.unique(np.concatenate([sel, np.arange(min(wq, 200)),
+                                        hq * wq - 1 - np.arange(min(wq, 200))]))
+        ys, xs = (sel // wq) * wl.stride, (sel % wq) * wl.stride
+        P = gen.patches_at(f, ys, xs, wl.patch)
+        bi, bd = oracle.brute_force(P, wl.ref)
+        gi, gd = host(out)[sel], host(ssd)[sel].astype(np.uint32)
+        assert np.array_equal(gi, bi) and np.array_equal(gd, bd), f"{name} frame {t}"
+        prev = out.clone()
+    idx.close()
