@@ -163,6 +163,11 @@ def main():
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--workload", default="hd720", choices=["hd720", "fhd_rgb", "uhd_mix"],
                     help="per-frame workload of the timed loop (hd720 is the headline)")
+    ap.add_argument("--dense-layout", default="column", choices=["column", "rows"],
+                    help="column: queries as MFMA rows (default); rows: references as "
+                         "MFMA rows, where the patch allows it")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default routing threshold")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-vs-plain comparison")
     ap.add_argument("--serving-streams", type=int, default=12)
@@ -191,7 +196,8 @@ def main():
     frames = [torch.from_numpy(f).to(dev) for f in frames_h]
     H, Wd = frames_h[0].shape[:2]
     idx = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
-                            stride=wl.stride)
+                            stride=wl.stride,
+                            flags=riann.FLAG_ROW_DENSE if args.dense_layout == "rows" else 0)
     hq, wq = idx.field_shape(H, Wd)
     Q = hq * wq
     bufs = [torch.empty((hq, wq), dtype=torch.int32, device=dev) for _ in range(2)]
@@ -210,6 +216,23 @@ def main():
         step(t)
         cur = 1 - cur
     torch.cuda.synchronize()
+    tuned = None
+    if not args.no_tune:
+        # routing threshold picked by measurement on the warm-up frames (set-up,
+        # outside the timed region); frames 1.. with the fields before them
+        from paper_1508_07953_amd import tune
+        fr, pv = [], []
+        f_prev = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+        idx.full_search(frames[0], out=f_prev)
+        for t in range(1, min(W, 3) + 1):
+            o = torch.empty_like(f_prev)
+            idx.match_frame(frames[t], prev=f_prev, out=o)
+            fr.append(frames[t])
+            pv.append(f_prev)
+            f_prev = o
+        tuned = tune.tune_threshold(idx, fr, pv, use_cache=False, write_cache=False)
+        log(f"tuned dense threshold {tuned['threshold']}: {tuned['ms']}")
+        torch.cuda.synchronize()
     idx.reset_stats()
     if not args.no_profile:
         idx.set_profiling(True)
@@ -245,19 +268,22 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC[args.workload] % Q,
-                   "frames_timed": K, "mode": "plain (one frame at a time)"},
+                   "frames_timed": K, "mode": "plain (one frame at a time)",
+                   "dense_layout": args.dense_layout},
         "frames_per_s": K / wall,
         "p50_frame_ms": float(np.percentile(lat, 50)),
         "p99_frame_ms": float(np.percentile(lat, 99)),
         "routing": {"ring_queries": st["ring_queries"], "dense_queries": st["dense_queries"],
                     "mean_mstar": st["sum_mstar"] / max(1, st["queries"]),
-                    "dense_threshold": int(idx.params.dense_threshold)},
+                    "dense_threshold": int(idx.params.dense_threshold),
+                    "autotune_ms_per_frame": tuned["ms"] if tuned else None},
     }
     if prof is not None:
         n, D = int(idx.params.n_ref), wl.D
-        d = prof["dense"]
-        dense_q_per_launch = st["dense_queries"] / max(1, d["launches"])
-        ms_per_launch = d["ms"] / max(1, d["launches"])
+        # the dense search runs on routed queries and on whole cut frames
+        launches = prof["dense"]["launches"] + prof["full"]["launches"]
+        dense_q_per_launch = st["dense_queries"] / max(1, launches)
+        ms_per_launch = (prof["dense"]["ms"] + prof["full"]["ms"]) / max(1, launches)
         ops = 2.0 * dense_q_per_launch * n * D
         achieved = ops / (ms_per_launch * 1e-3) / 1e12
         result["roofline"] = {"bound": "mfma", "kernel": "k_dense (int8 MFMA, routed queries)",

@@ -71,9 +71,16 @@ typedef struct riann_params {
     int64_t dense_threshold;   /* queries whose smallest ring holds more than
                                   this many candidates use the dense search;
                                   < 0 selects the library default             */
-    uint32_t flags;            /* reserved, must be 0                          */
+    uint32_t flags;            /* RIANN_FLAG_* bits, else 0                    */
     uint32_t reserved;         /* must be 0                                    */
 } riann_params_t;
+
+/* riann_params_t.flags: answer dense queries with the row-layout search
+ * (references as MFMA rows, queries as columns; patches of at most 96 padded
+ * bytes, else ignored) instead of the default column layout.  Results are
+ * identical; on the 720p workload it is slower, and it is kept for
+ * measurement and as a cross-check of the default kernel. */
+#define RIANN_FLAG_ROW_DENSE 1u
 
 /* One frame of a batch (riann_match_batch). */
 typedef struct riann_frame_desc {
@@ -188,6 +195,14 @@ riann_status_t riann_reset_stats(riann_index_t h);
 /* riann_get_params -- the parameters the index was built with, with the
  * dense threshold resolved to the value in use. */
 riann_status_t riann_get_params(riann_index_t h, riann_params_t *p);
+
+/*
+ * riann_set_dense_threshold -- change the routing threshold (queries whose
+ * smallest ring holds more than `threshold` candidates use the dense search)
+ * for launches issued after the call; threshold >= 0.  Routing never changes
+ * a result, only the time it takes (the autotuner picks this value).
+ */
+riann_status_t riann_set_dense_threshold(riann_index_t h, int64_t threshold);
 
 /*
  * riann_save / riann_load -- write / read the index (reference set, keys and

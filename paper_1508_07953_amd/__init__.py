@@ -29,12 +29,13 @@ LIB_PATH = os.path.join(_PKG, "libriann.so")
 RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, RIANN_E_IO = (
     0, -1, -2, -3, -4, -5)
 MODE_RING, MODE_FULL = 0, 1
+FLAG_ROW_DENSE = 1
 
 # every symbol include/riann.h declares
 EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
-           "riann_set_profiling", "riann_get_profile"]
+           "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -87,6 +88,7 @@ def _load():
     L.riann_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
     L.riann_destroy.argtypes = [vp]
     L.riann_set_profiling.argtypes = [vp, C.c_int]
+    L.riann_set_dense_threshold.argtypes = [vp, i64]
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
     L.riann_last_error.argtypes = []
     L.riann_last_error.restype = C.c_char_p
@@ -122,8 +124,8 @@ def field_shape(H: int, W: int, patch: int, stride: int) -> Tuple[int, int]:
 
 
 def make_params(n_ref: int, n_keys: int, patch: int, channels: int, stride: int,
-                dense_threshold: int = -1) -> Params:
-    return Params(patch, channels, stride, n_keys, n_ref, dense_threshold, 0, 0)
+                dense_threshold: int = -1, flags: int = 0) -> Params:
+    return Params(patch, channels, stride, n_keys, n_ref, dense_threshold, flags, 0)
 
 
 def footprint(n_ref: int, n_keys: int, patch: int, channels: int, stride: int,
@@ -159,12 +161,13 @@ class Index:
     # ---------------------------------------------------------------- build
     @classmethod
     def build(cls, ref: np.ndarray, keys: Sequence[int], patch: int, channels: int = 1,
-              stride: int = 1, dense_threshold: int = -1, stream=None) -> "Index":
+              stride: int = 1, dense_threshold: int = -1, stream=None,
+              flags: int = 0) -> "Index":
         ref = np.ascontiguousarray(ref, dtype=np.uint8)
         keys = np.ascontiguousarray(np.asarray(keys, dtype=np.int32))
         if ref.ndim != 2 or ref.shape[1] != patch * patch * channels:
             raise ValueError("ref must be (n, patch*patch*channels) uint8")
-        p = make_params(ref.shape[0], len(keys), patch, channels, stride, dense_threshold)
+        p = make_params(ref.shape[0], len(keys), patch, channels, stride, dense_threshold, flags)
         h = C.c_void_p()
         _check(_lib.riann_build(ref.ctypes.data, keys.ctypes.data if len(keys) else None,
                                 C.byref(p), _stream_ptr(stream), C.byref(h)))
@@ -257,6 +260,11 @@ class Index:
 
     def reset_stats(self) -> None:
         _check(_lib.riann_reset_stats(self._h))
+
+    def set_dense_threshold(self, threshold: int) -> None:
+        """Routing threshold for later launches (a performance knob only)."""
+        _check(_lib.riann_set_dense_threshold(self._h, int(threshold)))
+        self.params.dense_threshold = int(threshold)
 
     def set_profiling(self, enable: bool) -> None:
         _check(_lib.riann_set_profiling(self._h, 1 if enable else 0))

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libriann.so")
-SOURCES = ["api.hip", "k_extract.hip", "k_ring.hip", "k_dense.hip"]
+SOURCES = ["api.hip", "k_extract.hip", "k_ring.hip", "k_dense.hip", "k_dense_rows.hip"]
 ARCH = os.environ.get("RIANN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -22,7 +22,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 # per-source extras: MFMA results go straight to VGPRs in the dense search,
 # whose epilogue reads every accumulator element
-EXTRA = {"k_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"k_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "k_dense_rows.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:

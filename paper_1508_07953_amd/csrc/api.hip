@@ -21,7 +21,8 @@ struct riann_index {
     riann_params_t prm{};
     int D = 0, Dp = 0, K = 0;
     int64_t n = 0, n_pad = 0;
-    int64_t threshold = 0;
+    std::atomic<int64_t> threshold{0};
+    bool dense_rows = false;  // row-layout dense search (opt-in) where supported
     int device = 0;
     // host copies (kept for riann_save)
     std::vector<uint8_t> ref;
@@ -83,8 +84,8 @@ riann_status_t check_params(const riann_params_t *p) {
     if (p->n_keys < 0 || p->n_keys > kMaxKeys)
         return fail(RIANN_E_INVALID, "n_keys must be in [0, 64]");
     if (p->n_keys > p->n_ref) return fail(RIANN_E_INVALID, "n_keys exceeds n_ref");
-    if (p->flags != 0 || p->reserved != 0)
-        return fail(RIANN_E_INVALID, "flags and reserved must be 0");
+    if ((p->flags & ~RIANN_FLAG_ROW_DENSE) != 0 || p->reserved != 0)
+        return fail(RIANN_E_INVALID, "unknown flags or nonzero reserved field");
     return RIANN_OK;
 }
 
@@ -99,11 +100,11 @@ int64_t index_bytes(int64_t n, int D, int K) {
     const int Dp = (int)round_up(D, 32);
     const int64_t n_pad = round_up(n, kRefAlign);
     const int64_t n16 = round_up(n, 16), Kp = round_up(std::max(K, 1), 4);
-    return 2 * (n_pad * Dp + n_pad * 4) + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
+    return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
            (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 16 + 8) + 8192; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 16 + 12) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -174,6 +175,20 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         Rc[(size_t)r] = s;
         Rk[(size_t)r] = (uint32_t)(s + bias) << jb;
     }
+    // row-layout tables, permuted per tile to the accumulator row order
+    std::vector<int32_t> Hf((size_t)n_pad, 1 << 30);
+    for (int64_t t = 0; t < n_pad / kTile; ++t)
+        for (int g = 0; g < 2; ++g)
+            for (int r = 0; r < 16; ++r) {
+                const int m = 8 * (r / 4) + 4 * g + r % 4;
+                const int64_t ref = t * kTile + m;
+                const size_t o = (size_t)(t * kTile + g * 16 + r);
+                if (ref < n) {
+                    const int64_t rc = Rc[(size_t)ref];
+                    const int64_t p = rc & 1;
+                    Hf[o] = (int32_t)((rc + bias - p) / 2);
+                }
+            }
     const int KB = Dp / 32;
     for (int64_t r = 0; r < n_pad; ++r)
         for (int kb = 0; kb < KB; ++kb)
@@ -202,8 +217,8 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
                  szS = ST_COUNT * 8, szTs = Ts.size() * 4;
     size_t off[11], tot = 0;
-    const size_t sz[10] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs};
-    for (int i = 0; i < 10; ++i) {
+    const size_t sz[11] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szRc};
+    for (int i = 0; i < 11; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -226,6 +241,7 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.jb = jb;
     h->dix.bias = (int32_t)bias;
     h->dix.Ts = (const uint32_t *)(b + off[9]);
+    h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.n16 = (int32_t)n16;
     h->dix.ns = (int32_t)ns;
     h->dix.s0l = (int32_t)s0l;
@@ -245,6 +261,7 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         {b + off[5], h->keys.data(), (size_t)K * 4},
         {b + off[7], Rf.data(), szRv},          {b + off[8], Rk.data(), szRc},
         {b + off[9], Ts.data(), (size_t)K * ns * 4},
+        {b + off[10], Hf.data(), szRc},
     };
     for (auto &c : cp) {
         if (c.n == 0) continue;
@@ -308,6 +325,7 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
+    nw.fb_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.counters = (uint32_t *)(b + o);
     nw.capacity = cap;
     h->work[st] = nw;
@@ -395,7 +413,8 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
     riann_status_t s = get_work(h, st, q, &w);
     if (s != RIANN_OK) return s;
     hipError_t e;
-    if (!all_full) {
+    const bool rows = h->dense_rows && dense_rows_supported(h->dix);
+    if (!all_full || rows) {
         e = launch_zero_u32(w.counters, 4, st);
         if (e != hipSuccess) return hip_fail(e, "counter clear");
     }
@@ -408,7 +427,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
     if (!all_full) {
         {
             KTimer tm(h, RIANN_K_RING, st);
-            e = launch_ring(h->dix, fb, w, h->dstats, h->threshold, st);
+            e = launch_ring(h->dix, fb, w, h->dstats, h->threshold.load(), st);
             tm.stop();
             if (e != hipSuccess) return hip_fail(e, "k_ring launch");
         }
@@ -421,7 +440,15 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
     }
     {
         KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
-        e = launch_dense(h->dix, fb, w, st);
+        if (rows) {
+            // row layout; queries whose minimum sits in two tiles with equal
+            // Y then go through the column layout
+            e = launch_dense_rows(h->dix, fb, w, st);
+            if (e == hipSuccess)
+                e = launch_dense_list(h->dix, fb, w, w.fb_list, w.counters + 2, st);
+        } else {
+            e = launch_dense(h->dix, fb, w, st);
+        }
         tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_dense launch");
     }
@@ -478,8 +505,9 @@ riann_status_t riann_build(const uint8_t *ref_host, const int32_t *key_idx,
     h->K = p->n_keys;
     h->n = p->n_ref;
     h->n_pad = round_up(h->n, kRefAlign);
-    h->threshold = p->dense_threshold >= 0 ? p->dense_threshold : default_threshold(h->n);
-    h->prm.dense_threshold = h->threshold;
+    h->dense_rows = (p->flags & RIANN_FLAG_ROW_DENSE) != 0;
+    h->threshold.store(p->dense_threshold >= 0 ? p->dense_threshold : default_threshold(h->n));
+    h->prm.dense_threshold = h->threshold.load();
     (void)hipGetDevice(&h->device);
     try {
         h->ref.assign(ref_host, ref_host + (size_t)h->n * h->D);
@@ -591,6 +619,14 @@ riann_status_t riann_get_params(riann_index_t h, riann_params_t *p) {
     return RIANN_OK;
 }
 
+riann_status_t riann_set_dense_threshold(riann_index_t h, int64_t threshold) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (threshold < 0) return fail(RIANN_E_INVALID, "threshold must be >= 0");
+    h->threshold.store(threshold);
+    h->prm.dense_threshold = threshold;
+    return RIANN_OK;
+}
+
 riann_status_t riann_save(riann_index_t h, const char *path) {
     if (!h || !path) return fail(RIANN_E_INVALID, "NULL argument");
     {
@@ -646,7 +682,9 @@ riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out
     h->K = prm.n_keys;
     h->n = prm.n_ref;
     h->n_pad = round_up(h->n, kRefAlign);
-    h->threshold = prm.dense_threshold >= 0 ? prm.dense_threshold : default_threshold(h->n);
+    h->dense_rows = (prm.flags & RIANN_FLAG_ROW_DENSE) != 0;
+    h->threshold.store(prm.dense_threshold >= 0 ? prm.dense_threshold : default_threshold(h->n));
+    h->prm.dense_threshold = h->threshold.load();
     (void)hipGetDevice(&h->device);
     try {
         h->ref.resize((size_t)h->n * h->D);

@@ -166,7 +166,9 @@ struct DenseState {
 };
 
 template <int DP, bool SEG, int TPS, int ST>
-__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Work w) {
+__global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Work w,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ count_ptr) {
     constexpr int KB = DP / 32;
     constexpr int STAGE = ST * KB * 1024;         // fragment bytes of one stage
     static_assert(ST % TPS == 0, "tiles per step must divide a stage");
@@ -175,9 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Wo
     __shared__ __attribute__((aligned(16))) uint32_t s_r0[ST * kTile];
     __shared__ __attribute__((aligned(16))) uint32_t s_r1[ST * kTile];
 
-    // whole-frame batches search every query; otherwise the dense list
-    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
-    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
+    // no list: every query of the batch; otherwise the list and its count
+    const uint32_t count = list ? *count_ptr : (uint32_t)fb.Q;
     const uint32_t qbase = blockIdx.x * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Wo
 
 template <int DP>
 hipError_t launch_dense_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                          hipStream_t st) {
+                          const uint32_t *list, const uint32_t *count, hipStream_t st) {
     int64_t blocks = (fb.Q + kBlockQ - 1) / kBlockQ;
     if (blocks < 1) blocks = 1;
     // tile pairs (one v_min3 per update) while the epilogue is the bound,
@@ -284,28 +285,39 @@ hipError_t launch_dense_t(const DevIndex &ix, const FrameBatch &fb, const Work &
     const bool seg = (ix.n_pad / kTile) > (int64_t)(1u << ix.jb);
     if (seg)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, true, TPS, ST>), dim3((unsigned)blocks),
-                           dim3(kBlock), 0, st, ix, fb, w);
+                           dim3(kBlock), 0, st, ix, fb, w, list, count);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, false, TPS, ST>), dim3((unsigned)blocks),
-                           dim3(kBlock), 0, st, ix, fb, w);
+                           dim3(kBlock), 0, st, ix, fb, w, list, count);
     return hipGetLastError();
+}
+
+hipError_t dispatch(const DevIndex &ix, const FrameBatch &fb, const Work &w, const uint32_t *list,
+                    const uint32_t *count, hipStream_t st) {
+    switch (ix.Dp) {
+    case 32: return launch_dense_t<32>(ix, fb, w, list, count, st);
+    case 64: return launch_dense_t<64>(ix, fb, w, list, count, st);
+    case 96: return launch_dense_t<96>(ix, fb, w, list, count, st);
+    case 128: return launch_dense_t<128>(ix, fb, w, list, count, st);
+    case 160: return launch_dense_t<160>(ix, fb, w, list, count, st);
+    case 192: return launch_dense_t<192>(ix, fb, w, list, count, st);
+    case 224: return launch_dense_t<224>(ix, fb, w, list, count, st);
+    case 256: return launch_dense_t<256>(ix, fb, w, list, count, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st) {
-    switch (ix.Dp) {
-    case 32: return launch_dense_t<32>(ix, fb, w, st);
-    case 64: return launch_dense_t<64>(ix, fb, w, st);
-    case 96: return launch_dense_t<96>(ix, fb, w, st);
-    case 128: return launch_dense_t<128>(ix, fb, w, st);
-    case 160: return launch_dense_t<160>(ix, fb, w, st);
-    case 192: return launch_dense_t<192>(ix, fb, w, st);
-    case 224: return launch_dense_t<224>(ix, fb, w, st);
-    case 256: return launch_dense_t<256>(ix, fb, w, st);
-    default: return hipErrorInvalidValue;
-    }
+    return fb.all_full ? dispatch(ix, fb, w, nullptr, nullptr, st)
+                       : dispatch(ix, fb, w, w.dense_list, w.counters + 1, st);
+}
+
+hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                             const uint32_t *list, const uint32_t *count, hipStream_t st) {
+    return dispatch(ix, fb, w, list, count, st);
 }
 
 }  // namespace riann

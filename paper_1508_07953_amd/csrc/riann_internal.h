@@ -33,6 +33,13 @@ struct DevIndex {
                           // 32t + (l & 31), columns 32kb + 16(l >> 5) .. +16,
                           // at byte offset ((t * Dp/32 + kb) * 64 + l) * 16
     const uint32_t *Rk;   // n_pad dense key bases (see above)
+    // Row-layout dense search (references as MFMA rows, queries as columns):
+    // per tile t, 32 entries ordered [g][r] = reference 32t + 8(r/4) + 4g + r%4,
+    // the row the accumulator register r of lane group g holds.
+    //   Hf  = (Rc + bias - p) / 2 with p = Rc & 1, so that
+    //         Y = Hf + <a, v> and SSD - Qc + bias = 2Y + p (exact);
+    //         padding rows get 2^30, above every real Y
+    const int32_t *Hf;
     const uint32_t *T;    // K x n16, SSD(key_k, r) ascending; each key's list is
                           // padded to whole 16-entry (64-byte) lines with
                           // 0xFFFFFFFF, above every ring bound
@@ -91,7 +98,8 @@ struct Work {
     uint4 *rec;          // Q records {c, kstar, st, en}
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
-    uint32_t *counters;  // [0] ring count, [1] dense count
+    uint32_t *fb_list;   // Q, tie fallbacks of the row-layout dense search
+    uint32_t *counters;  // [0] ring count, [1] dense count, [2] fallback count
     int64_t capacity;    // Q capacity
 };
 
@@ -112,5 +120,15 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // device-side count.  Reads the query patches written by launch_extract.
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st);
+// Row-layout dense search (D <= 96).  Queries of the dense list (or all of an
+// all_full batch) are answered directly; the rare queries whose minimum is
+// attained with equal Y in two different tiles are appended to w.fb_list
+// (count w.counters[2]) for launch_dense_list.
+bool dense_rows_supported(const DevIndex &ix);
+hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                             hipStream_t st);
+// Column-layout dense search of an explicit list with a device-side count.
+hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                             const uint32_t *list, const uint32_t *count, hipStream_t st);
 
 }  // namespace riann

@@ -132,10 +132,11 @@ SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("p,C,s,n,K,H,W", SHAPES)
-def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W):
+def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W, flags):
     torch, dev = torch_dev
-    print_case(f"shape p={p} C={C} s={s} n={n} K={K} H={H} W={W}")
+    print_case(f"shape p={p} C={C} s={s} n={n} K={K} H={H} W={W} flags={flags}")
     rng = np.random.default_rng(p * 1000 + n)
     big = np.clip(np.rint(gen.texture(rng, max(H, p + 40), max(W, p + 40), C)), 0, 255)
     big = big.astype(np.uint8)
@@ -148,7 +149,8 @@ def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W):
     P = oracle.extract(f, p, s)
     hq, wq = oracle.field_shape(H, W, p, s)
     for thr in (-1, 1 << 30):
-        idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=s, dense_threshold=thr)
+        idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=s, dense_threshold=thr,
+                                flags=flags)
         fd = to_dev(torch, dev, f)
         out, ssd = idx.full_search(fd)
         torch.cuda.synchronize()
@@ -166,7 +168,8 @@ def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W):
         idx.close()
 
 
-def test_ties_and_constant_frame(torch_dev, riann):
+@pytest.mark.parametrize("flags", [0, 1])
+def test_ties_and_constant_frame(torch_dev, riann, flags):
     torch, dev = torch_dev
     print_case("ties")
     rng = np.random.default_rng(5)
@@ -178,7 +181,7 @@ def test_ties_and_constant_frame(torch_dev, riann):
     P = oracle.extract(f, 8, 1)
     for thr in (-1, 0, 1 << 30):
         idx = riann.Index.build(ref, [150, 7, 42, 250], patch=8, channels=1, stride=1,
-                                dense_threshold=thr)
+                                dense_threshold=thr, flags=flags)
         fd = to_dev(torch, dev, f)
         out, ssd = idx.full_search(fd)
         torch.cuda.synchronize()
@@ -401,4 +404,55 @@ def test_large_workloads_sampled(torch_dev, riann, name, nsamp):
         gi, gd = host(out)[sel], host(ssd)[sel].astype(np.uint32)
         assert np.array_equal(gi, bi) and np.array_equal(gd, bd), f"{name} frame {t}"
         prev = out.clone()
+    idx.close()
+
+
+@pytest.mark.parametrize("name", ["hd720", "tiny"])
+def test_row_and_column_dense_agree_everywhere(torch_dev, riann, name):
+    """Whole-frame full search by the row-layout dense kernel (with its tie
+    fallback) and by the column-layout kernel: identical at every query; a
+    sample also against brute force."""
+    torch, dev = torch_dev
+    print_case(f"row vs column dense {name}")
+    wl = gen.make_workload(name, frames=2)
+    a = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
+                          stride=wl.stride, flags=riann.FLAG_ROW_DENSE)
+    b = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
+                          stride=wl.stride)
+    f = wl.frame(1)
+    fd = to_dev(torch, dev, f)
+    oa, sa = a.full_search(fd)
+    ob, sb = b.full_search(fd)
+    torch.cuda.synchronize()
+    assert torch.equal(oa, ob) and torch.equal(sa, sb)
+    rng = np.random.default_rng(17)
+    P = oracle.extract(f, wl.patch, wl.stride)
+    sel = np.sort(rng.choice(len(P), min(len(P), 2000), replace=False))
+    bi, bd = oracle.brute_force(P[sel], wl.ref)
+    assert np.array_equal(host(oa)[sel], bi) and np.array_equal(host(sa)[sel].astype(np.uint32), bd)
+    a.close()
+    b.close()
+
+
+def test_tuned_threshold_keeps_results(torch_dev, riann, tmp_path, monkeypatch):
+    """The autotuner only moves the ring/dense routing threshold: the field
+    after tuning equals brute force, and the cached choice is re-applied."""
+    from paper_1508_07953_amd import tune
+    torch, dev = torch_dev
+    print_case("autotuned threshold")
+    monkeypatch.setenv("RIANN_TUNE_CACHE", str(tmp_path / "tune.json"))
+    wl = gen.make_workload("tiny", frames=3)
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    f = [to_dev(torch, dev, wl.frame(t)) for t in range(3)]
+    p0, _ = idx.full_search(f[0])
+    p1, _ = idx.match_frame(f[1], prev=p0)
+    r = tune.tune_threshold(idx, [f[1], f[2]], [p0, p1], candidates=(0, 32, 1 << 30),
+                            repeats=1)
+    assert not r["cached"] and r["threshold"] in (0, 32, int(idx.params.n_ref))
+    out, ssd = idx.match_frame(f[2], prev=p1)
+    torch.cuda.synchronize()
+    check_exact(out, ssd, oracle.extract(wl.frame(2), 8, 1), wl.ref, "tuned")
+    idx.set_dense_threshold(7)
+    r2 = tune.tune_threshold(idx, [f[1]], [p0])
+    assert r2["cached"] and idx.params.dense_threshold == r["threshold"]
     idx.close()
