@@ -42,20 +42,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def dense_traffic_bytes(workload):
-    """HBM bytes per k_dense dispatch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def dense_traffic_bytes(workload, layout):
+    """HBM bytes per dispatch of the dominant dense kernel from the committed
+    rocprofv3 counter summary, or None when there is none for this workload
+    and layout or the kernel source changed since it was taken."""
     import hashlib
-    if workload != "hd720":
-        return None
     try:
-        with open(os.path.join(ROOT, "profiles", "hd720_k_dense_traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", f"{workload}_dense_traffic.json")) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1508_07953_amd", "csrc", "k_dense.hip"), "rb") as f:
+        if rec.get("dense_layout") != layout:
+            return None
+        with open(os.path.join(ROOT, "paper_1508_07953_amd", "csrc", rec["source"]), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
-    return rec["bytes_per_dispatch"] if rec.get("k_dense_source_sha256") == sha else None
+    return rec["bytes_per_dispatch"] if rec.get("source_sha256") == sha else None
 
 
 def cpu_baseline(wl, f0, f1, target_s):
@@ -163,9 +164,9 @@ def main():
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--workload", default="hd720", choices=["hd720", "fhd_rgb", "uhd_mix"],
                     help="per-frame workload of the timed loop (hd720 is the headline)")
-    ap.add_argument("--dense-layout", default="column", choices=["column", "rows"],
-                    help="column: queries as MFMA rows (default); rows: references as "
-                         "MFMA rows, where the patch allows it")
+    ap.add_argument("--dense-layout", default="auto", choices=["auto", "column"],
+                    help="auto: references as MFMA rows where the patch allows it (the "
+                         "library default); column: always queries as MFMA rows")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default routing threshold")
     ap.add_argument("--no-serving", action="store_true",
@@ -197,7 +198,7 @@ def main():
     H, Wd = frames_h[0].shape[:2]
     idx = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
                             stride=wl.stride,
-                            flags=riann.FLAG_ROW_DENSE if args.dense_layout == "rows" else 0)
+                            flags=riann.FLAG_COLUMN_DENSE if args.dense_layout == "column" else 0)
     hq, wq = idx.field_shape(H, Wd)
     Q = hq * wq
     bufs = [torch.empty((hq, wq), dtype=torch.int32, device=dev) for _ in range(2)]
@@ -286,10 +287,13 @@ def main():
         ms_per_launch = (prof["dense"]["ms"] + prof["full"]["ms"]) / max(1, launches)
         ops = 2.0 * dense_q_per_launch * n * D
         achieved = ops / (ms_per_launch * 1e-3) / 1e12
-        result["roofline"] = {"bound": "mfma", "kernel": "k_dense (int8 MFMA, routed queries)",
+        rows = args.dense_layout == "auto" and wl.D <= 96
+        kname = ("k_dense_rows + k_resolve (int8 MFMA, references as rows)" if rows else
+                 "k_dense (int8 MFMA, queries as rows)")
+        result["roofline"] = {"bound": "mfma", "kernel": kname,
                               "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                               "frac": achieved / INT8_PEAK_TOPS,
-                              "traffic": dense_traffic_bytes(args.workload),
+                              "traffic": dense_traffic_bytes(args.workload, args.dense_layout),
                               "ms_per_launch": ms_per_launch,
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])

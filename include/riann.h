@@ -75,12 +75,11 @@ typedef struct riann_params {
     uint32_t reserved;         /* must be 0                                    */
 } riann_params_t;
 
-/* riann_params_t.flags: answer dense queries with the row-layout search
- * (references as MFMA rows, queries as columns; patches of at most 96 padded
- * bytes, else ignored) instead of the default column layout.  Results are
- * identical; on the 720p workload it is slower, and it is kept for
- * measurement and as a cross-check of the default kernel. */
-#define RIANN_FLAG_ROW_DENSE 1u
+/* riann_params_t.flags: answer dense queries with the column-layout search
+ * (queries as MFMA rows) also where the row layout (references as MFMA rows,
+ * patches of at most 96 padded bytes) is the default.  Results are identical;
+ * this exists for measurement and as a cross-check of the two kernels. */
+#define RIANN_FLAG_COLUMN_DENSE 1u
 
 /* One frame of a batch (riann_match_batch). */
 typedef struct riann_frame_desc {
@@ -112,6 +111,9 @@ typedef struct riann_stats {
     uint64_t sum_survivors;    /* sum over ring-scanned queries of |S|, the
                                   number of references inside all K rings     */
     uint64_t sum_mstar_ring;   /* sum of m* over ring-scanned queries only     */
+    uint64_t dense_fallback;   /* row-layout dense search only: queries whose
+                                  minimum the tile-resolve step could not pin
+                                  down, answered by an exhaustive search      */
 } riann_stats_t;
 
 /*

@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(_PKG, "libriann.so")
 RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, RIANN_E_IO = (
     0, -1, -2, -3, -4, -5)
 MODE_RING, MODE_FULL = 0, 1
-FLAG_ROW_DENSE = 1
+FLAG_COLUMN_DENSE = 1
 
 # every symbol include/riann.h declares
 EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
@@ -64,7 +64,7 @@ class Profile(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in
                 ("frames", "queries", "ring_queries", "dense_queries", "no_prior",
-                 "sum_mstar", "sum_survivors", "sum_mstar_ring")]
+                 "sum_mstar", "sum_survivors", "sum_mstar_ring", "dense_fallback")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -74,6 +74,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950)")
+    # torch ships its own HIP runtime.  Loading torch first makes the library
+    # bind to that same runtime; loaded the other way round, the process would
+    # hold two HIP/HSA runtimes and the second to start finds no device.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.riann_build.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(vp)]

@@ -22,7 +22,7 @@ struct riann_index {
     int D = 0, Dp = 0, K = 0;
     int64_t n = 0, n_pad = 0;
     std::atomic<int64_t> threshold{0};
-    bool dense_rows = false;  // row-layout dense search (opt-in) where supported
+    bool dense_rows = true;   // row-layout dense search where supported
     int device = 0;
     // host copies (kept for riann_save)
     std::vector<uint8_t> ref;
@@ -84,7 +84,7 @@ riann_status_t check_params(const riann_params_t *p) {
     if (p->n_keys < 0 || p->n_keys > kMaxKeys)
         return fail(RIANN_E_INVALID, "n_keys must be in [0, 64]");
     if (p->n_keys > p->n_ref) return fail(RIANN_E_INVALID, "n_keys exceeds n_ref");
-    if ((p->flags & ~RIANN_FLAG_ROW_DENSE) != 0 || p->reserved != 0)
+    if ((p->flags & ~RIANN_FLAG_COLUMN_DENSE) != 0 || p->reserved != 0)
         return fail(RIANN_E_INVALID, "unknown flags or nonzero reserved field");
     return RIANN_OK;
 }
@@ -104,7 +104,7 @@ int64_t index_bytes(int64_t n, int D, int K) {
            (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 16 + 12) + 8192; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 32 + 12) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -323,6 +323,7 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
     nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
     nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
+    nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 16, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.fb_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
@@ -441,11 +442,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
     {
         KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
         if (rows) {
-            // row layout; queries whose minimum sits in two tiles with equal
-            // Y then go through the column layout
-            e = launch_dense_rows(h->dix, fb, w, st);
-            if (e == hipSuccess)
-                e = launch_dense_list(h->dix, fb, w, w.fb_list, w.counters + 2, st);
+            e = launch_dense_rows(h->dix, fb, w, h->dstats, st);
         } else {
             e = launch_dense(h->dix, fb, w, st);
         }
@@ -505,7 +502,7 @@ riann_status_t riann_build(const uint8_t *ref_host, const int32_t *key_idx,
     h->K = p->n_keys;
     h->n = p->n_ref;
     h->n_pad = round_up(h->n, kRefAlign);
-    h->dense_rows = (p->flags & RIANN_FLAG_ROW_DENSE) != 0;
+    h->dense_rows = (p->flags & RIANN_FLAG_COLUMN_DENSE) == 0;
     h->threshold.store(p->dense_threshold >= 0 ? p->dense_threshold : default_threshold(h->n));
     h->prm.dense_threshold = h->threshold.load();
     (void)hipGetDevice(&h->device);
@@ -596,6 +593,7 @@ riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
     s->sum_mstar = v[ST_MSTAR];
     s->sum_survivors = v[ST_SURV];
     s->sum_mstar_ring = v[ST_MSTAR_RING];
+    s->dense_fallback = v[ST_FALLBACK];
     return RIANN_OK;
 }
 
@@ -682,7 +680,7 @@ riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out
     h->K = prm.n_keys;
     h->n = prm.n_ref;
     h->n_pad = round_up(h->n, kRefAlign);
-    h->dense_rows = (prm.flags & RIANN_FLAG_ROW_DENSE) != 0;
+    h->dense_rows = (prm.flags & RIANN_FLAG_COLUMN_DENSE) == 0;
     h->threshold.store(prm.dense_threshold >= 0 ? prm.dense_threshold : default_threshold(h->n));
     h->prm.dense_threshold = h->threshold.load();
     (void)hipGetDevice(&h->device);

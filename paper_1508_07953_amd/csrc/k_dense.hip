@@ -34,12 +34,23 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
-constexpr int kWaves = 8;                   // wavefronts per block
+#ifndef RIANN_DENSE_WAVES
+#define RIANN_DENSE_WAVES 8
+#endif
+#ifndef RIANN_DENSE_ST_NARROW
+#define RIANN_DENSE_ST_NARROW 8     // tiles per LDS stage, Dp <= 64
+#endif
+#ifndef RIANN_DENSE_ST_WIDE
+#define RIANN_DENSE_ST_WIDE 4       // tiles per LDS stage, Dp > 64
+#endif
+constexpr int kWaves = RIANN_DENSE_WAVES;   // wavefronts per block
 constexpr int kBlock = 64 * kWaves;
 constexpr int kQB = 2;                      // 32-query row blocks per wavefront
 constexpr int kWaveQ = 32 * kQB;
 constexpr int kBlockQ = kWaveQ * kWaves;
-static_assert(kRefAlign % (kTile * 8) == 0, "reference padding must cover 8-tile stages");
+static_assert(kRefAlign % (kTile * RIANN_DENSE_ST_NARROW) == 0 &&
+                  kRefAlign % (kTile * RIANN_DENSE_ST_WIDE) == 0,
+              "reference padding must cover whole stages");
 
 __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
     unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
@@ -182,7 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Wo
     const uint32_t qbase = blockIdx.x * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 31, grp = lane >> 5;
     const int nstages = (int)(ix.n_pad / (kTile * ST));
     const int64_t ntiles = ix.n_pad / kTile;
@@ -281,7 +293,7 @@ hipError_t launch_dense_t(const DevIndex &ix, const FrameBatch &fb, const Work &
     // single tiles for wide patches, where the matrix cores are; 8-tile
     // stages while they fit two blocks per CU in LDS
     constexpr int TPS = DP <= 96 ? 2 : 1;
-    constexpr int ST = DP <= 64 ? 8 : 4;
+    constexpr int ST = DP <= 64 ? RIANN_DENSE_ST_NARROW : RIANN_DENSE_ST_WIDE;
     const bool seg = (ix.n_pad / kTile) > (int64_t)(1u << ix.jb);
     if (seg)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense<DP, true, TPS, ST>), dim3((unsigned)blocks),

@@ -11,9 +11,11 @@
 // it.  A resolve kernel then recomputes that one tile's 32 exact SSDs and
 // takes their (SSD, index) minimum -- the global one, because every row
 // outside the tile has a larger Y, hence a larger SSD (2Y + p grows with Y).
-// When the smallest Y occurs in two different tiles the parities of those
-// tiles could decide differently, so such a query is handed to the
-// column-layout kernel (its index is appended to the fallback list).
+// The smallest Y can occur in several tiles (references whose SSDs differ by
+// one share a Y), so each lane also keeps the latest later tile with an equal
+// minimum and a count of them; the resolve kernel then checks up to two tiles,
+// and the rare query whose minimum Y sits in three or more tiles is answered
+// by an exhaustive per-query search (fallback list).
 #include "riann_internal.h"
 
 namespace riann {
@@ -25,12 +27,17 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
-constexpr int kWaves = 8;
+#ifndef RIANN_ROWS_WAVES
+#define RIANN_ROWS_WAVES 4
+#endif
+#ifndef RIANN_ROWS_QB
+#define RIANN_ROWS_QB 4
+#endif
+constexpr int kWaves = RIANN_ROWS_WAVES;
 constexpr int kBlock = 64 * kWaves;
-constexpr int kQB = 2;                 // 32-query column blocks per wavefront
+constexpr int kQB = RIANN_ROWS_QB;     // 32-query column blocks per wavefront
 constexpr int kWaveQ = 32 * kQB;
 constexpr int kBlockQ = kWaveQ * kWaves;
-constexpr int kTPS = 2;                // tiles per step
 
 template <int KB, int ST>
 __device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
@@ -67,67 +74,60 @@ struct RowState {
     v4i Bq[kQB][KB];        // query fragments (MFMA B operand)
     uint32_t bY[kQB];       // smallest Y so far (this lane's 16 rows)
     uint32_t bT[kQB];       // first tile attaining it
-    uint32_t tie[kQB];      // another tile reached the same Y
+    uint32_t bT2[kQB];      // the latest later tile reaching the same Y
+    uint32_t cnt[kQB];      // how many later tiles reached it
 
-    __device__ __forceinline__ void load_step(const int8_t *lf, const int32_t *lh, int u,
-                                              int lane, int grp, v4i (&Af)[kTPS][KB],
-                                              v16i (&H)[kTPS]) {
+    // A fragments and accumulator initial values (Hf) of tile u of a stage
+    __device__ __forceinline__ void load_tile(const int8_t *lf, const int32_t *lh, int u,
+                                              int lane, int grp, v4i (&Af)[KB], v16i &H) {
 #pragma unroll
-        for (int v = 0; v < kTPS; ++v) {
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-                Af[v][kb] = *reinterpret_cast<const v4i *>(lf + ((u * kTPS + v) * KB + kb) * 1024 +
-                                                           lane * 16);
-            const v4i *hp = reinterpret_cast<const v4i *>(lh + (u * kTPS + v) * kTile + grp * 16);
-            const v4i h0 = hp[0], h1 = hp[1], h2 = hp[2], h3 = hp[3];
-            H[v] = v16i{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3],
-                        h2[0], h2[1], h2[2], h2[3], h3[0], h3[1], h3[2], h3[3]};
-        }
+        for (int kb = 0; kb < KB; ++kb)
+            Af[kb] = *reinterpret_cast<const v4i *>(lf + (u * KB + kb) * 1024 + lane * 16);
+        const v4i *hp = reinterpret_cast<const v4i *>(lh + u * kTile + grp * 16);
+        const v4i h0 = hp[0], h1 = hp[1], h2 = hp[2], h3 = hp[3];
+        H = v16i{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3],
+                 h2[0], h2[1], h2[2], h2[3], h3[0], h3[1], h3[2], h3[3]};
     }
 
-    __device__ __forceinline__ void mma(int qb, const v4i (&Af)[kTPS][KB], const v16i (&H)[kTPS],
-                                        v16i (&acc)[kTPS]) {
+    __device__ __forceinline__ void mma(int qb, const v4i (&Af)[KB], const v16i &H, v16i &acc) {
+        acc = H;
 #pragma unroll
-        for (int v = 0; v < kTPS; ++v) {
-            acc[v] = H[v];
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-                acc[v] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[v][kb], Bq[qb][kb], acc[v], 0, 0,
-                                                               0);
-        }
+        for (int kb = 0; kb < KB; ++kb)
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], Bq[qb][kb], acc, 0, 0, 0);
     }
 
-    __device__ __forceinline__ void track(int qb, const v16i (&acc)[kTPS], uint32_t t0) {
-#pragma unroll
-        for (int v = 0; v < kTPS; ++v) {
-            const uint32_t m = min16(acc[v]);
-            const bool lt = m < bY[qb];
-            const bool eq = m == bY[qb];
-            tie[qb] = lt ? 0u : (tie[qb] | (eq ? 1u : 0u));
-            bT[qb] = lt ? t0 + v : bT[qb];
-            bY[qb] = lt ? m : bY[qb];
-        }
+    __device__ __forceinline__ void track(int qb, const v16i &acc, uint32_t t) {
+        const uint32_t m = min16(acc);
+        const bool lt = m < bY[qb];
+        const bool eq = m == bY[qb];
+        bT2[qb] = eq ? t : bT2[qb];
+        cnt[qb] = lt ? 0u : cnt[qb] + (eq ? 1u : 0u);
+        bT[qb] = lt ? t : bT[qb];
+        bY[qb] = lt ? m : bY[qb];
     }
 
-    // all tiles of one LDS stage, pipelined across the two query blocks
+    // all tiles of one LDS stage; the MFMA chain of the next query block (or
+    // of the next tile's first block) is issued before the current block's
+    // minimum tree, so the matrix core and the VALU overlap
     __device__ __forceinline__ void stage(const int8_t *lf, const int32_t *lh, uint32_t t0s,
                                           int lane, int grp) {
-        constexpr int NS = ST / kTPS;
-        v4i Af[kTPS][KB];
-        v16i H[kTPS];
-        v16i a0[kTPS], a1[kTPS];
-        load_step(lf, lh, 0, lane, grp, Af, H);
-        mma(0, Af, H, a0);
+        v4i Af[KB];
+        v16i H;
+        v16i acc[2];
+        load_tile(lf, lh, 0, lane, grp, Af, H);
+        mma(0, Af, H, acc[0]);
 #pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const uint32_t t0 = t0s + (uint32_t)(u * kTPS);
-            mma(1, Af, H, a1);
-            track(0, a0, t0);
-            if (u + 1 < NS) {
-                load_step(lf, lh, u + 1, lane, grp, Af, H);
-                mma(0, Af, H, a0);
+        for (int u = 0; u < ST; ++u) {
+#pragma unroll
+            for (int qb = 0; qb < kQB; ++qb) {
+                if (qb + 1 < kQB) {
+                    mma(qb + 1, Af, H, acc[(qb + 1) & 1]);
+                } else if (u + 1 < ST) {
+                    load_tile(lf, lh, u + 1, lane, grp, Af, H);
+                    mma(0, Af, H, acc[0]);
+                }
+                track(qb, acc[qb & 1], t0s + (uint32_t)u);
             }
-            track(1, a1, t0);
         }
     }
 };
@@ -136,7 +136,6 @@ template <int DP, int ST>
 __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w) {
     constexpr int KB = DP / 32;
     constexpr int STAGE = ST * KB * 1024;
-    static_assert(ST % kTPS == 0, "tile pairs must divide a stage");
     __shared__ __attribute__((aligned(16))) int8_t s_f0[STAGE];
     __shared__ __attribute__((aligned(16))) int8_t s_f1[STAGE];
     __shared__ __attribute__((aligned(16))) int32_t s_h0[ST * kTile];
@@ -144,18 +143,24 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
 
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    const uint32_t qbase = blockIdx.x * kBlockQ;
+    // two blocks per query chunk, each over one half of the reference stages
+    // (even blocks the first half, odd blocks the second; consecutive blocks
+    // land on different XCDs, so each XCD's L2 holds one half)
+    const uint32_t half = blockIdx.x & 1u;
+    const uint32_t qbase = (blockIdx.x >> 1) * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 31, grp = lane >> 5;
-    const int nstages = (int)(ix.n_pad / (kTile * ST));
+    const int ns_all = (int)(ix.n_pad / (kTile * ST));
+    const int s_mid = (ns_all + 1) / 2;
+    const int s_begin = half ? s_mid : 0, s_end = half ? ns_all : s_mid;
 
-    stage_dma<KB, ST>(ix.Rf, ix.Hf, 0, s_f0, s_h0, wv, lane);
+    if (s_begin < s_end) stage_dma<KB, ST>(ix.Rf, ix.Hf, s_begin, s_f0, s_h0, wv, lane);
 
     RowState<DP, ST> S;
     uint32_t qid[kQB];
-    int qc[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
         const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
@@ -164,77 +169,120 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
                             grp * 16;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) S.Bq[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
-        qc[qb] = w.qc[qid[qb]];
         S.bY[qb] = ~0u;
         S.bT[qb] = 0;
-        S.tie[qb] = 0;
+        S.bT2[qb] = 0;
+        S.cnt[qb] = 0;
     }
     __syncthreads();
 
-    for (int sg = 0; sg < nstages; sg += 2) {
-        if (sg + 1 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
+    for (int sg = s_begin; sg < s_end; sg += 2) {
+        if (sg + 1 < s_end) stage_dma<KB, ST>(ix.Rf, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
         S.stage(s_f0, s_h0, (uint32_t)(sg * ST), lane, grp);
         __syncthreads();
-        if (sg + 1 < nstages) {
-            if (sg + 2 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
+        if (sg + 1 < s_end) {
+            if (sg + 2 < s_end) stage_dma<KB, ST>(ix.Rf, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
             S.stage(s_f1, s_h1, (uint32_t)((sg + 1) * ST), lane, grp);
             __syncthreads();
         }
     }
 
-    // ---- merge the two lane groups (different rows of the same tiles)
-    uint32_t Ym[kQB], Tm[kQB], Xm[kQB];
+    // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
+    // accumulator order) and hand the result to the resolve kernel through the
+    // query's record (records of dense-routed queries are free after the ring
+    // phase): rec = {Y, T1 << 2 | group mask, T2 + 1 (0: none), fallback}.
+    // The minimum Y sits in tile T1 (and T2) within the masked groups' rows;
+    // three or more tiles go to the fallback.
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t oY = (uint32_t)__shfl_xor((int)S.bY[qb], 32, 64);
-        const uint32_t oT = (uint32_t)__shfl_xor((int)S.bT[qb], 32, 64);
-        const uint32_t oX = (uint32_t)__shfl_xor((int)S.tie[qb], 32, 64);
-        const uint32_t y = S.bY[qb], t = S.bT[qb], x = S.tie[qb];
-        Ym[qb] = min(y, oY);
-        Tm[qb] = y < oY ? t : (oY < y ? oT : min(t, oT));
-        Xm[qb] = y < oY ? x : (oY < y ? oX : (x | oX | (t != oT ? 1u : 0u)));
-    }
-
-    // ---- hand (Y, tile, tie) to the resolve kernel through the query's
-    // record (records of dense-routed queries are free after the ring phase)
+        const uint32_t y = S.bY[qb], t = S.bT[qb], t2 = S.bT2[qb], c = S.cnt[qb];
+        const uint32_t oY = (uint32_t)__shfl_xor((int)y, 32, 64);
+        const uint32_t oT = (uint32_t)__shfl_xor((int)t, 32, 64);
+        const uint32_t oT2 = (uint32_t)__shfl_xor((int)t2, 32, 64);
+        const uint32_t oC = (uint32_t)__shfl_xor((int)c, 32, 64);
+        uint32_t T1, T2p = 0, gm, fbk = 0;
+        if (y != oY) {
+            const bool own = y < oY;
+            const uint32_t cc = own ? c : oC;
+            T1 = own ? t : oT;
+            gm = own ? (1u << grp) : (2u >> grp);
+            if (cc == 1) T2p = (own ? t2 : oT2) + 1;
+            if (cc > 1) fbk = 1;
+        } else if (c > 1 || oC > 1) {
+            T1 = t; gm = 3u; fbk = 1;
+        } else {
+            // distinct tiles among t (< t2) and oT (< oT2)
+            const uint32_t a1 = t, a2 = c ? t2 : t, b1 = oT, b2 = oC ? oT2 : oT;
+            const uint32_t lo = min(a1, b1);
+            uint32_t hi = lo, n = 1;
+            const uint32_t cand[4] = {a1, a2, b1, b2};
 #pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
+            for (int k = 0; k < 4; ++k) {
+                if (cand[k] != lo && (n == 1 || cand[k] != hi)) {
+                    if (n == 1) { hi = cand[k]; n = 2; } else { n = 3; }
+                }
+            }
+            T1 = lo; gm = 3u;
+            if (n == 2) T2p = hi + 1;
+            if (n > 2) fbk = 1;
+        }
         const bool live = qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col) < count;
         if (live && grp == 0)
-            w.rec[qid[qb]] = make_uint4(Ym[qb], (Tm[qb] << 1) | (Xm[qb] ? 1u : 0u), 0u, 0u);
+            (half ? w.rec2 : w.rec)[qid[qb]] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
     }
 }
 
-// One thread per dense query: recompute the 32 SSDs of the winning tile with
-// v_dot4 and take the (SSD, index) minimum -- the global one, since every row
-// outside that tile has a larger Y.  Queries flagged as ties go to the
-// fallback list for the column-layout kernel.
+// Resolve step: 16 lanes per dense query, lane r taking accumulator row r of
+// each recorded (tile, lane group) -- tile row 8(r/4) + 4g + r%4 -- so the
+// loads of one query's candidate rows are issued together.  Each lane forms
+// the exact SSD with v_dot4; a 16-lane reduction keeps the (SSD, index)
+// minimum, which is the global one since every other row has a larger Y.
+// Queries flagged for the fallback are appended to the fallback list and
+// counted.
 template <int DP>
-__global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w) {
+__global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w,
+                                                 unsigned long long *stats) {
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, r = lane & 15;
+    const uint32_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = i < count;
     const uint32_t q = live ? (list ? list[i] : i) : 0u;
-    bool tie = false;
+    // merge the two reference halves: the smaller Y wins; at equal Y the
+    // tiles of both (disjoint ranges) are checked in both lane groups
+    uint4 rec = make_uint4(0u, 0u, 0u, 1u);
     if (live) {
-        const uint4 rec = w.rec[q];
-        tie = (rec.y & 1u) != 0;
-        if (!tie) {
-            const uint32_t T = rec.y >> 1;
-            uint32_t a[DP / 4];
-            const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP);
+        const uint4 r0 = w.rec[q], r1 = w.rec2[q];
+        if (r0.x != r1.x) {
+            rec = r0.x < r1.x ? r0 : r1;
+        } else {
+            const int n0 = r0.z ? 2 : 1, n1 = r1.z ? 2 : 1;
+            const uint32_t gm = (r0.y | r1.y) & 3u;
+            rec = make_uint4(r0.x, ((r0.y >> 2) << 2) | gm, 0u, (r0.w | r1.w) ? 1u : 0u);
+            if (n0 + n1 > 2) rec.w = 1u;
+            else rec.z = (r1.y >> 2) + 1;       // n0 = n1 = 1: tiles r0.T1, r1.T1
+        }
+    }
+    const bool fbk = rec.w != 0;
+    unsigned long long best = ~0ull;
+    if (!fbk) {
+        const uint32_t gm = rec.y & 3u;
+        const uint32_t tiles[2] = {rec.y >> 2, rec.z - 1};
+        const int ntl = rec.z ? 2 : 1;
+        uint32_t a[DP / 4];
+        const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP);
 #pragma unroll
-            for (int k = 0; k < DP / 16; ++k) {
-                const uint4 v = src[k];
-                a[4 * k] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
-            }
-            const int Qc = w.qc[q];
-            unsigned long long best = ~0ull;
-            for (int m = 0; m < kTile; ++m) {
-                const int64_t r = (int64_t)T * kTile + m;
-                if (r >= ix.n) break;
-                const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + r * DP);
+        for (int k = 0; k < DP / 16; ++k) {
+            const uint4 v = src[k];
+            a[4 * k] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
+        }
+        const int Qc = w.qc[q];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int tt = c >> 1, g = c & 1;
+            const int64_t ref = (int64_t)tiles[tt] * kTile + 8 * (r >> 2) + 4 * g + (r & 3);
+            if (tt < ntl && ((gm >> g) & 1u) && ref < ix.n) {
+                const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + ref * DP);
                 int d = 0;
 #pragma unroll
                 for (int k = 0; k < DP / 16; ++k) {
@@ -244,41 +292,120 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
                     d = __builtin_amdgcn_sdot4((int)a[4 * k + 2], (int)v.z, d, false);
                     d = __builtin_amdgcn_sdot4((int)a[4 * k + 3], (int)v.w, d, false);
                 }
-                const uint32_t ssd = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
-                const unsigned long long key = ((unsigned long long)ssd << 32) | (uint32_t)r;
+                const uint32_t ssd = (uint32_t)(Qc + ix.Rc[ref] + 2 * d);
+                const unsigned long long key = ((unsigned long long)ssd << 32) | (uint32_t)ref;
                 best = key < best ? key : best;
             }
-            const FrameDesc *fdp = &fb.f[w.fid[q]];
-            const int64_t ql = (int64_t)q - fdp->qbase;
-            fdp->out[ql] = (int32_t)(uint32_t)best;
-            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
         }
     }
-    const unsigned long long tmask = __ballot(tie);
-    if (tmask) {
-        const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+        const unsigned lo = __shfl_xor((unsigned)best, m, 64);
+        const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        best = o < best ? o : best;
+    }
+    if (live && !fbk && r == 0) {
+        const FrameDesc *fdp = &fb.f[w.fid[q]];
+        const int64_t ql = (int64_t)q - fdp->qbase;
+        fdp->out[ql] = (int32_t)(uint32_t)best;
+        if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
+    }
+    const bool mine = live && fbk && r == 0;
+    const unsigned long long fmask = __ballot(mine);
+    if (fmask) {
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&w.counters[2], (uint32_t)__popcll(tmask));
+        if (lane == 0) {
+            base = atomicAdd(&w.counters[2], (uint32_t)__popcll(fmask));
+            atomicAdd(&stats[ST_FALLBACK], (unsigned long long)__popcll(fmask));
+        }
         base = __shfl(base, 0, 64);
-        if (tie) {
-            const unsigned lo = __builtin_amdgcn_mbcnt_lo((unsigned)tmask, 0u);
-            w.fb_list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(tmask >> 32), lo)] = q;
+        if (mine) {
+            const unsigned lo = __builtin_amdgcn_mbcnt_lo((unsigned)fmask, 0u);
+            w.fb_list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32), lo)] = q;
         }
     }
 }
 
+// Exhaustive exact search for the few queries of a list: one block per query
+// (grid-stride over the list, whose length is read on the device), each
+// thread takes every 256th reference with v_dot4, and a block reduction
+// keeps the (SSD, index) minimum.  Every block leaves the loop once its index
+// passes the count.
 template <int DP>
-hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
-    int64_t blocks = (fb.Q + kBlockQ - 1) / kBlockQ;
-    if (blocks < 1) blocks = 1;
+__global__ __launch_bounds__(256) void k_brute_list(DevIndex ix, FrameBatch fb, Work w,
+                                                    const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ count_ptr) {
+    __shared__ unsigned long long s_red[4];
+    const uint32_t count = *count_ptr;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t q = list[i];
+        uint32_t a[DP / 4];
+        const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 16; ++k) {
+            const uint4 v = src[k];
+            a[4 * k] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
+        }
+        const int Qc = w.qc[q];
+        unsigned long long best = ~0ull;
+        for (int64_t r = tid; r < ix.n; r += 256) {
+            const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + r * DP);
+            int d = 0;
+#pragma unroll
+            for (int k = 0; k < DP / 16; ++k) {
+                const uint4 v = row[k];
+                d = __builtin_amdgcn_sdot4((int)a[4 * k], (int)v.x, d, false);
+                d = __builtin_amdgcn_sdot4((int)a[4 * k + 1], (int)v.y, d, false);
+                d = __builtin_amdgcn_sdot4((int)a[4 * k + 2], (int)v.z, d, false);
+                d = __builtin_amdgcn_sdot4((int)a[4 * k + 3], (int)v.w, d, false);
+            }
+            const uint32_t ssd = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
+            const unsigned long long key = ((unsigned long long)ssd << 32) | (uint32_t)r;
+            best = key < best ? key : best;
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            const unsigned lo = __shfl_xor((unsigned)best, m, 64);
+            const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
+            const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+            best = o < best ? o : best;
+        }
+        if (lane == 0) s_red[wv] = best;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = s_red[0];
+            for (int k = 1; k < 4; ++k) b = s_red[k] < b ? s_red[k] : b;
+            const FrameDesc *fdp = &fb.f[w.fid[q]];
+            const int64_t ql = (int64_t)q - fdp->qbase;
+            fdp->out[ql] = (int32_t)(uint32_t)b;
+            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(b >> 32);
+        }
+        __syncthreads();
+    }
+}
+
+template <int DP>
+hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                         unsigned long long *stats, hipStream_t st) {
+    int64_t blocks = 2 * ((fb.Q + kBlockQ - 1) / kBlockQ);
+    if (blocks < 2) blocks = 2;
     constexpr int ST = DP <= 64 ? 8 : 4;
+    static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks), dim3(kBlock),
                        0, st, ix, fb, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t rb = (fb.Q + 255) / 256;
+    const int64_t rb = (fb.Q + 15) / 16;          // 16 queries per 256-thread block
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)(rb < 1 ? 1 : rb)), dim3(256),
-                       0, st, ix, fb, w);
+                       0, st, ix, fb, w, stats);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the fallback list is short; at most 1024 blocks walk it
+    const int64_t fbl = fb.Q < 1024 ? (fb.Q < 1 ? 1 : fb.Q) : 1024;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_brute_list<DP>), dim3((unsigned)fbl), dim3(256), 0, st,
+                       ix, fb, w, (const uint32_t *)w.fb_list, (const uint32_t *)(w.counters + 2));
     return hipGetLastError();
 }
 
@@ -287,11 +414,11 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
 bool dense_rows_supported(const DevIndex &ix) { return ix.Dp <= 96; }
 
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                             hipStream_t st) {
+                             unsigned long long *stats, hipStream_t st) {
     switch (ix.Dp) {
-    case 32: return launch_rows_t<32>(ix, fb, w, st);
-    case 64: return launch_rows_t<64>(ix, fb, w, st);
-    case 96: return launch_rows_t<96>(ix, fb, w, st);
+    case 32: return launch_rows_t<32>(ix, fb, w, stats, st);
+    case 64: return launch_rows_t<64>(ix, fb, w, stats, st);
+    case 96: return launch_rows_t<96>(ix, fb, w, stats, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -14,7 +14,7 @@ namespace riann {
 //   Qc = sum (a + 1)^2,   Rc = sum v (v + 2).
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
-constexpr int kRefAlign = 256;   // n is padded to whole 8-tile dense stages
+constexpr int kRefAlign = 512;   // n is padded to whole 16-tile dense stages
 constexpr int kMaxKeys = 64;
 
 // Dense-search key of a (query, reference) pair, unsigned 32-bit:
@@ -95,17 +95,19 @@ struct Work {
     uint8_t *patches;    // Q x Dp encoded query patches (a = q ^ 0x7F, zero padded)
     int32_t *qc;         // Q, Qc of each query
     uint8_t *fid;        // Q, frame of each query within its launch
-    uint4 *rec;          // Q records {c, kstar, st, en}
+    uint4 *rec;          // Q records {c, kstar, st, en}; row-layout dense: the
+                         // first reference half's result
+    uint4 *rec2;         // Q, row-layout dense: the second reference half's
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
-    uint32_t *fb_list;   // Q, tie fallbacks of the row-layout dense search
+    uint32_t *fb_list;   // Q, queries the row-layout resolve step leaves open
     uint32_t *counters;  // [0] ring count, [1] dense count, [2] fallback count
     int64_t capacity;    // Q capacity
 };
 
 // device stats block (uint64 counters, same order as riann_stats_t after `frames`)
 enum StatSlot {
-    ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING,
+    ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING, ST_FALLBACK,
     ST_COUNT
 };
 
@@ -120,13 +122,12 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // device-side count.  Reads the query patches written by launch_extract.
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st);
-// Row-layout dense search (D <= 96).  Queries of the dense list (or all of an
-// all_full batch) are answered directly; the rare queries whose minimum is
-// attained with equal Y in two different tiles are appended to w.fb_list
-// (count w.counters[2]) for launch_dense_list.
+// Row-layout dense search (D <= 96): the row kernel, the resolve kernel and
+// the exhaustive search of the rare queries it cannot resolve (w.fb_list,
+// count w.counters[2], which must start at 0; counted in ST_FALLBACK).
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                             hipStream_t st);
+                             unsigned long long *stats, hipStream_t st);
 // Column-layout dense search of an explicit list with a device-side count.
 hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              const uint32_t *list, const uint32_t *count, hipStream_t st);

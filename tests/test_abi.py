@@ -43,3 +43,18 @@ def test_host_only_calls():
     p = r.make_params(10, 11, 8, 1, 1)           # more keys than references
     assert r.lib().riann_footprint(ctypes.byref(p), 0, 0, ctypes.byref(out)) == \
         r.RIANN_E_INVALID
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not load a second HIP
+    runtime beside torch's (the library binds to the one torch loads)."""
+    import subprocess
+    import sys
+    code = ("import paper_1508_07953_amd, torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -187,6 +187,10 @@ def test_ties_and_constant_frame(torch_dev, riann, flags):
         torch.cuda.synchronize()
         bi, bd = check_exact(out, ssd, P, ref, "full ties")
         assert bi[0] == 7 and bd[0] == 0
+        # equal minima in three tiles (7, 100, 250) leave the row layout's
+        # tile-resolve step undecided: those queries take its fallback
+        fbk = idx.stats()["dense_fallback"]
+        assert (fbk == 0) if flags else (fbk > 0)
         hq, wq = oracle.field_shape(20, 24, 8, 1)
         assert bi[10 * wq + 14] == 3 and bd[10 * wq + 14] == 0   # lowest of 3, 150, 200
         prev = np.full((hq, wq), 250, np.int32)
@@ -416,9 +420,9 @@ def test_row_and_column_dense_agree_everywhere(torch_dev, riann, name):
     print_case(f"row vs column dense {name}")
     wl = gen.make_workload(name, frames=2)
     a = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
-                          stride=wl.stride, flags=riann.FLAG_ROW_DENSE)
-    b = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
                           stride=wl.stride)
+    b = riann.Index.build(wl.ref, wl.keys, patch=wl.patch, channels=wl.channels,
+                          stride=wl.stride, flags=riann.FLAG_COLUMN_DENSE)
     f = wl.frame(1)
     fd = to_dev(torch, dev, f)
     oa, sa = a.full_search(fd)
@@ -455,4 +459,39 @@ def test_tuned_threshold_keeps_results(torch_dev, riann, tmp_path, monkeypatch):
     idx.set_dense_threshold(7)
     r2 = tune.tune_threshold(idx, [f[1]], [p0])
     assert r2["cached"] and idx.params.dense_threshold == r["threshold"]
+    idx.close()
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_minimum_split_over_two_tiles(torch_dev, riann, flags):
+    """References whose SSDs to a query differ by one share the row layout's
+    half-distance Y; placed in different tiles they must be resolved across
+    both tiles (and at equal SSD the lower index wins)."""
+    torch, dev = torch_dev
+    print_case(f"two-tile minimum flags={flags}")
+    rng = np.random.default_rng(23)
+    n = 600
+    ref = rng.integers(0, 256, (n, 64), dtype=np.uint8)
+    q = rng.integers(20, 236, (4, 64), dtype=np.uint8)
+
+    def near(p, d):                       # SSD(p, near(p, d)) == d for d <= 3
+        r = p.astype(np.int64).copy()
+        r[:d] += 1
+        return r.astype(np.uint8)
+    # query 0: SSD 1 in tile 2, SSD 2 in tile 9; query 1: SSD 2 in tile 3, 3 in tile 12;
+    # query 2: SSD 0 in tiles 5 and 17 (exact tie: lower index); query 3: SSD 1 then 0
+    plan = [(0, 70, 1), (0, 300, 2), (1, 100, 2), (1, 390, 3), (2, 170, 0), (2, 550, 0),
+            (3, 40, 1), (3, 500, 0)]
+    for qi, r, d in plan:
+        ref[r] = near(q[qi], d)
+    f = np.zeros((8, 4 * 8, 1), np.uint8)
+    for qi in range(4):
+        f[:, 8 * qi:8 * qi + 8, 0] = q[qi].reshape(8, 8)
+    P = oracle.extract(f, 8, 1)
+    idx = riann.Index.build(ref, [0, 1, 2], patch=8, channels=1, stride=1, flags=flags)
+    out, ssd = idx.full_search(to_dev(torch, dev, f))
+    torch.cuda.synchronize()
+    bi, bd = check_exact(out, ssd, P, ref, "two-tile")
+    assert list(bi[[0, 8, 16, 24]]) == [70, 100, 170, 500]
+    assert list(bd[[0, 8, 16, 24]]) == [1, 2, 0, 0]
     idx.close()
