@@ -36,6 +36,7 @@ typedef __attribute__((address_space(1))) void glb_void;
 constexpr int kWaves = RIANN_ROWS_WAVES;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kQB = RIANN_ROWS_QB;     // 32-query column blocks per wavefront
+static_assert(kQB >= 2, "the LDS prefetch runs one query block ahead");
 constexpr int kWaveQ = 32 * kQB;
 constexpr int kBlockQ = kWaveQ * kWaves;
 
@@ -108,25 +109,36 @@ struct RowState {
 
     // all tiles of one LDS stage; the MFMA chain of the next query block (or
     // of the next tile's first block) is issued before the current block's
-    // minimum tree, so the matrix core and the VALU overlap
+    // minimum tree, so the matrix core and the VALU overlap.  The next tile's
+    // LDS operands are read one query block ahead.
     __device__ __forceinline__ void stage(const int8_t *lf, const int32_t *lh, uint32_t t0s,
                                           int lane, int grp) {
-        v4i Af[KB];
-        v16i H;
+        v4i Af[2][KB];
+        v16i H[2];
         v16i acc[2];
-        load_tile(lf, lh, 0, lane, grp, Af, H);
-        mma(0, Af, H, acc[0]);
+        load_tile(lf, lh, 0, lane, grp, Af[0], H[0]);
+        mma(0, Af[0], H[0], acc[0]);
 #pragma unroll
         for (int u = 0; u < ST; ++u) {
+            const int cur = u & 1;
 #pragma unroll
             for (int qb = 0; qb < kQB; ++qb) {
-                if (qb + 1 < kQB) {
-                    mma(qb + 1, Af, H, acc[(qb + 1) & 1]);
-                } else if (u + 1 < ST) {
-                    load_tile(lf, lh, u + 1, lane, grp, Af, H);
-                    mma(0, Af, H, acc[0]);
-                }
+                if (qb == kQB - 2 && u + 1 < ST)
+                    load_tile(lf, lh, u + 1, lane, grp, Af[cur ^ 1], H[cur ^ 1]);
+                if (qb + 1 < kQB)
+                    mma(qb + 1, Af[cur], H[cur], acc[(qb + 1) & 1]);
+                else if (u + 1 < ST)
+                    mma(0, Af[cur ^ 1], H[cur ^ 1], acc[0]);
                 track(qb, acc[qb & 1], t0s + (uint32_t)u);
+                // one MFMA, then half of the tree, then the chain's second
+                // MFMA and the rest: the wave keeps issuing VALU work while
+                // each MFMA of the chain executes
+                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, KB - 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
