@@ -61,6 +61,9 @@ def lib():
         L.orc_riann_candidates.argtypes = [u8p, u8p, C.c_int64, C.c_int, i32p, C.c_int,
                                            u32p, i32p, u32p, C.c_int32, i32p, C.c_int64]
         L.orc_riann_candidates.restype = C.c_int64
+        L.orc_reconstruct.argtypes = [i32p, C.c_int, C.c_int, u8p, C.c_int, C.c_int, C.c_int,
+                                      C.c_int, C.c_int, u32p, u32p, C.POINTER(C.c_float),
+                                      u8p, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -108,6 +111,31 @@ def brute_force(patches: np.ndarray, ref: np.ndarray) -> Tuple[np.ndarray, np.nd
     lib().orc_bf(_p(q, C.c_uint8), Q, _p(r, C.c_uint8), r.shape[0], D,
                  _p(idx, C.c_int32), _p(d, C.c_uint32))
     return idx, d
+
+
+def reconstruct(field: np.ndarray, app: np.ndarray, p: int, s: int, H: int, W: int,
+                gt: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """Average of the matched (or transformed) patches over the frame
+    (Sec. 4): returns f_R (H, W, Ca) float32, the per-pixel sum and count,
+    and, when gt (H, W[, Ca]) uint8 is given, E and its parts."""
+    fld = np.ascontiguousarray(field, np.int32)
+    hq, wq = fld.shape
+    a = np.ascontiguousarray(app, np.uint8)
+    Ca = a.shape[1] // (p * p)
+    assert a.shape[1] == p * p * Ca
+    sm = np.empty((H, W, Ca), np.uint32)
+    cnt = np.empty((H, W), np.uint32)
+    fr = np.empty((H, W, Ca), np.float32)
+    err = np.zeros(4, np.float64)
+    g = None if gt is None else np.ascontiguousarray(gt, np.uint8).reshape(H, W, Ca)
+    lib().orc_reconstruct(_p(fld, C.c_int32), hq, wq, _p(a, C.c_uint8), p, Ca, s, H, W,
+                          _p(sm, C.c_uint32), _p(cnt, C.c_uint32), _p(fr, C.c_float),
+                          _p(g, C.c_uint8), _p(err, C.c_double))
+    out = {"f_r": fr, "sum": sm, "count": cnt}
+    if g is not None:
+        out.update(E=float(err[0]), sq_err=float(err[1]), sq_gt=float(err[2]),
+                   values=int(err[3]))
+    return out
 
 
 def isqrt(x: int) -> int:

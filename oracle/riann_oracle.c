@@ -35,6 +35,11 @@
  *                   smallest ring is scanned and every candidate must lie in
  *                   all K rings; the survivors are checked by exact distance
  *                   and the argmin is returned.
+ *   orc_reconstruct the reconstruction used to judge a field (Sec. 4): every
+ *                   query patch is replaced by its match (or by the caller's
+ *                   transformed version of that reference, Sec. 5) and
+ *                   overlapping patches are averaged; the normalised error
+ *                   E = ||f_GT - f_R|| / ||f_GT|| over the covered pixels.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so riann_oracle.c -lm
  */
@@ -289,4 +294,54 @@ int64_t orc_riann_candidates(const uint8_t *q, const uint8_t *ref, int64_t n, in
         ++cnt;
     }
     return cnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* reconstruction (Sec. 4) and patch replacement (Sec. 5)              */
+/* ------------------------------------------------------------------ */
+/* field: hq x wq match indices; app: n x (p*p*Ca) appearance patches in
+ * (dy, dx, c) order (the references themselves, or their transformed
+ * versions).  Outputs per pixel of the H x W x Ca frame: the sum of the
+ * covering patches' values and how many patches cover it; f_R = sum / count
+ * as float32 (0 where nothing covers).  If gt (H x W x Ca, row pitch
+ * W*Ca) is given, err[0] = E, err[1] = sum (gt - f_R)^2, err[2] = sum gt^2,
+ * err[3] = number of covered values, all over covered pixels only. */
+void orc_reconstruct(const int32_t *field, int hq, int wq, const uint8_t *app, int p, int Ca,
+                     int s, int H, int W, uint32_t *sum, uint32_t *count, float *fr,
+                     const uint8_t *gt, double *err)
+{
+    const int64_t npx = (int64_t)H * W;
+    memset(sum, 0, sizeof(uint32_t) * npx * Ca);
+    memset(count, 0, sizeof(uint32_t) * npx);
+    for (int i = 0; i < hq; ++i)
+        for (int j = 0; j < wq; ++j) {
+            const uint8_t *patch = app + (int64_t)field[(int64_t)i * wq + j] * p * p * Ca;
+            for (int dy = 0; dy < p; ++dy)
+                for (int dx = 0; dx < p; ++dx) {
+                    const int64_t px = (int64_t)(s * i + dy) * W + (s * j + dx);
+                    count[px] += 1;
+                    for (int c = 0; c < Ca; ++c)
+                        sum[px * Ca + c] += patch[(dy * p + dx) * Ca + c];
+                }
+        }
+    double se = 0.0, sg = 0.0, nv = 0.0;
+    for (int64_t px = 0; px < npx; ++px)
+        for (int c = 0; c < Ca; ++c) {
+            const int64_t v = px * Ca + c;
+            if (count[px] == 0) { fr[v] = 0.0f; continue; }
+            fr[v] = (float)sum[v] / (float)count[px];
+            if (gt) {
+                const double g = (double)gt[v];
+                const double d = g - (double)fr[v];
+                se += (g_fault == 8) ? d : d * d;          /* planted: unsquared error */
+                sg += g * g;
+                nv += 1.0;
+            }
+        }
+    if (gt && err) {
+        err[0] = sg > 0.0 ? sqrt(se / sg) : 0.0;
+        err[1] = se;
+        err[2] = sg;
+        err[3] = nv;
+    }
 }

@@ -343,6 +343,60 @@ def test_riann_workload_tiny_frames():
         prev = out["idx"]
 
 
+# ---------------------------------------------------------------- reconstruction
+def test_reconstruct_hand_example():
+    """Sec. 4 reconstruction worked by hand: 3x3 frame, 2x2 patches, stride
+    1, references all-0 and all-4, field [[0, 1], [1, 1]].  Each pixel is the
+    mean of the patches covering it; E against an all-4 frame is
+    sqrt((16 + 4 + 4 + 1) / (9 * 16)) = 5/12."""
+    app = np.array([[0] * 4, [4] * 4], np.uint8)
+    field = np.array([[0, 1], [1, 1]], np.int32)
+    gt = np.full((3, 3), 4, np.uint8)
+    r = oracle.reconstruct(field, app, 2, 1, 3, 3, gt=gt)
+    np.testing.assert_array_equal(r["f_r"][:, :, 0], [[0, 2, 4], [2, 3, 4], [4, 4, 4]])
+    np.testing.assert_array_equal(r["count"], [[1, 2, 1], [2, 4, 2], [1, 2, 1]])
+    assert r["sq_err"] == 25.0 and r["sq_gt"] == 144.0 and r["values"] == 9
+    assert abs(r["E"] - 5.0 / 12.0) < 1e-15
+
+
+@pytest.mark.parametrize("H,W,p,s", [(9, 13, 3, 1), (20, 17, 4, 2), (16, 16, 8, 3), (5, 5, 5, 1)])
+def test_reconstruct_identity_and_coverage(H, W, p, s):
+    """Replacing every patch by itself gives the frame back on every covered
+    pixel (E = 0); the coverage count is the product of the row and column
+    counts #{i : s*i <= y <= s*i + p - 1}."""
+    rng = np.random.default_rng(H * W + p)
+    f = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    P = oracle.extract(f, p, s)
+    hq, wq = oracle.field_shape(H, W, p, s)
+    r = oracle.reconstruct(np.arange(hq * wq, dtype=np.int32).reshape(hq, wq), P, p, s, H, W,
+                           gt=f)
+    cy = np.array([sum(1 for i in range(hq) if s * i <= y <= s * i + p - 1) for y in range(H)])
+    cx = np.array([sum(1 for j in range(wq) if s * j <= x <= s * j + p - 1) for x in range(W)])
+    np.testing.assert_array_equal(r["count"], np.outer(cy, cx))
+    cov = r["count"] > 0
+    np.testing.assert_array_equal(r["f_r"][:, :, 0][cov], f[cov].astype(np.float32))
+    assert np.all(r["f_r"][:, :, 0][~cov] == 0)
+    assert r["E"] == 0.0 and r["values"] == int(cov.sum())
+
+
+def test_reconstruct_transformed_references():
+    """Patch replacement with a transformed reference set (Sec. 5): matching
+    on gray patches, replacing with 3-channel versions whose channel c is
+    (c+1) * value // 4; with every patch matched to itself the output is
+    that transform of the frame, channel by channel."""
+    rng = np.random.default_rng(3)
+    f = rng.integers(0, 256, (12, 10), dtype=np.uint8)
+    P = oracle.extract(f, 4, 2)
+    hq, wq = oracle.field_shape(12, 10, 4, 2)
+    app = np.stack([(P.astype(np.int32) * (c + 1)) // 4 for c in range(3)],
+                   axis=-1).reshape(len(P), -1).astype(np.uint8)
+    r = oracle.reconstruct(np.arange(hq * wq, dtype=np.int32).reshape(hq, wq), app, 4, 2, 12, 10)
+    cov = r["count"] > 0
+    for c in range(3):
+        want = (f.astype(np.int32) * (c + 1)) // 4
+        np.testing.assert_array_equal(r["f_r"][:, :, c][cov], want[cov].astype(np.float32))
+
+
 # ---------------------------------------------------------------- planted faults
 def _pins_pass():
     """Cheap versions of the pins above; True when all hold."""
@@ -356,12 +410,13 @@ def _pins_pass():
         test_tables_hand()
         test_riann_hand()
         test_riann_equals_brute_force(10, 6, "random")
+        test_reconstruct_hand_example()
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_planted_faults(fault):
     assert _pins_pass()
     oracle.set_fault(fault)
