@@ -298,6 +298,25 @@ def main():
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
                                           for k, v in prof.items() if v["launches"]}
+    # reconstruction of the last timed frame from its field (Sec. 4), with E
+    rf, rg = bufs[cur], frames[W + K]
+    out_r, err_r = idx.reconstruct(rf, H, Wd, gt=rg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 20
+    e0.record(stream)
+    for _ in range(nrep):
+        idx.reconstruct(rf, H, Wd, gt=rg, out=out_r)
+    e1.record(stream)
+    e1.synchronize()
+    ms_r = e0.elapsed_time(e1) / nrep
+    Cc = wl.channels
+    rbytes = Q * 4 + H * Wd * Cc * (1 + 4) + int(idx.params.n_ref) * wl.D
+    result["reconstruct"] = {"ms": ms_r, "E": float(err_r[0].item()),
+                             "algorithmic_bytes": rbytes,
+                             "GBps": rbytes / (ms_r * 1e-3) / 1e9,
+                             "note": "field 4 B/query + frame 1 B and output 4 B per value + "
+                                     "appearance set once; gathers served by L2"}
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)

@@ -190,6 +190,35 @@ riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *desc
 riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W,
                                int64_t *bytes);
 
+/*
+ * riann_reconstruct -- rebuild a frame from its ANN field (Sec. 4: replace
+ * every query patch by its match and average overlapping patches) or apply a
+ * transformation through the field (Sec. 5: replace every query patch by the
+ * transformed version of its match, T(R) computed by the caller).
+ *   field         device, Hq x Wq int32 field of an H x W frame (Hq, Wq from
+ *                 the index's patch and stride, as for riann_match_frame);
+ *                 entries outside [0, n) contribute no patch
+ *   app           device, n x (p*p*app_channels) uint8 appearance patches in
+ *                 (dy, dx, c) order, or NULL for the index's own references
+ *   app_channels  1..4; must equal the index's channels when app is NULL
+ *   out           device, H x W x app_channels float32:
+ *                 out = (sum of the covering patches' values) / (their count),
+ *                 one float division; 0 where no patch covers the pixel (right
+ *                 and bottom borders when the stride does not reach them)
+ *   gt, gt_pitch  device H x W x app_channels uint8 with a row pitch in bytes,
+ *                 or NULL; the reference frame for the error
+ *   err           device, 4 doubles, or NULL (requires gt): {E, sum (gt-out)^2,
+ *                 sum gt^2, number of values}, over covered pixels, with the
+ *                 normalised error E = sqrt(err[1] / err[2]) (0 if err[2] = 0),
+ *                 reduced in a fixed order (deterministic)
+ * Asynchronous on hip_stream.  out must not overlap the inputs.  The first
+ * call with err on a stream (or a larger frame) allocates a small scratch.
+ */
+riann_status_t riann_reconstruct(riann_index_t h, const int32_t *field, int32_t H, int32_t W,
+                                 const uint8_t *app, int32_t app_channels, float *out,
+                                 const uint8_t *gt, int64_t gt_pitch, double *err,
+                                 void *hip_stream);
+
 /* riann_get_stats -- synchronises the device and copies the counters. */
 riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s);
 riann_status_t riann_reset_stats(riann_index_t h);

@@ -35,7 +35,8 @@ FLAG_COLUMN_DENSE = 1
 EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
-           "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold"]
+           "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
+           "riann_reconstruct"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -94,6 +95,7 @@ def _load():
     L.riann_set_profiling.argtypes = [vp, C.c_int]
     L.riann_set_dense_threshold.argtypes = [vp, i64]
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
+    L.riann_reconstruct.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp]
     L.riann_last_error.argtypes = []
     L.riann_last_error.restype = C.c_char_p
     L.riann_version.argtypes = []
@@ -243,6 +245,38 @@ class Index:
         _check(_lib.riann_full_search(self._h, frame.data_ptr(), H, W, pitch, out.data_ptr(),
                                       ssd.data_ptr(), _stream_ptr(stream)))
         return out, ssd
+
+    def reconstruct(self, field, H: int, W: int, app=None, gt=None, out=None, with_error=True,
+                    stream=None):
+        """Frame rebuilt from `field` (Sec. 4): every query patch replaced by
+        its match -- or by row field[i, j] of `app`, an (n, p*p*Ca) uint8
+        device tensor of transformed references (Sec. 5) -- and overlapping
+        patches averaged.  Returns (out (H, W, Ca) float32, err) where err is
+        a device float64 tensor {E, sum (gt-out)^2, sum gt^2, values} when
+        `gt` (H, W[, Ca] uint8 device frame) is given and with_error, else None."""
+        import torch
+        p = self.params
+        if field.dtype != torch.int32 or not field.is_cuda or not field.is_contiguous():
+            raise TypeError("field must be a contiguous int32 device tensor")
+        if app is not None:
+            if app.dtype != torch.uint8 or not app.is_cuda or not app.is_contiguous():
+                raise TypeError("app must be a contiguous uint8 device tensor")
+            ca = app.shape[1] // (p.patch * p.patch)
+        else:
+            ca = p.channels
+        gp = 0
+        if gt is not None:
+            _, _, gp = _frame_geom(gt, ca)
+        if out is None:
+            out = torch.empty((H, W, ca), dtype=torch.float32, device=field.device)
+        err = (torch.empty(4, dtype=torch.float64, device=field.device)
+               if gt is not None and with_error else None)
+        _check(_lib.riann_reconstruct(self._h, field.data_ptr(), H, W,
+                                      app.data_ptr() if app is not None else None, ca,
+                                      out.data_ptr(), gt.data_ptr() if gt is not None else None,
+                                      gp, err.data_ptr() if err is not None else None,
+                                      _stream_ptr(stream)))
+        return out, err
 
     def match_batch(self, items: List[dict], stream=None) -> None:
         """items: dicts with frame, out, ssd (optional), prev (optional), mode."""

@@ -37,6 +37,7 @@ struct riann_index {
     std::atomic<uint64_t> frames{0}, full_queries{0};
     std::mutex mu;
     std::map<hipStream_t, Work> work;
+    std::map<hipStream_t, std::pair<double *, int64_t>> recon_scratch;  // partials, blocks
     // kernel timing (riann_set_profiling)
     std::atomic<bool> profiling{false};
     std::mutex pmu;
@@ -284,6 +285,7 @@ void free_index(riann_index *h) {
         (void)hipEventDestroy(p.b);
     }
     for (auto &kv : h->work) (void)hipFree(kv.second.patches);
+    for (auto &kv : h->recon_scratch) (void)hipFree(kv.second.first);
     if (h->dmem) (void)hipFree(h->dmem);
     delete h;
 }
@@ -747,6 +749,53 @@ riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
         out->launches[k] = h->prof_launches[k];
         out->ms[k] = h->prof_ms[k];
     }
+    return RIANN_OK;
+}
+
+riann_status_t riann_reconstruct(riann_index_t h, const int32_t *field, int32_t H, int32_t W,
+                                 const uint8_t *app, int32_t app_channels, float *out,
+                                 const uint8_t *gt, int64_t gt_pitch, double *err,
+                                 void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (!field || !out) return fail(RIANN_E_INVALID, "field and out are required");
+    const int p = h->prm.patch, s = h->prm.stride;
+    if (H < p || W < p) return fail(RIANN_E_INVALID, "frame smaller than one patch");
+    if (app_channels < 1 || app_channels > 4)
+        return fail(RIANN_E_INVALID, "app_channels must be in [1, 4]");
+    if (!app && app_channels != h->prm.channels)
+        return fail(RIANN_E_INVALID, "without app, app_channels must equal the index's channels");
+    if (err && !gt) return fail(RIANN_E_INVALID, "err needs gt");
+    if (gt && gt_pitch < (int64_t)W * app_channels)
+        return fail(RIANN_E_INVALID, "gt_pitch smaller than a row");
+    const int hq = (H - p) / s + 1, wq = (W - p) / s + 1;
+    const size_t nout = (size_t)H * W * app_channels * sizeof(float);
+    if (overlap(out, nout, field, (size_t)hq * wq * 4) ||
+        (app && overlap(out, nout, app, (size_t)h->n * p * p * app_channels)) ||
+        (gt && overlap(out, nout, gt, (size_t)(H - 1) * gt_pitch + (size_t)W * app_channels)))
+        return fail(RIANN_E_INVALID, "out overlaps an input");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DeviceGuard g(h->device);
+    ReconArgs ra{field, hq, wq, H, W, app_channels, app, out, gt, gt_pitch, nullptr};
+    if (err) {
+        const int64_t nb = recon_blocks(H, W);
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto &sc = h->recon_scratch[st];
+        if (sc.second < nb) {
+            if (sc.first) {
+                hipError_t e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return hip_fail(e, "stream sync");
+                (void)hipFree(sc.first);
+                sc = {nullptr, 0};
+            }
+            void *pp = nullptr;
+            if (hipMalloc(&pp, (size_t)nb * 3 * sizeof(double)) != hipSuccess)
+                return fail(RIANN_E_NOMEM, "hipMalloc of reconstruction scratch failed");
+            sc = {(double *)pp, nb};
+        }
+        ra.partials = sc.first;
+    }
+    hipError_t e = launch_recon(h->dix, ra, err, st);
+    if (e != hipSuccess) return hip_fail(e, "k_recon launch");
     return RIANN_OK;
 }
 

@@ -16,6 +16,7 @@ namespace riann {
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
 constexpr int kRefAlign = 512;   // n is padded to whole 16-tile dense stages
 constexpr int kMaxKeys = 64;
+constexpr int kMaxPatch = 16;    // p <= 16 (D = p*p*C <= 256)
 
 // Dense-search key of a (query, reference) pair, unsigned 32-bit:
 //   X   = SSD - Qc + bias = Rc + 2<a, v> + bias,  bias = D * 16384 >= max Qc
@@ -128,6 +129,23 @@ hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              unsigned long long *stats, hipStream_t st);
+// Frame reconstruction (k_recon.hip): out = average of the appearance patches
+// field[i][j] over the patches covering each pixel; app == nullptr uses the
+// index's references (Ca == C).  With gt and partials set, one fp64 partial
+// {sum (gt - out)^2, sum gt^2, values} per block is written and reduced into
+// err[0..3] = {E, sum (gt - out)^2, sum gt^2, values}.
+struct ReconArgs {
+    const int32_t *field;   // Hq x Wq
+    int Hq, Wq, H, W, Ca;
+    const uint8_t *app;     // n x (p*p*Ca) or nullptr
+    float *out;             // H x W x Ca
+    const uint8_t *gt;      // H x W x Ca with row pitch gt_pitch, or nullptr
+    int64_t gt_pitch;
+    double *partials;       // 3 per block, or nullptr (no error)
+};
+int64_t recon_blocks(int H, int W);
+hipError_t launch_recon(const DevIndex &ix, const ReconArgs &ra, double *err, hipStream_t st);
+
 // Column-layout dense search of an explicit list with a device-side count.
 hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              const uint32_t *list, const uint32_t *count, hipStream_t st);
