@@ -61,6 +61,8 @@ def lib():
         L.orc_riann_candidates.argtypes = [u8p, u8p, C.c_int64, C.c_int, i32p, C.c_int,
                                            u32p, i32p, u32p, C.c_int32, i32p, C.c_int64]
         L.orc_riann_candidates.restype = C.c_int64
+        L.orc_extract3d.argtypes = [C.POINTER(u8p), C.c_int, C.c_int, C.c_int, C.c_int,
+                                    C.c_int, C.c_int, u8p]
         L.orc_reconstruct.argtypes = [i32p, C.c_int, C.c_int, u8p, C.c_int, C.c_int, C.c_int,
                                       C.c_int, C.c_int, u32p, u32p, C.POINTER(C.c_float),
                                       u8p, C.POINTER(C.c_double)]
@@ -92,6 +94,20 @@ def extract(frame: np.ndarray, p: int, s: int) -> np.ndarray:
     hq, wq = field_shape(H, W, p, s)
     out = np.empty((hq * wq, p * p * Cc), np.uint8)
     lib().orc_extract(_p(f, C.c_uint8), H, W, Cc, W * Cc, p, s, _p(out, C.c_uint8))
+    return out
+
+
+def extract3d(frames, p: int, s: int) -> np.ndarray:
+    """T frames (each (H, W) or (H, W, C) uint8, oldest first) ->
+    (Hq*Wq, p*p*T*C) spatio-temporal patches, (dy, dx, t, c) order."""
+    fs = [np.ascontiguousarray(f if f.ndim == 3 else f[:, :, None], np.uint8) for f in frames]
+    H, W, Cc = fs[0].shape
+    assert all(f.shape == fs[0].shape for f in fs)
+    T = len(fs)
+    hq, wq = field_shape(H, W, p, s)
+    out = np.empty((hq * wq, p * p * T * Cc), np.uint8)
+    ptrs = (C.POINTER(C.c_uint8) * T)(*[_p(f, C.c_uint8) for f in fs])
+    lib().orc_extract3d(ptrs, T, H, W, Cc, p, s, _p(out, C.c_uint8))
     return out
 
 

@@ -35,6 +35,9 @@
  *                   smallest ring is scanned and every candidate must lie in
  *                   all K rings; the survivors are checked by exact distance
  *                   and the argmin is returned.
+ *   orc_extract3d   spatio-temporal query patches (the 3D extension noted in
+ *                   Sec. 1): p x p windows of T consecutive frames, flattened
+ *                   in (dy, dx, t, c) order.
  *   orc_reconstruct the reconstruction used to judge a field (Sec. 4): every
  *                   query patch is replaced by its match (or by the caller's
  *                   transformed version of that reference, Sec. 5) and
@@ -294,6 +297,27 @@ int64_t orc_riann_candidates(const uint8_t *q, const uint8_t *ref, int64_t n, in
         ++cnt;
     }
     return cnt;
+}
+
+/* frames: T separate H x W x C frames (oldest first), each with row pitch
+ * W*C; out: Hq*Wq patches of p*p*T*C bytes in (dy, dx, t, c) order. */
+void orc_extract3d(const uint8_t *const *frames, int T, int H, int W, int C, int p, int s,
+                   uint8_t *out)
+{
+    int hq = (H - p) / s + 1, wq = (W - p) / s + 1;
+    int64_t D = (int64_t)p * p * T * C;
+    for (int qy = 0; qy < hq; ++qy)
+        for (int qx = 0; qx < wq; ++qx) {
+            uint8_t *q = out + ((int64_t)qy * wq + qx) * D;
+            int64_t k = 0;
+            for (int dy = 0; dy < p; ++dy)
+                for (int dx = 0; dx < p; ++dx)
+                    for (int t = 0; t < T; ++t)
+                        for (int c = 0; c < C; ++c) {
+                            int tt = (g_fault == 9) ? T - 1 - t : t;   /* planted: time reversed */
+                            q[k++] = frames[tt][((int64_t)(qy * s + dy) * W + (qx * s + dx)) * C + c];
+                        }
+        }
 }
 
 /* ------------------------------------------------------------------ */

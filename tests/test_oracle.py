@@ -343,6 +343,28 @@ def test_riann_workload_tiny_frames():
         prev = out["idx"]
 
 
+# ---------------------------------------------------------------- 3D patches
+def test_extract3d_position_code():
+    """Spatio-temporal patches: frame t holds the value 50*t + (y*W + x) % 50
+    at (y, x), so every byte names its frame and position; checked against
+    the definition element by element, with T = 1 reducing to the 2D case."""
+    H, W, T, p, s = 9, 11, 3, 3, 2
+    yy, xx = np.mgrid[0:H, 0:W]
+    frames = [((50 * t + (yy * W + xx) % 50) % 256).astype(np.uint8) for t in range(T)]
+    P = oracle.extract3d(frames, p, s)
+    hq, wq = oracle.field_shape(H, W, p, s)
+    assert P.shape == (hq * wq, p * p * T)
+    for q in (0, 5, hq * wq - 1):
+        i, j = divmod(q, wq)
+        k = 0
+        for dy in range(p):
+            for dx in range(p):
+                for t in range(T):
+                    assert P[q, k] == frames[t][s * i + dy, s * j + dx]
+                    k += 1
+    np.testing.assert_array_equal(oracle.extract3d(frames[:1], p, s), oracle.extract(frames[0], p, s))
+
+
 # ---------------------------------------------------------------- reconstruction
 def test_reconstruct_hand_example():
     """Sec. 4 reconstruction worked by hand: 3x3 frame, 2x2 patches, stride
@@ -411,12 +433,13 @@ def _pins_pass():
         test_riann_hand()
         test_riann_equals_brute_force(10, 6, "random")
         test_reconstruct_hand_example()
+        test_extract3d_position_code()
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_planted_faults(fault):
     assert _pins_pass()
     oracle.set_fault(fault)
