@@ -35,6 +35,15 @@
  *             stream and return; argument errors are reported synchronously;
  *             a device fault surfaces as RIANN_E_DEVICE from the next call
  *             that synchronises (riann_get_stats, riann_save, riann_destroy).
+ *   graphs    match / full_search / batch calls can be captured into a HIP
+ *             graph: the first call on a stream (or one with more queries
+ *             than any before) allocates that stream's scratch, and later
+ *             calls of up to that size allocate nothing, synchronise nothing
+ *             and clear their counters with a kernel, not a memset.  Warm the
+ *             capture stream with one call, then capture; a replay re-reads
+ *             the captured frame/prev buffers and rewrites out/ssd.  The
+ *             host-side frame counter of riann_get_stats counts the capture,
+ *             not the replays.
  *   ownership the index owns device copies of the reference set and its
  *             tables; the caller owns frames and fields.
  *   threads   one index may be used from several host threads and streams at
@@ -189,6 +198,22 @@ riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *desc
  */
 riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W,
                                int64_t *bytes);
+
+/*
+ * riann_stack_frames -- spatio-temporal patches (the 3D extension of Sec. 1).
+ * Interleaves T frames into one H x W x (T*C) frame whose channel t*C + c is
+ * channel c of frames[t], so that a p x p patch of the result is the
+ * p x p x T space-time patch in (dy, dx, t, c) order.  An index built with
+ * channels = T*C on such patches then matches space-time patches with every
+ * other call unchanged.
+ *   frames  host array of T device pointers (oldest first), each H x W x C
+ *           uint8 with row pitch `pitch` bytes; 1 <= T <= 16
+ *   out     device, H x W x (T*C) uint8, rows contiguous (pitch W*T*C); must
+ *           not overlap any input frame
+ * Asynchronous on hip_stream.  No index is needed.
+ */
+riann_status_t riann_stack_frames(const uint8_t *const *frames, int32_t T, int32_t H, int32_t W,
+                                  int32_t C, int64_t pitch, uint8_t *out, void *hip_stream);
 
 /*
  * riann_reconstruct -- rebuild a frame from its ANN field (Sec. 4: replace

@@ -36,7 +36,7 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
-           "riann_reconstruct"]
+           "riann_reconstruct", "riann_stack_frames"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -96,6 +96,7 @@ def _load():
     L.riann_set_dense_threshold.argtypes = [vp, i64]
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
     L.riann_reconstruct.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp]
+    L.riann_stack_frames.argtypes = [C.POINTER(vp), i32, i32, i32, i32, i64, vp, vp]
     L.riann_last_error.argtypes = []
     L.riann_last_error.restype = C.c_char_p
     L.riann_version.argtypes = []
@@ -155,6 +156,26 @@ def _frame_geom(frame, channels: int):
     if frame.stride(2) != 1 or frame.stride(1) != channels:
         raise ValueError("frame rows must be contiguous (H, W, C) with C innermost")
     return int(frame.shape[0]), int(frame.shape[1]), int(frame.stride(0))
+
+
+def stack_frames(frames, out=None, stream=None):
+    """T device frames (each (H, W) or (H, W, C) uint8, oldest first) -> one
+    (H, W, T*C) frame whose p x p patches are the p x p x T space-time
+    patches in (dy, dx, t, c) order (riann_stack_frames)."""
+    import torch
+    T = len(frames)
+    if T < 1:
+        raise ValueError("need at least one frame")
+    C0 = 1 if frames[0].dim() == 2 else int(frames[0].shape[2])
+    geo = [_frame_geom(f, C0) for f in frames]
+    H, W, pitch = geo[0]
+    if any(g != geo[0] for g in geo):
+        raise ValueError("frames must share shape and row pitch")
+    if out is None:
+        out = torch.empty((H, W, T * C0), dtype=torch.uint8, device=frames[0].device)
+    arr = (C.c_void_p * T)(*[f.data_ptr() for f in frames])
+    _check(_lib.riann_stack_frames(arr, T, H, W, C0, pitch, out.data_ptr(), _stream_ptr(stream)))
+    return out
 
 
 class Index:

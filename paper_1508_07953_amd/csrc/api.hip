@@ -80,6 +80,10 @@ riann_status_t check_params(const riann_params_t *p) {
         return fail(RIANN_E_INVALID, "patch, channels and stride must be >= 1");
     const int64_t D = (int64_t)p->patch * p->patch * p->channels;
     if (D > 256) return fail(RIANN_E_UNSUPPORTED, "patch dimension p*p*C must be <= 256");
+    // the extraction kernel stages a (kExtTY - 1)s + p by (kExtTX - 1)s + p pixel window
+    if ((int64_t)((kExtTY - 1) * (int64_t)p->stride + p->patch) *
+            ((kExtTX - 1) * (int64_t)p->stride + p->patch) * p->channels > 65536)
+        return fail(RIANN_E_UNSUPPORTED, "stride too large for the extraction tile");
     if (p->n_ref < 1 || p->n_ref > (int64_t)0x7FFFFF00)
         return fail(RIANN_E_INVALID, "n_ref must be in [1, 2^31 - 256]");
     if (p->n_keys < 0 || p->n_keys > kMaxKeys)
@@ -749,6 +753,25 @@ riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
         out->launches[k] = h->prof_launches[k];
         out->ms[k] = h->prof_ms[k];
     }
+    return RIANN_OK;
+}
+
+riann_status_t riann_stack_frames(const uint8_t *const *frames, int32_t T, int32_t H, int32_t W,
+                                  int32_t C, int64_t pitch, uint8_t *out, void *hip_stream) {
+    if (!frames || !out) return fail(RIANN_E_INVALID, "frames and out are required");
+    if (T < 1 || T > kMaxStack) return fail(RIANN_E_INVALID, "T must be in [1, 16]");
+    if (H < 1 || W < 1 || C < 1) return fail(RIANN_E_INVALID, "H, W and C must be >= 1");
+    if (pitch < (int64_t)W * C) return fail(RIANN_E_INVALID, "pitch smaller than a row");
+    StackArgs sa{};
+    const size_t nout = (size_t)H * W * T * C, nin = (size_t)(H - 1) * pitch + (size_t)W * C;
+    for (int t = 0; t < T; ++t) {
+        if (!frames[t]) return fail(RIANN_E_INVALID, "NULL frame pointer");
+        if (overlap(out, nout, frames[t], nin)) return fail(RIANN_E_INVALID, "out overlaps a frame");
+        sa.f[t] = frames[t];
+    }
+    sa.T = T; sa.H = H; sa.W = W; sa.C = C; sa.pitch = pitch; sa.out = out;
+    hipError_t e = launch_stack(sa, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "k_stack launch");
     return RIANN_OK;
 }
 

@@ -101,4 +101,28 @@ hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &
     }
 }
 
+namespace {
+
+// One thread per (pixel, byte of the stacked pixel): reads are contiguous per
+// source frame row, writes contiguous in the output row.
+__global__ __launch_bounds__(256) void k_stack(StackArgs sa) {
+    const int TC = sa.T * sa.C;
+    const int64_t row = (int64_t)sa.W * TC;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    if (k >= row) return;
+    const int x = (int)(k / TC), tc = (int)(k - (int64_t)x * TC);
+    const int t = tc / sa.C, c = tc - t * sa.C;
+    sa.out[(int64_t)y * row + k] = sa.f[t][(int64_t)y * sa.pitch + (int64_t)x * sa.C + c];
+}
+
+}  // namespace
+
+hipError_t launch_stack(const StackArgs &sa, hipStream_t st) {
+    const int64_t row = (int64_t)sa.W * sa.T * sa.C;
+    hipLaunchKernelGGL(k_stack, dim3((unsigned)((row + 255) / 256), (unsigned)sa.H), dim3(256), 0,
+                       st, sa);
+    return hipGetLastError();
+}
+
 }  // namespace riann

@@ -129,6 +129,17 @@ hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              unsigned long long *stats, hipStream_t st);
+// T planar frames (each H x W x C, common row pitch) -> one H x W x (T*C)
+// frame whose channel t*C + c is channel c of frame t (k_extract.hip).
+constexpr int kMaxStack = 16;
+struct StackArgs {
+    const uint8_t *f[kMaxStack];
+    int T, H, W, C;
+    int64_t pitch;
+    uint8_t *out;
+};
+hipError_t launch_stack(const StackArgs &sa, hipStream_t st);
+
 // Frame reconstruction (k_recon.hip): out = average of the appearance patches
 // field[i][j] over the patches covering each pixel; app == nullptr uses the
 // index's references (Ca == C).  With gt and partials set, one fp64 partial

@@ -495,3 +495,34 @@ def test_minimum_split_over_two_tiles(torch_dev, riann, flags):
     assert list(bi[[0, 8, 16, 24]]) == [70, 100, 170, 500]
     assert list(bd[[0, 8, 16, 24]]) == [1, 2, 0, 0]
     idx.close()
+
+
+def test_spatiotemporal_patches(torch_dev, riann):
+    """p x p x T space-time patches (the 3D extension of Sec. 1): frames
+    t-2..t stacked on the device, matched by an index over 3D reference
+    patches, equal the oracle's brute force over its own 3D extraction."""
+    torch, dev = torch_dev
+    print_case("space-time patches T=3")
+    T, p = 3, 6
+    wl = gen.make_workload("tiny", frames=6)
+    other = gen.make_video("tiny", frames=T, second=True)
+    R3 = oracle.extract3d([other.frame(t) for t in range(T)], p, 1)
+    rng = np.random.default_rng(31)
+    ref = R3[np.sort(rng.choice(len(R3), 700, replace=False))]
+    keys = np.sort(rng.choice(len(ref), 6, replace=False))
+    idx = riann.Index.build(ref, keys, patch=p, channels=T, stride=1)
+    frames = [to_dev(torch, dev, wl.frame(t)) for t in range(6)]
+    prev = None
+    for t in range(T - 1, 6):
+        st = riann.stack_frames(frames[t - T + 1:t + 1])
+        torch.cuda.synchronize()
+        want_stack = np.stack([wl.frame(k)[:, :, 0] for k in range(t - T + 1, t + 1)], axis=-1)
+        assert np.array_equal(st.cpu().numpy(), want_stack)
+        if prev is None:
+            out, ssd = idx.full_search(st)
+        else:
+            out, ssd = idx.match_frame(st, prev=prev)
+        P = oracle.extract3d([wl.frame(k) for k in range(t - T + 1, t + 1)], p, 1)
+        check_exact(out, ssd, P, ref, f"3D t={t}")
+        prev = out.clone()
+    idx.close()
