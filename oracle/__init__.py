@@ -61,6 +61,9 @@ def lib():
         L.orc_riann_candidates.argtypes = [u8p, u8p, C.c_int64, C.c_int, i32p, C.c_int,
                                            u32p, i32p, u32p, C.c_int32, i32p, C.c_int64]
         L.orc_riann_candidates.restype = C.c_int64
+        L.orc_knn_bf.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int, C.c_int, i32p, u32p]
+        L.orc_knn_riann.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int, i32p, C.c_int,
+                                    u32p, i32p, u32p, i32p, C.c_int, i32p, u32p]
         L.orc_extract3d.argtypes = [C.POINTER(u8p), C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_int, u8p]
         L.orc_reconstruct.argtypes = [i32p, C.c_int, C.c_int, u8p, C.c_int, C.c_int, C.c_int,
@@ -154,6 +157,20 @@ def reconstruct(field: np.ndarray, app: np.ndarray, p: int, s: int, H: int, W: i
     return out
 
 
+def knn_brute_force(patches: np.ndarray, ref: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Exact k nearest neighbours of each patch: (Q, k) idx int32 and ssd
+    uint32, each row ascending by (SSD, index)."""
+    q = np.ascontiguousarray(patches, np.uint8)
+    r = np.ascontiguousarray(ref, np.uint8)
+    Q, D = q.shape
+    assert 1 <= k <= min(64, r.shape[0])
+    idx = np.empty((Q, k), np.int32)
+    d = np.empty((Q, k), np.uint32)
+    lib().orc_knn_bf(_p(q, C.c_uint8), Q, _p(r, C.c_uint8), r.shape[0], D, k,
+                     _p(idx, C.c_int32), _p(d, C.c_uint32))
+    return idx, d
+
+
 def isqrt(x: int) -> int:
     return int(lib().orc_isqrt(C.c_uint64(x)))
 
@@ -200,6 +217,20 @@ class Tables:
                         _p(out["kstar"], C.c_int32), _p(out["nsurv"], C.c_int64),
                         _p(out["noprior"], C.c_uint8))
         return out
+
+    def knn(self, patches: np.ndarray, prev: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
+        """Exact-mode RIANN k-NN with previous k-NN matches `prev` (Q, k)."""
+        q = np.ascontiguousarray(patches, np.uint8)
+        pv = np.ascontiguousarray(prev, np.int32).reshape(-1)
+        Q = q.shape[0]
+        assert pv.size == Q * k and q.shape[1] == self.D and 1 <= k <= min(64, self.n)
+        idx = np.empty((Q, k), np.int32)
+        d = np.empty((Q, k), np.uint32)
+        lib().orc_knn_riann(_p(q, C.c_uint8), Q, _p(self.ref, C.c_uint8), self.n, self.D,
+                            _p(self.keys, C.c_int32), self.K, _p(self.T, C.c_uint32),
+                            _p(self.P, C.c_int32), _p(self.Piv, C.c_uint32), _p(pv, C.c_int32),
+                            k, _p(idx, C.c_int32), _p(d, C.c_uint32))
+        return idx, d
 
     def candidates(self, patch: np.ndarray, prev: int) -> np.ndarray:
         q = np.ascontiguousarray(patch, np.uint8).reshape(-1)

@@ -35,6 +35,11 @@
  *                   smallest ring is scanned and every candidate must lie in
  *                   all K rings; the survivors are checked by exact distance
  *                   and the argmin is returned.
+ *   orc_knn_bf      exact k nearest neighbours by exhaustive search, in
+ *                   ascending (SSD, index) order.
+ *   orc_knn_riann   the same search with k-NN rings: the radius is the
+ *                   largest distance to the k previous matches, so the k
+ *                   nearest lie inside every ring (exact k-NN fields).
  *   orc_extract3d   spatio-temporal query patches (the 3D extension noted in
  *                   Sec. 1): p x p windows of T consecutive frames, flattened
  *                   in (dy, dx, t, c) order.
@@ -258,6 +263,99 @@ void orc_riann(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int 
         if (kstar) kstar[i] = bk;
         if (nsurv) nsurv[i] = cnt;
         if (noprior) noprior[i] = (uint8_t)np;
+        free(lo);
+        free(hi);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* exact k nearest neighbours                                          */
+/* ------------------------------------------------------------------ */
+/* Insert (d, r) into the ascending list (bd, br) of length kk, keeping the k
+ * smallest by (distance, index). */
+static void orc_topk_insert(uint64_t *bd, int64_t *br, int kk, uint64_t d, int64_t r)
+{
+    int pos = kk;
+    while (pos > 0 && (d < bd[pos - 1] || (d == bd[pos - 1] && r < br[pos - 1]))) --pos;
+    if (pos >= kk) return;
+    for (int j = kk - 1; j > pos; --j) { bd[j] = bd[j - 1]; br[j] = br[j - 1]; }
+    bd[pos] = d;
+    br[pos] = r;
+}
+
+/* idx/ssd: Q x k, each row ascending by (SSD, index); k <= n. */
+void orc_knn_bf(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int D, int k,
+                int32_t *idx, uint32_t *ssd)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < Q; ++i) {
+        uint64_t bd[64];
+        int64_t br[64];
+        for (int j = 0; j < k; ++j) { bd[j] = ORC_INF; br[j] = -1; }
+        for (int64_t r = 0; r < n; ++r)
+            orc_topk_insert(bd, br, k, orc_ssd(qp + i * D, ref + r * D, D), r);
+        for (int j = 0; j < k; ++j) {
+            idx[i * k + j] = (int32_t)br[j];
+            ssd[i * k + j] = (uint32_t)bd[j];
+        }
+    }
+}
+
+/* Exact-mode RIANN for k-NN fields.  prev: Q x k previous matches.  When all
+ * k entries are in [0, n) and distinct, the radius c is the largest of their
+ * SSDs to the query: those k references lie within sqrt(c), so the k nearest
+ * do too, and they are in every ring; otherwise there is no radius.  Rings,
+ * the smallest ring and the all-ring filter are as in orc_riann; the answer
+ * is the k smallest (SSD, index) over S. */
+void orc_knn_riann(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int D,
+                   const int32_t *keys, int K, const uint32_t *T, const int32_t *P,
+                   const uint32_t *Piv, const int32_t *prev, int k, int32_t *idx,
+                   uint32_t *ssd)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < Q; ++i) {
+        const uint8_t *q = qp + i * D;
+        int np = 0;
+        uint64_t c = 0;
+        for (int j = 0; j < k && !np; ++j) {
+            const int32_t pv = prev[i * k + j];
+            if (pv < 0 || (int64_t)pv >= n) { np = 1; break; }
+            for (int j2 = 0; j2 < j; ++j2)
+                if (prev[i * k + j2] == pv) np = 1;
+            const uint64_t d = orc_ssd(q, ref + (int64_t)pv * D, D);
+            if (g_fault == 10) { if (j == 0 || d < c) c = d; }   /* planted: min, not max */
+            else if (d > c) c = d;
+        }
+        if (np) c = ORC_INF;
+        uint64_t *lo = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(K + 1));
+        uint64_t *hi = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(K + 1));
+        int64_t bst = 0, ben = n, bm = n;
+        int bk = -1;
+        for (int kk = 0; kk < K; ++kk) {
+            uint64_t b = orc_ssd(q, ref + (int64_t)keys[kk] * D, D);
+            orc_ring_bounds(b, c, &lo[kk], &hi[kk]);
+            const uint32_t *t = T + (int64_t)kk * n;
+            int64_t st = orc_lower(t, n, lo[kk]);
+            int64_t en = (hi[kk] == ORC_INF) ? n : orc_upper(t, n, hi[kk]);
+            int64_t m = en - st;
+            if (bk < 0 || m < bm) { bm = m; bk = kk; bst = st; ben = en; }
+        }
+        uint64_t bd[64];
+        int64_t br[64];
+        for (int j = 0; j < k; ++j) { bd[j] = ORC_INF; br[j] = -1; }
+        for (int64_t j = bst; j < ben; ++j) {
+            int64_t r = (bk < 0) ? j : P[(int64_t)bk * n + j];
+            int in = 1;
+            for (int kk = 0; kk < K && in; ++kk) {
+                uint64_t a = Piv[r * K + kk];
+                if (a < lo[kk] || a > hi[kk]) in = 0;
+            }
+            if (in) orc_topk_insert(bd, br, k, orc_ssd(q, ref + r * D, D), r);
+        }
+        for (int j = 0; j < k; ++j) {
+            idx[i * k + j] = (int32_t)br[j];
+            ssd[i * k + j] = (uint32_t)(br[j] < 0 ? 0xFFFFFFFFu : bd[j]);
+        }
         free(lo);
         free(hi);
     }

@@ -343,6 +343,53 @@ def test_riann_workload_tiny_frames():
         prev = out["idx"]
 
 
+# ---------------------------------------------------------------- k-NN fields
+def test_knn_bf_matches_numpy_sort():
+    """k nearest by exhaustive search against a numpy lexsort of all SSDs by
+    (SSD, index); k = 1 reduces to the 1-NN brute force."""
+    rng = np.random.default_rng(8)
+    ref = rng.integers(0, 256, (300, 12), dtype=np.uint8)
+    ref[[10, 20, 250]] = ref[5]                 # equal distances: index order
+    q = np.concatenate([rng.integers(0, 256, (40, 12), dtype=np.uint8), ref[[5, 7]]])
+    d = ((q[:, None, :].astype(np.int64) - ref[None, :, :].astype(np.int64)) ** 2).sum(-1)
+    for k in (1, 3, 8):
+        idx, dd = oracle.knn_brute_force(q, ref, k)
+        for i in range(len(q)):
+            order = np.lexsort((np.arange(len(ref)), d[i]))[:k]
+            assert list(idx[i]) == list(order)
+            assert list(dd[i]) == list(d[i][order])
+    assert list(oracle.knn_brute_force(ref[[5]], ref, 4)[0][0]) == [5, 10, 20, 250]
+    b1, d1 = oracle.brute_force(q, ref)
+    k1, kd1 = oracle.knn_brute_force(q, ref, 1)
+    np.testing.assert_array_equal(k1[:, 0], b1)
+    np.testing.assert_array_equal(kd1[:, 0], d1)
+
+
+@pytest.mark.parametrize("K", [0, 1, 5])
+def test_knn_riann_equals_brute_force(K):
+    """With the radius taken as the largest SSD to k distinct previous
+    matches, the k nearest lie in every ring (containment): the k-NN ring
+    search equals the exhaustive one for random, partly invalid, duplicated
+    and exact previous fields."""
+    rng = np.random.default_rng(40 + K)
+    ref = rng.integers(0, 256, (400, 16), dtype=np.uint8)
+    keys = np.sort(rng.choice(400, K, replace=False))
+    t = oracle.Tables(ref, keys)
+    q = np.clip(ref[rng.integers(0, 400, 120)].astype(np.int32) +
+                rng.integers(-20, 21, (120, 16)), 0, 255).astype(np.uint8)
+    k = 4
+    bi, bd = oracle.knn_brute_force(q, ref, k)
+    prevs = [rng.integers(0, 400, (120, k)).astype(np.int32)]
+    p2 = prevs[0].copy()
+    p2[::3, 1] = -1                                # no prior
+    p2[1::3, 2] = p2[1::3, 0]                      # duplicates: no radius either
+    prevs += [p2, bi.copy()]
+    for pv in prevs:
+        gi, gd = t.knn(q, pv, k)
+        np.testing.assert_array_equal(gi, bi)
+        np.testing.assert_array_equal(gd, bd)
+
+
 # ---------------------------------------------------------------- 3D patches
 def test_extract3d_position_code():
     """Spatio-temporal patches: frame t holds the value 50*t + (y*W + x) % 50
@@ -434,12 +481,13 @@ def _pins_pass():
         test_riann_equals_brute_force(10, 6, "random")
         test_reconstruct_hand_example()
         test_extract3d_position_code()
+        test_knn_riann_equals_brute_force(5)
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_planted_faults(fault):
     assert _pins_pass()
     oracle.set_fault(fault)
