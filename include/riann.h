@@ -193,6 +193,30 @@ riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *desc
                                  int32_t n, void *hip_stream);
 
 /*
+ * riann_match_knn -- exact k-nearest-neighbour field of one frame (the k-NN
+ * extension the paper lists as future work, Sec. 6): for every query the k
+ * references with the smallest (SSD, index), in ascending order.
+ *   k       1..8; k <= n.  k = 1 is riann_match_frame / riann_full_search.
+ *   prev    RING mode: device Hq x Wq x k, the previous frame's k-NN field, or
+ *           NULL.  The ring radius is the largest SSD from the query to its k
+ *           previous matches; those k references lie within it, so the k
+ *           nearest do too and every one of them is inside every ring.  A
+ *           query whose k entries are not k distinct indices in [0, n) has no
+ *           radius (the exact result is still returned).  Ignored in FULL mode.
+ *   out     device Hq x Wq x k int32;  ssd  device Hq x Wq x k uint32 or NULL
+ *   mode    RIANN_MODE_RING or RIANN_MODE_FULL (exhaustive)
+ * For k > 1 the dense search keeps its keys in 32 bits, which limits the
+ * reference set to n <= 32 * 2^jb (rounded up to 512) with
+ * jb = 32 - ceil(log2(81409 * D + 2)): n <= 32768 for D <= 32, 16384 for
+ * D <= 64, 8192 for D <= 192, 4096 for D <= 256; larger sets return
+ * RIANN_E_UNSUPPORTED.  The row-layout dense search is not used for k > 1.
+ * Asynchronous on hip_stream; prev must not overlap out or ssd.
+ */
+riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame, int32_t H, int32_t W,
+                               int64_t pitch, int32_t k, const int32_t *prev, int32_t *out,
+                               uint32_t *ssd, int32_t mode, void *hip_stream);
+
+/*
  * riann_footprint -- device bytes an index with parameters p needs, plus the
  * per-stream scratch for frames of H x W (H = W = 0: index only).
  */

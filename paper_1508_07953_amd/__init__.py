@@ -36,7 +36,7 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
-           "riann_reconstruct", "riann_stack_frames"]
+           "riann_reconstruct", "riann_stack_frames", "riann_match_knn"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -96,6 +96,7 @@ def _load():
     L.riann_set_dense_threshold.argtypes = [vp, i64]
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
     L.riann_reconstruct.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp]
+    L.riann_match_knn.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, i32, vp]
     L.riann_stack_frames.argtypes = [C.POINTER(vp), i32, i32, i32, i32, i64, vp, vp]
     L.riann_last_error.argtypes = []
     L.riann_last_error.restype = C.c_char_p
@@ -257,6 +258,27 @@ class Index:
         _check(_lib.riann_match_frame(self._h, frame.data_ptr(), H, W, pitch,
                                       prev.data_ptr() if prev is not None else None,
                                       out.data_ptr(), ssd.data_ptr(), _stream_ptr(stream)))
+        return out, ssd
+
+    def match_knn(self, frame, k: int, prev=None, full: bool = False, out=None, ssd=None,
+                  stream=None):
+        """Exact k-NN field (Hq, Wq, k), ascending (SSD, index) per query;
+        `prev` is the previous frame's (Hq, Wq, k) field (ring mode)."""
+        import torch
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        hq, wq = self.field_shape(max(H, 1), max(W, 1))
+        hq, wq = max(hq, 1), max(wq, 1)
+        if out is None:
+            out = torch.empty((hq, wq, k), dtype=torch.int32, device=frame.device)
+        if ssd is None:
+            ssd = torch.empty((hq, wq, k), dtype=torch.int32, device=frame.device)
+        if prev is not None and (prev.numel() != out.numel() or not prev.is_contiguous()
+                                 or prev.element_size() != 4):
+            raise ValueError("prev must be a contiguous int32 (Hq, Wq, k) tensor")
+        _check(_lib.riann_match_knn(self._h, frame.data_ptr(), H, W, pitch, int(k),
+                                    prev.data_ptr() if prev is not None and not full else None,
+                                    out.data_ptr(), ssd.data_ptr(),
+                                    MODE_FULL if full else MODE_RING, _stream_ptr(stream)))
         return out, ssd
 
     def full_search(self, frame, out=None, ssd=None, stream=None):

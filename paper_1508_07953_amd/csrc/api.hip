@@ -349,7 +349,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 // Checks one frame and fills its descriptor (qbase/tbase are set later).
 riann_status_t frame_desc(const riann_index *h, const uint8_t *frame, int32_t H, int32_t W,
                           int64_t pitch, const int32_t *prev, int32_t *out, uint32_t *ssd,
-                          int32_t mode, FrameDesc *fd) {
+                          int32_t mode, FrameDesc *fd, int knn = 1) {
     const int p = h->prm.patch, C = h->prm.channels, s = h->prm.stride;
     if (!frame) return fail(RIANN_E_INVALID, "frame is NULL");
     if (!out) return fail(RIANN_E_INVALID, "out is NULL");
@@ -369,7 +369,7 @@ riann_status_t frame_desc(const riann_index *h, const uint8_t *frame, int32_t H,
     fd->ssd = ssd;
     const int64_t Q = (int64_t)fd->Hq * fd->Wq;
     if (Q >= (int64_t)0x7FFFFFFF) return fail(RIANN_E_UNSUPPORTED, "too many queries in one frame");
-    const size_t qb = (size_t)Q * 4;
+    const size_t qb = (size_t)Q * 4 * knn;
     if (overlap(fd->prev, qb, out, qb)) return fail(RIANN_E_INVALID, "prev overlaps out");
     if (overlap(ssd, qb, out, qb)) return fail(RIANN_E_INVALID, "ssd overlaps out");
     if (overlap(fd->prev, qb, ssd, qb)) return fail(RIANN_E_INVALID, "prev overlaps ssd");
@@ -400,7 +400,8 @@ struct KTimer {
 };
 
 // One launch sequence over up to kMaxBatch frames (descriptors validated).
-riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
+riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn = 1) {
+    fb.knn = knn;
     int64_t q = 0;
     int32_t t = 0;
     bool all_full = true;
@@ -420,7 +421,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
     riann_status_t s = get_work(h, st, q, &w);
     if (s != RIANN_OK) return s;
     hipError_t e;
-    const bool rows = h->dense_rows && dense_rows_supported(h->dix);
+    const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
     if (!all_full || rows) {
         e = launch_zero_u32(w.counters, 4, st);
         if (e != hipSuccess) return hip_fail(e, "counter clear");
@@ -440,14 +441,17 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st) {
         }
         {
             KTimer tm(h, RIANN_K_SCAN, st);
-            e = launch_scan(h->dix, fb, w, h->dstats, st);
+            e = knn > 1 ? launch_scan_knn(h->dix, fb, w, h->dstats, st)
+                        : launch_scan(h->dix, fb, w, h->dstats, st);
             tm.stop();
             if (e != hipSuccess) return hip_fail(e, "k_scan launch");
         }
     }
     {
         KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
-        if (rows) {
+        if (knn > 1) {
+            e = launch_dense_knn(h->dix, fb, w, st);
+        } else if (rows) {
             e = launch_dense_rows(h->dix, fb, w, h->dstats, st);
         } else {
             e = launch_dense(h->dix, fb, w, st);
@@ -534,6 +538,24 @@ riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev, int3
     if (s != RIANN_OK) return s;
     DeviceGuard g(h->device);
     return run_batch(h, fb, (hipStream_t)hip_stream);
+}
+
+riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
+                               int64_t pitch, int32_t k, const int32_t *prev_dev, int32_t *out_dev,
+                               uint32_t *ssd_dev, int32_t mode, void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (k < 1 || k > kMaxKnn) return fail(RIANN_E_INVALID, "k must be in [1, 8]");
+    if (k > h->n) return fail(RIANN_E_INVALID, "k exceeds the number of references");
+    if (k > 1 && !knn_dense_supported(h->dix))
+        return fail(RIANN_E_UNSUPPORTED,
+                    "k-NN fields need n <= 32 * 2^jb for this patch size (see riann.h)");
+    FrameBatch fb;
+    fb.n = 1;
+    riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, prev_dev, out_dev, ssd_dev, mode,
+                                  &fb.f[0], k);
+    if (s != RIANN_OK) return s;
+    DeviceGuard g(h->device);
+    return run_batch(h, fb, (hipStream_t)hip_stream, k);
 }
 
 riann_status_t riann_full_search(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,

@@ -284,6 +284,144 @@ __global__ __launch_bounds__(kBlock) void k_dense(DevIndex ix, FrameBatch fb, Wo
     }
 }
 
+// ---------------------------------------------------------------- k-NN
+// Dense k-NN search (column layout, unsegmented keys): each wavefront holds
+// 32 queries as one MFMA A operand; lane (col, group) keeps, for each of its
+// 16 query rows, the KN smallest keys (X << jb | tile) of its reference column
+// in a sorted register list (one v_min and one v_max per level).  At the end,
+// KN rounds of a 32-lane minimum over the list heads of each row, on
+// (X, index) pairs, give the row's KN nearest in ascending order (KN = 2, 4
+// or 8; the first k are written).
+template <int DP, int KN, int ST>
+__global__ __launch_bounds__(kBlock) void k_dense_knn(DevIndex ix, FrameBatch fb, Work w,
+                                                       const uint32_t *__restrict__ list,
+                                                       const uint32_t *__restrict__ count_ptr) {
+    constexpr int KB = DP / 32;
+    constexpr int STAGE = ST * KB * 1024;
+    constexpr int BQ = 32 * kWaves;               // queries per block
+    __shared__ __attribute__((aligned(16))) int8_t s_f0[STAGE];
+    __shared__ __attribute__((aligned(16))) int8_t s_f1[STAGE];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r0[ST * kTile];
+    __shared__ __attribute__((aligned(16))) uint32_t s_r1[ST * kTile];
+
+    const uint32_t count = list ? *count_ptr : (uint32_t)fb.Q;
+    const uint32_t qbase = blockIdx.x * BQ;
+    if (qbase >= count) return;                   // whole block exits together
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = lane & 31, grp = lane >> 5;
+    const int nstages = (int)(ix.n_pad / (kTile * ST));
+    const uint32_t jb = (uint32_t)ix.jb, ash = jb + 1;
+
+    stage_dma<KB, ST>(ix.Rf, ix.Rk, 0, s_f0, s_r0, wv, lane);
+    const uint32_t slot = min(qbase + (uint32_t)(wv * 32 + col), count - 1);
+    const uint32_t qid = list ? list[slot] : slot;
+    v4i A[KB];
+    {
+        const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) + (int64_t)qid * DP + grp * 16;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) A[kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
+    }
+    const int qc = w.qc[qid];
+    uint32_t lst[16][KN];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+        for (int q = 0; q < KN; ++q) lst[i][q] = ~0u;
+    __syncthreads();
+
+    auto tile = [&](const int8_t *lf, const uint32_t *lr, int u, uint32_t t) {
+        v4i B[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+            B[kb] = *reinterpret_cast<const v4i *>(lf + (u * KB + kb) * 1024 + lane * 16);
+        const uint32_t rnj = lr[u * kTile + col] | t;
+        v16i acc = v16i{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[kb], B[kb], acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            uint32_t v = rnj + ((uint32_t)acc[i] << ash);
+#pragma unroll
+            for (int q = 0; q < KN; ++q) {        // sorted insertion
+                const uint32_t o = lst[i][q];
+                lst[i][q] = min(o, v);
+                v = max(o, v);
+            }
+        }
+    };
+    for (int sg = 0; sg < nstages; sg += 2) {
+        if (sg + 1 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Rk, sg + 1, s_f1, s_r1, wv, lane);
+#pragma unroll
+        for (int u = 0; u < ST; ++u) tile(s_f0, s_r0, u, (uint32_t)(sg * ST + u));
+        __syncthreads();
+        if (sg + 1 < nstages) {
+            if (sg + 2 < nstages) stage_dma<KB, ST>(ix.Rf, ix.Rk, sg + 2, s_f0, s_r0, wv, lane);
+#pragma unroll
+            for (int u = 0; u < ST; ++u) tile(s_f1, s_r1, u, (uint32_t)((sg + 1) * ST + u));
+            __syncthreads();
+        }
+    }
+
+    // ---- merge the 32 columns of every query row
+    const uint32_t jm = (1u << jb) - 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m = 8 * (i >> 2) + 4 * grp + (i & 3);   // the row register i holds
+        const uint32_t qm = (uint32_t)__shfl((int)qid, m, 64);
+        const int Qc_m = __shfl(qc, m, 64);
+        const bool live = qbase + (uint32_t)(wv * 32 + m) < count;
+        const FrameDesc *fdp = &fb.f[w.fid[qm]];
+        const int64_t ql = (int64_t)qm - fdp->qbase;
+#pragma unroll
+        for (int r = 0; r < KN; ++r) {
+            const uint32_t h = lst[i][0];
+            const unsigned long long mine =
+                ((unsigned long long)(h >> jb) << 32) | ((h & jm) * kTile + (uint32_t)col);
+            unsigned long long b = mine;
+#pragma unroll
+            for (int x = 16; x >= 1; x >>= 1) {
+                const unsigned lo = __shfl_xor((unsigned)b, x, 64);
+                const unsigned hi = __shfl_xor((unsigned)(b >> 32), x, 64);
+                const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+                b = o < b ? o : b;
+            }
+            if (mine == b) {                             // the one column holding it pops
+#pragma unroll
+                for (int q = 0; q + 1 < KN; ++q) lst[i][q] = lst[i][q + 1];
+                lst[i][KN - 1] = ~0u;
+            }
+            if (col == 0 && live && r < fb.knn) {
+                fdp->out[ql * fb.knn + r] = (int32_t)(uint32_t)b;
+                if (fdp->ssd)
+                    fdp->ssd[ql * fb.knn + r] =
+                        (uint32_t)((int)(uint32_t)(b >> 32) - ix.bias + Qc_m);
+            }
+        }
+    }
+}
+
+template <int DP, int KN>
+hipError_t launch_knn_t2(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
+    constexpr int ST = DP <= 64 ? 8 : 4;
+    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
+    const uint32_t *count = fb.all_full ? nullptr : w.counters + 1;
+    int64_t blocks = (fb.Q + 32 * kWaves - 1) / (32 * kWaves);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_knn<DP, KN, ST>), dim3((unsigned)blocks),
+                       dim3(kBlock), 0, st, ix, fb, w, list, count);
+    return hipGetLastError();
+}
+
+template <int DP>
+hipError_t launch_knn_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
+    // lists of 2, 4 or 8 entries; the first fb.knn of them are written
+    if (fb.knn < 2 || fb.knn > kMaxKnn) return hipErrorInvalidValue;
+    if (fb.knn <= 2) return launch_knn_t2<DP, 2>(ix, fb, w, st);
+    if (fb.knn <= 4) return launch_knn_t2<DP, 4>(ix, fb, w, st);
+    return launch_knn_t2<DP, 8>(ix, fb, w, st);
+}
+
 template <int DP>
 hipError_t launch_dense_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                           const uint32_t *list, const uint32_t *count, hipStream_t st) {
@@ -325,6 +463,25 @@ hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st) {
     return fb.all_full ? dispatch(ix, fb, w, nullptr, nullptr, st)
                        : dispatch(ix, fb, w, w.dense_list, w.counters + 1, st);
+}
+
+bool knn_dense_supported(const DevIndex &ix) {
+    return (ix.n_pad / kTile) <= ((int64_t)1 << ix.jb);
+}
+
+hipError_t launch_dense_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                            hipStream_t st) {
+    switch (ix.Dp) {
+    case 32: return launch_knn_t<32>(ix, fb, w, st);
+    case 64: return launch_knn_t<64>(ix, fb, w, st);
+    case 96: return launch_knn_t<96>(ix, fb, w, st);
+    case 128: return launch_knn_t<128>(ix, fb, w, st);
+    case 160: return launch_knn_t<160>(ix, fb, w, st);
+    case 192: return launch_knn_t<192>(ix, fb, w, st);
+    case 224: return launch_knn_t<224>(ix, fb, w, st);
+    case 256: return launch_knn_t<256>(ix, fb, w, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,

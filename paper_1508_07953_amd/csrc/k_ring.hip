@@ -178,12 +178,23 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb,
         }
     }
     const int Qc = w.qc[qq];
-    const int32_t pv = prev ? prev[ql] : -1;
-    const bool noprior = pv < 0 || (int64_t)pv >= ix.n;
+    // radius: the SSD to the previous match; for k-NN fields the largest SSD
+    // to the k previous matches, which must be k distinct references (then
+    // the k nearest lie within it); anything else means no prior
+    bool noprior = prev == nullptr;
     uint32_t c = 0xFFFFFFFFu;
     if (!noprior) {
-        int d = dot_row<DP>(a, ix.Rv + (int64_t)pv * ix.Dp);
-        c = (uint32_t)(Qc + ix.Rc[pv] + 2 * d);
+        const int kn = fb.knn;
+        uint32_t cm = 0;
+        for (int j = 0; j < kn && !noprior; ++j) {
+            const int32_t pv = prev[ql * kn + j];
+            if (pv < 0 || (int64_t)pv >= ix.n) { noprior = true; break; }
+            for (int j2 = 0; j2 < j; ++j2)
+                if (prev[ql * kn + j2] == pv) noprior = true;
+            int d = dot_row<DP>(a, ix.Rv + (int64_t)pv * ix.Dp);
+            cm = max(cm, (uint32_t)(Qc + ix.Rc[pv] + 2 * d));
+        }
+        if (!noprior) c = cm;
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
     if (!full && !noprior && ix.K > 0) {
@@ -345,6 +356,107 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameBatch fb, Wor
     }
 }
 
+// ---------------------------------------------------------------- k_scan_knn
+// k-NN variant of k_scan: each lane keeps the KN smallest (SSD, index) keys of
+// its candidates in a sorted register list (KN = 2, 4 or 8 >= k); the
+// wavefront then takes the global smallest by rounds of a wave minimum over
+// the list heads (the keys are distinct: every candidate is scanned by one
+// lane only) and writes the first k.
+template <int DP, int KN>
+__global__ __launch_bounds__(kBlock) void k_scan_knn(DevIndex ix, FrameBatch fb, Work w,
+                                                      unsigned long long *__restrict__ stats) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t count = w.counters[0];
+    const uint32_t n = (uint32_t)ix.n;
+    const int K = ix.K, kq = ix.Kp / 4;
+    unsigned long long surv_tot = 0, mstar_tot = 0;
+    for (uint32_t item = blockIdx.x * (kBlock / 64) + wv; item < count;
+         item += gridDim.x * (kBlock / 64)) {
+        const uint32_t qid = w.ring_list[item];
+        const uint4 rec = w.rec[qid];
+        const uint32_t c = rec.x, ks = rec.y, st = rec.z, en = rec.w;
+        const uint32_t mine = lane < DP / 4
+            ? reinterpret_cast<const uint32_t *>(w.patches + (int64_t)qid * DP)[lane] : 0u;
+        uint32_t a[DP / 4];
+#pragma unroll
+        for (int i = 0; i < DP / 4; ++i) a[i] = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+        const int Qc = w.qc[qid];
+        uint32_t lo = 0, hi = 0xFFFFFFFFu;
+        if (lane < K) {
+            const int key = ix.keys[lane];
+            int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
+            uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
+            ring_bounds(b, c, lo, hi);
+        }
+        unsigned long long lst[KN];
+#pragma unroll
+        for (int j = 0; j < KN; ++j) lst[j] = ~0ull;
+        uint32_t cnt = 0;
+        const int32_t *Pk = ix.P + (int64_t)ks * n;
+        for (uint32_t j = st + lane; j < en; j += 64) {
+            const int32_t r = Pk[j];
+            const uint4 *row = reinterpret_cast<const uint4 *>(ix.Piv + (int64_t)r * ix.Kp);
+            uint4 pv[kMaxKeys / 4];
+#pragma unroll
+            for (int q = 0; q < kMaxKeys / 4; ++q)
+                if (q < kq) pv[q] = row[q];
+            bool in = true;
+#pragma unroll
+            for (int q = 0; q < kMaxKeys / 4; ++q) {
+                if (q < kq) {
+                    const uint32_t x[4] = {pv[q].x, pv[q].y, pv[q].z, pv[q].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, 4 * q + e);
+                        const uint32_t hk = (uint32_t)__builtin_amdgcn_readlane((int)hi, 4 * q + e);
+                        in = in && x[e] >= lk && x[e] <= hk;
+                    }
+                }
+            }
+            if (in) {
+                ++cnt;
+                int d = dot_row<DP>(a, ix.Rv + (int64_t)r * ix.Dp);
+                const uint32_t s = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
+                unsigned long long v = ((unsigned long long)s << 32) | (uint32_t)r;
+#pragma unroll
+                for (int q = 0; q < KN; ++q) {       // sorted insertion
+                    const unsigned long long t = lst[q];
+                    lst[q] = v < t ? v : t;
+                    v = v < t ? t : v;
+                }
+            }
+        }
+        const FrameDesc *fdp = &fb.f[w.fid[qid]];
+        const int64_t ql = (int64_t)qid - fdp->qbase;
+#pragma unroll
+        for (int r = 0; r < KN; ++r) {
+            const unsigned long long m = wave_min_u64(lst[0]);
+            if (lst[0] == m) {                       // the one lane holding it pops
+#pragma unroll
+                for (int q = 0; q + 1 < KN; ++q) lst[q] = lst[q + 1];
+                lst[KN - 1] = ~0ull;
+            }
+            if (lane == 0 && r < fb.knn) {
+                fdp->out[ql * fb.knn + r] = (int32_t)(uint32_t)m;
+                if (fdp->ssd) fdp->ssd[ql * fb.knn + r] = (uint32_t)(m >> 32);
+            }
+        }
+        const unsigned long long tot = wave_sum_u64(cnt);
+        if (lane == 0) {
+            surv_tot += tot;
+            mstar_tot += en - st;
+        }
+    }
+    __shared__ unsigned long long s_acc[kBlock / 64][2];
+    if (lane == 0) { s_acc[wv][0] = surv_tot; s_acc[wv][1] = mstar_tot; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
+        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
+    }
+}
+
 template <int DP>
 hipError_t launch_ring_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                          unsigned long long *stats, int64_t threshold, hipStream_t st) {
@@ -352,6 +464,23 @@ hipError_t launch_ring_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
     const size_t lds = (size_t)ix.K * ix.ns * 4;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP>), dim3((unsigned)blocks), dim3(kRingBlock),
                        lds, st, ix, fb, w, stats, threshold);
+    return hipGetLastError();
+}
+
+template <int DP>
+hipError_t launch_scan_knn_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                             unsigned long long *stats, hipStream_t st) {
+    // lists of 2, 4 or 8 entries; the first fb.knn of them are written
+    if (fb.knn < 2 || fb.knn > kMaxKnn) return hipErrorInvalidValue;
+    if (fb.knn <= 2)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_knn<DP, 2>), dim3(1024), dim3(kBlock), 0, st,
+                           ix, fb, w, stats);
+    else if (fb.knn <= 4)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_knn<DP, 4>), dim3(1024), dim3(kBlock), 0, st,
+                           ix, fb, w, stats);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_knn<DP, 8>), dim3(1024), dim3(kBlock), 0, st,
+                           ix, fb, w, stats);
     return hipGetLastError();
 }
 
@@ -395,6 +524,13 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 #define CALL_SCAN(D) launch_scan_t<D>(ix, fb, w, stats, st)
     RIANN_DP_SWITCH(ix.Dp, CALL_SCAN)
 #undef CALL_SCAN
+}
+
+hipError_t launch_scan_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                           unsigned long long *stats, hipStream_t st) {
+#define CALL_SCAN_KNN(D) launch_scan_knn_t<D>(ix, fb, w, stats, st)
+    RIANN_DP_SWITCH(ix.Dp, CALL_SCAN_KNN)
+#undef CALL_SCAN_KNN
 }
 
 }  // namespace riann

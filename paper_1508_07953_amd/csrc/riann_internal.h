@@ -84,7 +84,8 @@ struct FrameBatch {
     int32_t ntiles;          // extraction tiles over all frames
     int64_t Q;               // queries over all frames
     int32_t all_full;        // every frame in full-search mode
-    int32_t pad;
+    int32_t knn;             // neighbours per query (1: prev/out/ssd are Hq x Wq;
+                             // k > 1: Hq x Wq x k, each row ascending)
     FrameDesc f[kMaxBatch];
 };
 
@@ -156,6 +157,17 @@ struct ReconArgs {
 };
 int64_t recon_blocks(int H, int W);
 hipError_t launch_recon(const DevIndex &ix, const ReconArgs &ra, double *err, hipStream_t st);
+
+// k-NN fields (fb.knn = k in [2, kMaxKnn]): the ring kernel takes the radius
+// from the k previous matches; these answer the ring list and the dense list
+// with the k smallest (SSD, index) per query.  The dense search needs the
+// unsegmented key (n_pad / 32 tiles <= 2^jb), see knn_dense_supported.
+constexpr int kMaxKnn = 8;
+hipError_t launch_scan_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                           unsigned long long *stats, hipStream_t st);
+bool knn_dense_supported(const DevIndex &ix);
+hipError_t launch_dense_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                            hipStream_t st);
 
 // Column-layout dense search of an explicit list with a device-side count.
 hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
