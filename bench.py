@@ -317,6 +317,30 @@ def main():
                              "GBps": rbytes / (ms_r * 1e-3) / 1e9,
                              "note": "field 4 B/query + frame 1 B and output 4 B per value + "
                                      "appearance set once; gathers served by L2"}
+    # exact k-NN fields (k = 4) on the same frames, where the key range allows
+    try:
+        kk = 4
+        kout = [torch.empty((hq, wq, kk), dtype=torch.int32, device=dev) for _ in range(2)]
+        kss = torch.empty((hq, wq, kk), dtype=torch.int32, device=dev)
+        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
+        e1.record(stream)
+        e1.synchronize()
+        full_ms = e0.elapsed_time(e1)
+        nk = min(10, K)
+        kc = 0
+        e0.record(stream)
+        for i in range(nk):
+            idx.match_knn(frames[W + 1 + i], kk, prev=kout[kc], out=kout[1 - kc], ssd=kss)
+            kc = 1 - kc
+        e1.record(stream)
+        e1.synchronize()
+        result["knn"] = {"k": kk, "full_frame_ms": full_ms,
+                         "ring_frame_ms": e0.elapsed_time(e1) / nk, "frames": nk}
+    except riann.RiannError as ex:
+        result["knn"] = {"k": 4, "unsupported": str(ex)}
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)

@@ -64,6 +64,11 @@ def lib():
         L.orc_knn_bf.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int, C.c_int, i32p, u32p]
         L.orc_knn_riann.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int, i32p, C.c_int,
                                     u32p, i32p, u32p, i32p, C.c_int, i32p, u32p]
+        L.orc_splitmix.argtypes = [C.c_uint64]
+        L.orc_splitmix.restype = C.c_uint64
+        L.orc_paper_tables.argtypes = [u8p, C.c_int64, C.c_int, u32p, u32p, i32p]
+        L.orc_paper.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int, u32p, u32p, i32p, i32p,
+                                C.c_int, C.c_uint64, C.c_uint64, C.c_int64, i32p, u32p, i32p]
         L.orc_extract3d.argtypes = [C.POINTER(u8p), C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_int, u8p]
         L.orc_reconstruct.argtypes = [i32p, C.c_int, C.c_int, u8p, C.c_int, C.c_int, C.c_int,
@@ -169,6 +174,42 @@ def knn_brute_force(patches: np.ndarray, ref: np.ndarray, k: int) -> Tuple[np.nd
     lib().orc_knn_bf(_p(q, C.c_uint8), Q, _p(r, C.c_uint8), r.shape[0], D, k,
                      _p(idx, C.c_int32), _p(d, C.c_uint32))
     return idx, d
+
+
+def splitmix(x: int) -> int:
+    """SplitMix64 output for state x (the counter-based anchor generator)."""
+    return int(lib().orc_splitmix(C.c_uint64(x & (2**64 - 1))))
+
+
+class PaperTables:
+    """The paper's pre-processing for Algorithm 1 (Sec. 3.3): the n x n SSD
+    matrix of the references and each row sorted by (value, index)."""
+
+    def __init__(self, ref: np.ndarray):
+        self.ref = np.ascontiguousarray(ref, np.uint8)
+        n, self.D = self.ref.shape
+        self.n = n
+        self.dm = np.empty((n, n), np.uint32)
+        self.tv = np.empty((n, n), np.uint32)
+        self.tp = np.empty((n, n), np.int32)
+        lib().orc_paper_tables(_p(self.ref, C.c_uint8), n, self.D, _p(self.dm, C.c_uint32),
+                               _p(self.tv, C.c_uint32), _p(self.tp, C.c_int32))
+
+    def search(self, patches: np.ndarray, prev: np.ndarray, L: int = 20, seed: int = 0,
+               t: int = 0, qbase: int = 0) -> Dict[str, np.ndarray]:
+        """Algorithm 1 for every patch (approximate; see orc_paper)."""
+        q = np.ascontiguousarray(patches, np.uint8)
+        pv = np.ascontiguousarray(prev, np.int32).reshape(-1)
+        Q = q.shape[0]
+        assert pv.size == Q and q.shape[1] == self.D
+        out = dict(idx=np.empty(Q, np.int32), ssd=np.empty(Q, np.uint32),
+                   iters=np.empty(Q, np.int32))
+        lib().orc_paper(_p(q, C.c_uint8), Q, _p(self.ref, C.c_uint8), self.n, self.D,
+                        _p(self.dm, C.c_uint32), _p(self.tv, C.c_uint32), _p(self.tp, C.c_int32),
+                        _p(pv, C.c_int32), int(L), C.c_uint64(seed), C.c_uint64(t),
+                        int(qbase), _p(out["idx"], C.c_int32), _p(out["ssd"], C.c_uint32),
+                        _p(out["iters"], C.c_int32))
+        return out
 
 
 def isqrt(x: int) -> int:

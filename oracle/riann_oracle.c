@@ -40,6 +40,12 @@
  *   orc_knn_riann   the same search with k-NN rings: the radius is the
  *                   largest distance to the k previous matches, so the k
  *                   nearest lie inside every ring (exact k-NN fields).
+ *   orc_paper       the paper's own approximate search (Algorithm 1): fat
+ *                   rings d -/+ alpha*d with alpha = 1/4 around the previous
+ *                   match, then around random anchors drawn from the
+ *                   candidate set until fewer than L candidates remain.
+ *   orc_splitmix    the SplitMix64 generator (Steele, Lea and Flood, 2014)
+ *                   that draws the anchors, as a counter-based hash.
  *   orc_extract3d   spatio-temporal query patches (the 3D extension noted in
  *                   Sec. 1): p x p windows of T consecutive frames, flattened
  *                   in (dy, dx, t, c) order.
@@ -150,6 +156,12 @@ void orc_ring_bounds(uint64_t b, uint64_t c, uint64_t *lo, uint64_t *hi)
 /* pre-processing: sorted key-distance tables                           */
 /* ------------------------------------------------------------------ */
 typedef struct { uint32_t v; int32_t r; } orc_pair;
+
+static int orc_cmp_u64(const void *x, const void *y)
+{
+    const uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+    return (a > b) - (a < b);
+}
 
 static int orc_cmp_pair(const void *x, const void *y)
 {
@@ -358,6 +370,142 @@ void orc_knn_riann(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, 
         }
         free(lo);
         free(hi);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* the paper's approximate search (Algorithm 1)                        */
+/* ------------------------------------------------------------------ */
+/* SplitMix64 output for state x: add the golden gamma, then two
+ * xor-shift-multiply rounds and a final xor-shift. */
+uint64_t orc_splitmix(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* The anchor draw of (seed, frame t, query, iteration): a chain of SplitMix64
+ * steps, one counter mixed in per step. */
+static uint64_t orc_draw(uint64_t seed, uint64_t t, uint64_t query, uint64_t it)
+{
+    return orc_splitmix(orc_splitmix(orc_splitmix(orc_splitmix(seed) ^ t) ^ query) ^ it);
+}
+
+/* With alpha = 1/4 the ring d - alpha d <= dist(r_k, r_j) <= d + alpha d
+ * reads, in squared integer distances a = SSD(r_k, r_j) and c = d^2,
+ * 9c <= 16a <= 25c. */
+static int orc_in_fat_ring(uint64_t a, uint64_t c)
+{
+    if (g_fault == 11) return 9 * c < 16 * a && 16 * a < 25 * c;   /* planted: open ends */
+    return 9 * c <= 16 * a && 16 * a <= 25 * c;
+}
+
+/* dm: n x n SSD matrix between references; tv/tp: each row of dm sorted
+ * ascending by (value, index) -- values and indices.  Per query i (global
+ * index qbase + i within frame t):
+ *   r_i = prev[i] (outside [0,n): a random initial match, the draw with
+ *         iteration 2^32 - 1, modulo n)
+ *   c   = SSD(q, r_i);  S = ring of r_i (positions of its sorted row with
+ *         9c <= 16a <= 25c), in row order, preceded by r_i itself when c > 0
+ *         (its own ring excludes it otherwise)
+ *   while |S| >= L and some member of S has not been an anchor:
+ *       u = draw(iteration) mod (number of members not yet anchors); the
+ *       anchor r_k is the u-th such member in S order; S' = members of S in
+ *       the ring of r_k (radius from SSD(q, r_k)); if S' is empty stop
+ *       (keep S), else S = S'
+ *   out = (SSD, index) minimum over S.
+ * iters (optional): anchors drawn per query. */
+void orc_paper(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int D,
+               const uint32_t *dm, const uint32_t *tv, const int32_t *tp, const int32_t *prev,
+               int L, uint64_t seed, uint64_t t, int64_t qbase, int32_t *idx, uint32_t *ssd,
+               int32_t *iters)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < Q; ++i) {
+        const uint8_t *q = qp + i * D;
+        int64_t ri = prev[i];
+        if (ri < 0 || ri >= n)
+            ri = (int64_t)(orc_draw(seed, t, (uint64_t)(qbase + i), 0xFFFFFFFFull) % (uint64_t)n);
+        const uint64_t c = orc_ssd(q, ref + ri * D, D);
+        /* ring of r_i in its sorted row */
+        const uint32_t *row = tv + ri * n;
+        int64_t st = 0, en = 0;
+        while (st < n && !(16 * (uint64_t)row[st] >= 9 * c && (g_fault != 11 || 16 * (uint64_t)row[st] > 9 * c))) ++st;
+        en = st;
+        while (en < n && orc_in_fat_ring(row[en], c)) ++en;
+        /* S as a list of reference indices in S order, with anchor marks */
+        int64_t cap = (en - st) + 1, m = 0;
+        int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        uint8_t *used = (uint8_t *)calloc((size_t)cap, 1);
+        int64_t *S2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        uint8_t *used2 = (uint8_t *)malloc((size_t)cap);
+        if (c > 0) S[m++] = ri;
+        for (int64_t pos = st; pos < en; ++pos) S[m++] = tp[ri * n + pos];
+        int32_t it = 0;
+        for (;;) {
+            if (m < L) break;
+            int64_t free_cnt = 0;
+            for (int64_t e = 0; e < m; ++e) free_cnt += !used[e];
+            if (free_cnt == 0) break;
+            const uint64_t u = orc_draw(seed, t, (uint64_t)(qbase + i), (uint64_t)it) %
+                               (uint64_t)free_cnt;
+            int64_t e = 0, seen = 0;
+            for (; e < m; ++e)
+                if (!used[e]) {
+                    if ((uint64_t)seen == u) break;
+                    ++seen;
+                }
+            used[e] = 1;
+            ++it;
+            const int64_t rk = S[e];
+            const uint64_t ck = orc_ssd(q, ref + rk * D, D);
+            int64_t m2 = 0;
+            for (int64_t f = 0; f < m; ++f)
+                if (orc_in_fat_ring(dm[rk * n + S[f]], ck)) {
+                    S2[m2] = S[f];
+                    used2[m2] = used[f];
+                    ++m2;
+                }
+            if (m2 == 0) break;
+            memcpy(S, S2, sizeof(int64_t) * (size_t)m2);
+            memcpy(used, used2, (size_t)m2);
+            m = m2;
+        }
+        uint64_t best = ORC_INF;
+        int64_t arg = -1;
+        for (int64_t e = 0; e < m; ++e) {
+            const uint64_t d = orc_ssd(q, ref + S[e] * D, D);
+            if (d < best || (d == best && S[e] < arg)) { best = d; arg = S[e]; }
+        }
+        if (m == 0) { arg = ri; best = c; }   /* empty ring of r_i and c == 0 cannot happen */
+        idx[i] = (int32_t)arg;
+        ssd[i] = (uint32_t)best;
+        if (iters) iters[i] = it;
+        free(S); free(used); free(S2); free(used2);
+    }
+}
+
+/* Pairwise SSD matrix of the references and its rows sorted by (value,
+ * index): the paper's pre-processing for Algorithm 1 (Sec. 3.3). */
+void orc_paper_tables(const uint8_t *ref, int64_t n, int D, uint32_t *dm, uint32_t *tv,
+                      int32_t *tp)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t *pr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+        for (int64_t j = 0; j < n; ++j) {
+            const uint32_t d = (uint32_t)orc_ssd(ref + i * D, ref + j * D, D);
+            dm[i * n + j] = d;
+            pr[j] = ((uint64_t)d << 32) | (uint64_t)j;
+        }
+        qsort(pr, (size_t)n, sizeof(uint64_t), orc_cmp_u64);
+        for (int64_t j = 0; j < n; ++j) {
+            tv[i * n + j] = (uint32_t)(pr[j] >> 32);
+            tp[i * n + j] = (int32_t)(pr[j] & 0xFFFFFFFFu);
+        }
+        free(pr);
     }
 }
 

@@ -390,6 +390,80 @@ def test_knn_riann_equals_brute_force(K):
         np.testing.assert_array_equal(gd, bd)
 
 
+# ---------------------------------------------------------------- paper mode
+def test_splitmix_published_vector():
+    """SplitMix64 (Steele, Lea and Flood 2014): the first outputs for seeds 0
+    and 1 of the published generator."""
+    assert oracle.splitmix(0) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix(1) == 0x910A2DEC89025CC1
+
+
+def _paper(ref, q, prev, L, seed=3, t=1):
+    pt = oracle.PaperTables(np.asarray(ref, np.uint8).reshape(len(ref), -1))
+    return pt, pt.search(np.asarray(q, np.uint8).reshape(len(q), -1),
+                         np.asarray(prev, np.int32), L=L, seed=seed, t=t)
+
+
+def test_paper_hand_examples():
+    """1-pixel patches worked by hand (alpha = 1/4: 9c <= 16a <= 25c), refs
+    0, 12, 20, 40, 10.  q = 16, r_i = ref 0: c = 256, the ring of ref 0 is
+    a in [144, 400], both ends closed, so 12 (a = 144) and 20 (a = 400) join
+    r_i; the best is 12 (SSD 16, lower index than 20).  q = 12, r_i = ref 4
+    (10): c = 4, the ring a in [2.25, 6.25] holds 12 (a = 4): exact match.
+    q = 11, r_i = ref 4: c = 1, the ring a in [0.5625, 1.5625] is empty, so
+    S = {r_i}.  With L = 1 that member is drawn as anchor; its own ring
+    excludes it (a = 0), the intersection would be empty, so S is kept."""
+    ref = [[0], [12], [20], [40], [10]]
+    pt, r = _paper(ref, [[16], [12], [11]], [0, 4, 4], L=20)
+    assert list(r["idx"]) == [1, 1, 4] and list(r["ssd"]) == [16, 0, 1]
+    assert list(r["iters"]) == [0, 0, 0]
+    _, r1 = _paper(ref, [[11]], [4], L=1)
+    assert list(r1["idx"]) == [4] and list(r1["iters"]) == [1]
+    assert pt.tv[0].tolist() == [0, 100, 144, 400, 1600]
+    assert pt.tp[0].tolist() == [0, 4, 1, 2, 3]
+
+
+def test_paper_without_anchors_is_the_first_ring():
+    """With L above n no anchor is drawn: the answer is the (SSD, index)
+    minimum over r_i and the references whose distance to r_i lies in the
+    fat ring, computed here from numpy distances."""
+    rng = np.random.default_rng(21)
+    ref = rng.integers(0, 256, (150, 9), dtype=np.uint8)
+    q = rng.integers(0, 256, (60, 9), dtype=np.uint8)
+    prev = rng.integers(0, 150, 60)
+    _, r = _paper(ref, q, prev, L=1000)
+    R = ref.astype(np.int64)
+    for i in range(60):
+        c = int(((q[i].astype(np.int64) - R[prev[i]]) ** 2).sum())
+        a = ((R - R[prev[i]]) ** 2).sum(1)
+        S = set(np.nonzero((9 * c <= 16 * a) & (16 * a <= 25 * c))[0]) | {int(prev[i])}
+        S = sorted(S)
+        d = ((R[S] - q[i].astype(np.int64)) ** 2).sum(1)
+        j = int(np.lexsort((S, d))[0])
+        assert r["idx"][i] == S[j] and r["ssd"][i] == d[j] and r["iters"][i] == 0
+
+
+def test_paper_invariants_and_determinism():
+    """The answer lies in r_i's first ring or is r_i; runs are reproducible
+    for a seed; the anchor count only grows when |S| >= L was reached."""
+    wl = gen.make_workload("tiny", frames=2)
+    P = oracle.extract(wl.frame(1), 8, 1)[:400]
+    rng = np.random.default_rng(2)
+    prev = rng.integers(0, len(wl.ref), len(P)).astype(np.int32)
+    pt = oracle.PaperTables(wl.ref)
+    a = pt.search(P, prev, L=20, seed=11, t=1)
+    b = pt.search(P, prev, L=20, seed=11, t=1)
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+    R = wl.ref.astype(np.int64)
+    for i in range(0, 400, 7):
+        c = int(((P[i].astype(np.int64) - R[prev[i]]) ** 2).sum())
+        ai = int(pt.dm[prev[i], a["idx"][i]])
+        assert a["idx"][i] == prev[i] or (9 * c <= 16 * ai <= 25 * c)
+    assert a["iters"].max() > 0
+    bi, bd = oracle.brute_force(P, wl.ref)
+    assert np.all(a["ssd"] >= bd)
+
+
 # ---------------------------------------------------------------- 3D patches
 def test_extract3d_position_code():
     """Spatio-temporal patches: frame t holds the value 50*t + (y*W + x) % 50
@@ -482,12 +556,13 @@ def _pins_pass():
         test_reconstruct_hand_example()
         test_extract3d_position_code()
         test_knn_riann_equals_brute_force(5)
+        test_paper_hand_examples()
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
 def test_planted_faults(fault):
     assert _pins_pass()
     oracle.set_fault(fault)
