@@ -88,6 +88,48 @@ def cpu_baseline(wl, f0, f1, target_s):
                       f"{elapsed:.2f} s wall, table build excluded"}
 
 
+def paper_mode(idx, frames, hq, wq, dev, log_fn, nframes=12, timed=6):
+    """The paper's approximate Algorithm 1 (alpha = 1/4, L = 20, random
+    anchors) on the same frames, started from a random field: time per frame
+    once converged, and accuracy against the exact field of each frame."""
+    import torch
+    t0 = time.time()
+    idx.build_paper_tables()
+    build_s = time.time() - t0
+    log_fn(f"paper tables built in {build_s:.1f}s")
+    nframes = min(nframes, len(frames) - 1)
+    timed = min(timed, nframes)
+    prev = None
+    outs = [torch.empty((hq, wq), dtype=torch.int32, device=dev) for _ in range(2)]
+    ssd = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    iters = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    ex_out = torch.empty_like(ssd)
+    ex_ssd = torch.empty_like(ssd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms, exact, ratio, anchors = [], [], [], []
+    for t in range(1, nframes + 1):
+        cur = outs[t % 2]
+        torch.cuda.synchronize()
+        e0.record()
+        idx.match_paper(frames[t], prev=prev, L=20, seed=150807953, t=t, out=cur, ssd=ssd,
+                        iters=iters)
+        e1.record()
+        e1.synchronize()
+        if t > nframes - timed:
+            ms.append(e0.elapsed_time(e1))
+            idx.full_search(frames[t], out=ex_out, ssd=ex_ssd)
+            torch.cuda.synchronize()
+            exact.append(float((cur == ex_out).float().mean().item()))
+            ratio.append(float(ssd.double().mean().item() / ex_ssd.double().mean().item()))
+            anchors.append(float(iters.double().mean().item()))
+        prev = cur
+    m = float(np.mean(ms))
+    return {"L": 20, "alpha": 0.25, "ms_per_frame": m, "patches_per_s": hq * wq / (m * 1e-3),
+            "exact_fraction": float(np.mean(exact)), "mean_ssd_ratio_vs_exact": float(np.mean(ratio)),
+            "mean_anchors": float(np.mean(anchors)), "table_build_s": build_s,
+            "frames": f"{nframes} from a random field, last {timed} timed"}
+
+
 def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
     """Serving (continuous batching) vs plain (one frame at a time) on a
     scaled serving workload: `streams` RGB streams, stream id mod 3 ->
@@ -169,6 +211,8 @@ def main():
                          "library default); column: always queries as MFMA rows")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default routing threshold")
+    ap.add_argument("--no-paper-mode", action="store_true",
+                    help="skip the paper's approximate search (needs n x n tables)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-vs-plain comparison")
     ap.add_argument("--serving-streams", type=int, default=12)
@@ -341,6 +385,8 @@ def main():
                          "ring_frame_ms": e0.elapsed_time(e1) / nk, "frames": nk}
     except riann.RiannError as ex:
         result["knn"] = {"k": 4, "unsupported": str(ex)}
+    if not args.no_paper_mode:
+        result["paper_mode"] = paper_mode(idx, frames, hq, wq, dev, log)
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)

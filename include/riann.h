@@ -224,6 +224,36 @@ riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W,
                                int64_t *bytes);
 
 /*
+ * The paper's own approximate search (Algorithm 1), for comparison with the
+ * exact search.  Patches are raw uint8 (no unit normalisation), distances are
+ * integer SSDs, and alpha = 1/4, so the fat ring d -/+ alpha*d around a
+ * reference r at query distance d is 9*SSD(q,r) <= 16*SSD(r,r_j) <=
+ * 25*SSD(q,r).  Per query: r_i = prev entry (outside [0, n), or prev NULL: a
+ * random reference drawn from the generator below); S = the ring of r_i,
+ * preceded by r_i itself when SSD(q, r_i) > 0; while |S| >= L and some member
+ * has not yet been an anchor: draw u = g(seed, t, q, iteration) mod (number
+ * of members not yet drawn), take the u-th such member in S order as anchor
+ * r_k and intersect S with r_k's ring -- unless that leaves nothing, which
+ * stops the loop with S kept; the answer is the (SSD, index) minimum over S.
+ * g is the SplitMix64 output function (Steele, Lea and Flood 2014) chained
+ * over the counters: g = sm(sm(sm(sm(seed) ^ t) ^ q) ^ it), q = the query's
+ * row-major field index (it = 2^32 - 1 draws the random initial match).
+ *
+ * riann_build_paper_tables -- pre-processing (Sec. 3.3): the n x n SSD
+ *   matrix of the references and every row sorted by (value, index), built on
+ *   the host and kept on the device (12 n^2 bytes; n <= 32768, else
+ *   RIANN_E_UNSUPPORTED).  Synchronous.  Needed once per index.
+ * riann_match_paper -- one frame; out/ssd Hq x Wq as for riann_match_frame;
+ *   iters (device Hq x Wq int32, or NULL) receives the anchors drawn per
+ *   query; L >= 1 (the paper uses 20); t is the frame number.  Asynchronous.
+ */
+riann_status_t riann_build_paper_tables(riann_index_t h, void *hip_stream);
+riann_status_t riann_match_paper(riann_index_t h, const uint8_t *frame, int32_t H, int32_t W,
+                                 int64_t pitch, const int32_t *prev, int32_t *out, uint32_t *ssd,
+                                 int32_t *iters, int32_t L, uint64_t seed, uint64_t t,
+                                 void *hip_stream);
+
+/*
  * riann_stack_frames -- spatio-temporal patches (the 3D extension of Sec. 1).
  * Interleaves T frames into one H x W x (T*C) frame whose channel t*C + c is
  * channel c of frames[t], so that a p x p patch of the result is the

@@ -36,7 +36,8 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_footprint", "riann_get_stats", "riann_reset_stats", "riann_get_params",
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
-           "riann_reconstruct", "riann_stack_frames", "riann_match_knn"]
+           "riann_reconstruct", "riann_stack_frames", "riann_match_knn",
+           "riann_build_paper_tables", "riann_match_paper"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -97,6 +98,9 @@ def _load():
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
     L.riann_reconstruct.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp]
     L.riann_match_knn.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, i32, vp]
+    L.riann_build_paper_tables.argtypes = [vp, vp]
+    L.riann_match_paper.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp, i32, C.c_uint64,
+                                    C.c_uint64, vp]
     L.riann_stack_frames.argtypes = [C.POINTER(vp), i32, i32, i32, i32, i64, vp, vp]
     L.riann_last_error.argtypes = []
     L.riann_last_error.restype = C.c_char_p
@@ -280,6 +284,29 @@ class Index:
                                     out.data_ptr(), ssd.data_ptr(),
                                     MODE_FULL if full else MODE_RING, _stream_ptr(stream)))
         return out, ssd
+
+    def build_paper_tables(self, stream=None) -> None:
+        """n x n sorted distance tables for match_paper (synchronous)."""
+        _check(_lib.riann_build_paper_tables(self._h, _stream_ptr(stream)))
+
+    def match_paper(self, frame, prev=None, L: int = 20, seed: int = 0, t: int = 0,
+                    out=None, ssd=None, iters=None, stream=None):
+        """The paper's approximate search (Algorithm 1, alpha = 1/4) of one
+        frame; returns (out, ssd, iters) with iters the anchors per query."""
+        import torch
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        out, ssd = self._outputs(H, W, frame.device, out, ssd)
+        if iters is None:
+            iters = torch.empty_like(out)
+        if prev is not None and (prev.numel() != out.numel() or not prev.is_contiguous()
+                                 or prev.element_size() != 4):
+            raise ValueError("prev must be a contiguous int32 (Hq, Wq) tensor")
+        _check(_lib.riann_match_paper(self._h, frame.data_ptr(), H, W, pitch,
+                                      prev.data_ptr() if prev is not None else None,
+                                      out.data_ptr(), ssd.data_ptr(), iters.data_ptr(), int(L),
+                                      C.c_uint64(seed & (2**64 - 1)), C.c_uint64(t),
+                                      _stream_ptr(stream)))
+        return out, ssd, iters
 
     def full_search(self, frame, out=None, ssd=None, stream=None):
         """Exact exhaustive search of one frame (first frame, scene cuts)."""

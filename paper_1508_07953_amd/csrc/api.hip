@@ -38,6 +38,7 @@ struct riann_index {
     std::mutex mu;
     std::map<hipStream_t, Work> work;
     std::map<hipStream_t, std::pair<double *, int64_t>> recon_scratch;  // partials, blocks
+    void *paper_mem = nullptr;   // Dm | T | P of the paper's search, n x n each
     // kernel timing (riann_set_profiling)
     std::atomic<bool> profiling{false};
     std::mutex pmu;
@@ -290,6 +291,7 @@ void free_index(riann_index *h) {
     }
     for (auto &kv : h->work) (void)hipFree(kv.second.patches);
     for (auto &kv : h->recon_scratch) (void)hipFree(kv.second.first);
+    if (h->paper_mem) (void)hipFree(h->paper_mem);
     if (h->dmem) (void)hipFree(h->dmem);
     delete h;
 }
@@ -775,6 +777,107 @@ riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
         out->launches[k] = h->prof_launches[k];
         out->ms[k] = h->prof_ms[k];
     }
+    return RIANN_OK;
+}
+
+riann_status_t riann_build_paper_tables(riann_index_t h, void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (h->paper_mem) return RIANN_OK;
+    const int64_t n = h->n;
+    const int D = h->D;
+    if (n > kMaxPaperN) return fail(RIANN_E_UNSUPPORTED, "the paper's tables need n <= 32768");
+    const size_t nn = (size_t)n * (size_t)n;
+    std::vector<uint32_t> dm, tv;
+    std::vector<int32_t> tp;
+    try {
+        dm.resize(nn);
+        tv.resize(nn);
+        tp.resize(nn);
+    } catch (const std::bad_alloc &) {
+        return fail(RIANN_E_NOMEM, "host memory for the n x n tables");
+    }
+    // pairwise SSD rows, each sorted by (value, index); rows split over threads
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        std::vector<uint64_t> pr((size_t)n);
+        for (int64_t i; (i = next.fetch_add(1)) < n;) {
+            const uint8_t *ri = &h->ref[(size_t)i * D];
+            for (int64_t j = 0; j < n; ++j) {
+                const uint8_t *rj = &h->ref[(size_t)j * D];
+                uint32_t s = 0;
+                for (int k = 0; k < D; ++k) {
+                    const int d = (int)ri[k] - (int)rj[k];
+                    s += (uint32_t)(d * d);
+                }
+                dm[(size_t)i * n + j] = s;
+                pr[(size_t)j] = ((uint64_t)s << 32) | (uint64_t)j;
+            }
+            std::sort(pr.begin(), pr.end());
+            for (int64_t j = 0; j < n; ++j) {
+                tv[(size_t)i * n + j] = (uint32_t)(pr[(size_t)j] >> 32);
+                tp[(size_t)i * n + j] = (int32_t)(pr[(size_t)j] & 0xFFFFFFFFu);
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned k = 0; k < nt; ++k) th.emplace_back(work);
+    for (auto &x : th) x.join();
+    DeviceGuard g(h->device);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, nn * 12) != hipSuccess)
+        return fail(RIANN_E_NOMEM, "hipMalloc of the n x n tables failed");
+    hipStream_t st = (hipStream_t)hip_stream;
+    char *b = (char *)mem;
+    hipError_t e = hipMemcpyAsync(b, dm.data(), nn * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + nn * 4, tv.data(), nn * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + nn * 8, tp.data(), nn * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "upload of the n x n tables");
+    }
+    h->paper_mem = mem;
+    return RIANN_OK;
+}
+
+riann_status_t riann_match_paper(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
+                                 int64_t pitch, const int32_t *prev_dev, int32_t *out_dev,
+                                 uint32_t *ssd_dev, int32_t *iters_dev, int32_t L, uint64_t seed,
+                                 uint64_t t, void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (!h->paper_mem) return fail(RIANN_E_INVALID, "call riann_build_paper_tables first");
+    if (L < 1) return fail(RIANN_E_INVALID, "L must be >= 1");
+    FrameBatch fb;
+    fb.n = 1;
+    riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, prev_dev, out_dev, ssd_dev,
+                                  RIANN_MODE_RING, &fb.f[0]);
+    if (s != RIANN_OK) return s;
+    const int64_t Q = (int64_t)fb.f[0].Hq * fb.f[0].Wq;
+    if (iters_dev && (overlap(iters_dev, (size_t)Q * 4, out_dev, (size_t)Q * 4) ||
+                      overlap(iters_dev, (size_t)Q * 4, ssd_dev, (size_t)Q * 4)))
+        return fail(RIANN_E_INVALID, "iters overlaps an output");
+    DeviceGuard g(h->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    FrameDesc &fd = fb.f[0];
+    fd.qbase = 0;
+    fd.tbase = 0;
+    fb.Q = Q;
+    fb.ntiles = ((fd.Wq + kExtTX - 1) / kExtTX) * ((fd.Hq + kExtTY - 1) / kExtTY);
+    fb.all_full = 0;
+    fb.knn = 1;
+    Work w;
+    s = get_work(h, st, Q, &w);
+    if (s != RIANN_OK) return s;
+    hipError_t e = launch_extract(h->dix, fb, w, st);
+    if (e != hipSuccess) return hip_fail(e, "k_extract launch");
+    const size_t nn = (size_t)h->n * (size_t)h->n;
+    const char *b = (const char *)h->paper_mem;
+    PaperArgs pa{(const uint32_t *)b, (const uint32_t *)(b + nn * 4), (const int32_t *)(b + nn * 8),
+                 L, 0, seed, t, iters_dev};
+    e = launch_paper(h->dix, fb, w, pa, st);
+    if (e != hipSuccess) return hip_fail(e, "k_paper launch");
+    h->frames.fetch_add(1);
     return RIANN_OK;
 }
 

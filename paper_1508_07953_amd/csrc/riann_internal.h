@@ -169,6 +169,23 @@ bool knn_dense_supported(const DevIndex &ix);
 hipError_t launch_dense_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                             hipStream_t st);
 
+// The paper's approximate search (k_paper.hip, Algorithm 1, alpha = 1/4):
+// Dm n x n SSD between references, T/P each row of Dm sorted by (value,
+// index) -- values and indices; iters (optional) receives anchors per query.
+constexpr int64_t kMaxPaperN = 32768;
+struct PaperArgs {
+    const uint32_t *Dm;
+    const uint32_t *T;
+    const int32_t *P;
+    int32_t L;
+    int32_t pad;
+    uint64_t seed, t;
+    int32_t *iters;
+};
+size_t paper_lds_bytes(int64_t n);
+hipError_t launch_paper(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                        const PaperArgs &pa, hipStream_t st);
+
 // Column-layout dense search of an explicit list with a device-side count.
 hipError_t launch_dense_list(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              const uint32_t *list, const uint32_t *count, hipStream_t st);
