@@ -130,7 +130,8 @@ def paper_mode(idx, frames, hq, wq, dev, log_fn, nframes=12, timed=6):
             "frames": f"{nframes} from a random field, last {timed} timed"}
 
 
-def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
+def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=None,
+                    label=None):
     """Serving (continuous batching) vs plain (one frame at a time) on a
     scaled serving workload: `streams` RGB streams, stream id mod 3 ->
     640x360 / 1280x720 / 1920x1080, 8x8x3 patches, one shared reference set
@@ -143,12 +144,13 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
     import paper_1508_07953_amd as riann
     from paper_1508_07953_amd import serve
 
+    shape_of = shape_of or gen.serving_stream_shape
     wl = gen.make_workload("serving")
     idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=3, stride=1)
     t0 = time.time()
     frames = []
     for s in range(streams):
-        H, W = gen.serving_stream_shape(s)
+        H, W = shape_of(s)
         v = gen.make_video("serving", stream=s, H=H, W=W, frames=frames_per_stream)
         frames.append([torch.from_numpy(v.frame(k)).to(dev) for k in range(frames_per_stream)])
     log_fn(f"serving: generated {streams} x {frames_per_stream} frames in {time.time() - t0:.1f}s")
@@ -158,7 +160,7 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
 
     def run(max_batch, inflight, trace, scale):
         srv = serve.Server(idx, max_batch=max_batch, inflight=inflight)
-        sids = {s: srv.open_stream(*gen.serving_stream_shape(s)) for s in range(streams)}
+        sids = {s: srv.open_stream(*shape_of(s)) for s in range(streams)}
         # warm the per-stream scratch and kernels
         for s in range(streams):
             srv.submit(sids[s], frame_of(s, 0), full=True)
@@ -167,11 +169,11 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
         r = serve.replay(srv, trace, frame_of, sids, time_scale=scale)
         per_res = {}
         for c in srv.completed:
-            H, W = gen.serving_stream_shape(c.stream)
+            H, W = shape_of(c.stream)
             per_res.setdefault(f"{W}x{H}", []).append(c.latency * 1e3)
         r["p99_ms_by_resolution"] = {k: float(np.percentile(v, 99)) for k, v in per_res.items()}
-        q = sum(idx.field_shape(*gen.serving_stream_shape(s))[0] *
-                idx.field_shape(*gen.serving_stream_shape(s))[1] for s in range(streams))
+        q = sum(idx.field_shape(*shape_of(s))[0] *
+                idx.field_shape(*shape_of(s))[1] for s in range(streams))
         r["patches_per_s"] = r["frames_per_s"] * q / streams
         return r
 
@@ -187,12 +189,16 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn):
     trace = [(t, s, k + 1) for (t, s, k) in trace]
     plain_lat = run(1, 1, trace, 1.0)
     serve_lat = run(40, 2, trace, 1.0)
+    # latency-first setting: one batch in flight, each batch takes everything
+    # ready when the previous one completes
+    serve_lat1 = run(40, 1, trace, 1.0)
     idx.close()
-    return {"workload": f"{streams} RGB streams (360p/720p/1080p by id mod 3), 8x8x3 patches, "
-                        "n=65536, K=32, Poisson arrivals",
+    return {"workload": label or (f"{streams} RGB streams (360p/720p/1080p by id mod 3), "
+                                  "8x8x3 patches, n=65536, K=32, Poisson arrivals"),
             "saturation": {"plain": plain_sat, "serving": serve_sat},
             "lambda": lam, "offered_fps": 30.0 * lam * streams, "trace_seconds": seconds,
-            "at_lambda": {"plain": plain_lat, "serving": serve_lat}}
+            "at_lambda": {"plain": plain_lat, "serving": serve_lat,
+                          "serving_one_in_flight": serve_lat1}}
 
 
 def main():
@@ -390,6 +396,10 @@ def main():
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)
+        # small frames only: one frame no longer fills the GPU, batching does
+        result["serving_vs_plain_360p"] = serving_compare(
+            dev, 24, 3, args.serving_seconds, log, shape_of=lambda s: (360, 640),
+            label="24 RGB 640x360 streams, 8x8x3 patches, n=65536, K=32, Poisson arrivals")
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
         src = torch.ones(nb, dtype=torch.uint8, device=dev)

@@ -200,9 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
     }
 
     // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
-    // accumulator order) and hand the result to the resolve kernel through the
-    // query's record (records of dense-routed queries are free after the ring
-    // phase): rec = {Y, T1 << 2 | group mask, T2 + 1 (0: none), fallback}.
+    // accumulator order) and hand the result to the resolve kernel through
+    // the record at the query's dense-list position (the records are free
+    // once the ring scan has run): rec = {Y, T1 << 2 | group mask, T2 + 1
+    // (0: none), fallback}.
     // The minimum Y sits in tile T1 (and T2) within the masked groups' rows;
     // three or more tiles go to the fallback.
 #pragma unroll
@@ -238,9 +239,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
             if (n == 2) T2p = hi + 1;
             if (n > 2) fbk = 1;
         }
-        const bool live = qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col) < count;
-        if (live && grp == 0)
-            (half ? w.rec2 : w.rec)[qid[qb]] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
+        const uint32_t slot = qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col);
+        if (slot < count && grp == 0)
+            (half ? w.rec2 : w.rec)[slot] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
     }
 }
 
@@ -261,10 +262,11 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
     const bool live = i < count;
     const uint32_t q = live ? (list ? list[i] : i) : 0u;
     // merge the two reference halves: the smaller Y wins; at equal Y the
-    // tiles of both (disjoint ranges) are checked in both lane groups
+    // tiles of both (disjoint ranges) are checked in both lane groups.  The
+    // records sit at the list position, so they load alongside the list.
     uint4 rec = make_uint4(0u, 0u, 0u, 1u);
     if (live) {
-        const uint4 r0 = w.rec[q], r1 = w.rec2[q];
+        const uint4 r0 = w.rec[i], r1 = w.rec2[i];
         if (r0.x != r1.x) {
             rec = r0.x < r1.x ? r0 : r1;
         } else {

@@ -97,9 +97,10 @@ struct Work {
     uint8_t *patches;    // Q x Dp encoded query patches (a = q ^ 0x7F, zero padded)
     int32_t *qc;         // Q, Qc of each query
     uint8_t *fid;        // Q, frame of each query within its launch
-    uint4 *rec;          // Q records {c, kstar, st, en}; row-layout dense: the
-                         // first reference half's result
-    uint4 *rec2;         // Q, row-layout dense: the second reference half's
+    uint4 *rec;          // Q ring records {c, kstar, st, en}, by query; after the
+                         // ring scan, row-layout dense: the first reference
+                         // half's result, by dense-list position
+    uint4 *rec2;         // Q, row-layout dense: the second half's, likewise
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
     uint32_t *fb_list;   // Q, queries the row-layout resolve step leaves open
