@@ -149,12 +149,15 @@ template <int DP>
 __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb, Work w,
                                                       unsigned long long *__restrict__ stats,
                                                       int64_t threshold) {
-    extern __shared__ uint32_t s_samp[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t s_samp[];
     __shared__ uint32_t s_wcnt[kRingWaves][2];
     __shared__ uint32_t s_base[2];
     __shared__ unsigned long long s_st[kRingWaves][4];
     const int nsamp = ix.K * ix.ns;
-    for (int i = threadIdx.x; i < nsamp; i += kRingBlock) s_samp[i] = ix.Ts[i];
+    // 16-byte copies (the table is 256-byte aligned): four rounds for 64 KB
+    for (int i = threadIdx.x; i < nsamp / 4; i += kRingBlock)
+        reinterpret_cast<uint4 *>(s_samp)[i] = reinterpret_cast<const uint4 *>(ix.Ts)[i];
+    for (int i = (nsamp & ~3) + threadIdx.x; i < nsamp; i += kRingBlock) s_samp[i] = ix.Ts[i];
     __syncthreads();
 
     const int64_t Q = fb.Q;
