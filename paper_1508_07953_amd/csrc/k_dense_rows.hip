@@ -416,8 +416,8 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
                        0, st, ix, fb, w, stats);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the fallback list is short; at most 1024 blocks walk it
-    const int64_t fbl = fb.Q < 1024 ? (fb.Q < 1 ? 1 : fb.Q) : 1024;
+    // the fallback list is short; at most 256 blocks walk it
+    const int64_t fbl = fb.Q < 256 ? (fb.Q < 1 ? 1 : fb.Q) : 256;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_brute_list<DP>), dim3((unsigned)fbl), dim3(256), 0, st,
                        ix, fb, w, (const uint32_t *)w.fb_list, (const uint32_t *)(w.counters + 2));
     return hipGetLastError();
