@@ -110,7 +110,7 @@ int64_t index_bytes(int64_t n, int D, int K) {
            (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 32 + 12) + 8192; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 64 + 12) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -331,7 +331,7 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
     nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
     nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
-    nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 16, 256);
+    nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 48, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.fb_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);

@@ -8,15 +8,19 @@
 // exactly.  Per (query, tile) a lane holds 16 rows of one query column: a
 // v_min3 tree gives the tile minimum of Y (about 0.5 VALU op per pair) and a
 // few compares keep, per query, the smallest Y and the first tile attaining
-// it.  A resolve kernel then recomputes that one tile's 32 exact SSDs and
-// takes their (SSD, index) minimum -- the global one, because every row
-// outside the tile has a larger Y, hence a larger SSD (2Y + p grows with Y).
-// The smallest Y can occur in several tiles (references whose SSDs differ by
-// one share a Y), so each lane also keeps the latest later tile with an equal
-// minimum and a count of them; the resolve kernel then checks up to two tiles,
-// and the rare query whose minimum Y sits in three or more tiles is answered
-// by an exhaustive per-query search (fallback list).
+// it.  A resolve kernel then recomputes the exact SSDs of that tile's rows in
+// the lane group(s) that reached the minimum and takes their (SSD, index)
+// minimum -- the global one, because every row elsewhere has a larger Y,
+// hence a larger SSD (2Y + p grows with Y).  The smallest Y can occur in
+// several tiles (references whose SSDs differ by one share a Y), so each lane
+// also keeps the latest later tile with an equal minimum and a count of them;
+// the resolve kernel then checks up to two tiles, and the rare query whose
+// minimum Y sits in three or more tiles is answered by an exhaustive
+// per-query search (fallback list).  For small frames the reference range is
+// split over up to four blocks per query chunk, which the resolve step merges.
 #include "riann_internal.h"
+
+#include <algorithm>
 
 namespace riann {
 
@@ -39,6 +43,10 @@ constexpr int kQB = RIANN_ROWS_QB;     // 32-query column blocks per wavefront
 static_assert(kQB >= 2, "the LDS prefetch runs one query block ahead");
 constexpr int kWaveQ = 32 * kQB;
 constexpr int kBlockQ = kWaveQ * kWaves;
+constexpr int kMaxSplit = 4;                   // reference-range parts per query chunk
+#ifndef RIANN_ROWS_SPLIT
+#define RIANN_ROWS_SPLIT 0                     // 0: chosen per launch
+#endif
 
 template <int KB, int ST>
 __device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
@@ -145,7 +153,8 @@ struct RowState {
 };
 
 template <int DP, int ST>
-__global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w) {
+__global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
+                                                       int nsplit) {
     constexpr int KB = DP / 32;
     constexpr int STAGE = ST * KB * 1024;
     __shared__ __attribute__((aligned(16))) int8_t s_f0[STAGE];
@@ -155,19 +164,19 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
 
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    // two blocks per query chunk, each over one half of the reference stages
-    // (even blocks the first half, odd blocks the second; consecutive blocks
-    // land on different XCDs, so each XCD's L2 holds one half)
-    const uint32_t half = blockIdx.x & 1u;
-    const uint32_t qbase = (blockIdx.x >> 1) * kBlockQ;
+    // nsplit blocks per query chunk, each over one part of the reference
+    // stages (consecutive blocks take consecutive parts and land on
+    // different XCDs, so each XCD's L2 holds fewer parts)
+    const uint32_t split = blockIdx.x % (uint32_t)nsplit;
+    const uint32_t qbase = (blockIdx.x / (uint32_t)nsplit) * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
     // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 31, grp = lane >> 5;
     const int ns_all = (int)(ix.n_pad / (kTile * ST));
-    const int s_mid = (ns_all + 1) / 2;
-    const int s_begin = half ? s_mid : 0, s_end = half ? ns_all : s_mid;
+    const int s_begin = (int)((int64_t)split * ns_all / nsplit);
+    const int s_end = (int)((int64_t)(split + 1) * ns_all / nsplit);
 
     if (s_begin < s_end) stage_dma<KB, ST>(ix.Rf, ix.Hf, s_begin, s_f0, s_h0, wv, lane);
 
@@ -240,8 +249,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
             if (n > 2) fbk = 1;
         }
         const uint32_t slot = qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col);
-        if (slot < count && grp == 0)
-            (half ? w.rec2 : w.rec)[slot] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
+        if (slot < count && grp == 0) {
+            uint4 *dst = split ? w.rec2 + (int64_t)(split - 1) * w.capacity : w.rec;
+            dst[slot] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
+        }
     }
 }
 
@@ -254,28 +265,49 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
 // counted.
 template <int DP>
 __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w,
-                                                 unsigned long long *stats) {
+                                                 unsigned long long *stats, int nsplit) {
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
     const int lane = threadIdx.x & 63, r = lane & 15;
     const uint32_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = i < count;
     const uint32_t q = live ? (list ? list[i] : i) : 0u;
-    // merge the two reference halves: the smaller Y wins; at equal Y the
-    // tiles of both (disjoint ranges) are checked in both lane groups.  The
+    // merge the parts of the reference range: the smallest Y wins; parts
+    // that tie on it contribute their tiles (disjoint ranges), checked in
+    // both lane groups -- more than two tiles in all go to the fallback.  The
     // records sit at the list position, so they load alongside the list.
     uint4 rec = make_uint4(0u, 0u, 0u, 1u);
     if (live) {
-        const uint4 r0 = w.rec[i], r1 = w.rec2[i];
-        if (r0.x != r1.x) {
-            rec = r0.x < r1.x ? r0 : r1;
-        } else {
-            const int n0 = r0.z ? 2 : 1, n1 = r1.z ? 2 : 1;
-            const uint32_t gm = (r0.y | r1.y) & 3u;
-            rec = make_uint4(r0.x, ((r0.y >> 2) << 2) | gm, 0u, (r0.w | r1.w) ? 1u : 0u);
-            if (n0 + n1 > 2) rec.w = 1u;
-            else rec.z = (r1.y >> 2) + 1;       // n0 = n1 = 1: tiles r0.T1, r1.T1
+        uint4 rp[4];
+        uint32_t ymin = ~0u;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s < nsplit) {
+                rp[s] = s ? w.rec2[(int64_t)(s - 1) * w.capacity + i] : w.rec[i];
+                ymin = min(ymin, rp[s].x);
+            }
         }
+        uint32_t t[2] = {0u, 0u}, gm = 0u, fb = 0u;
+        int nt = 0, nrec = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s < nsplit && rp[s].x == ymin) {
+                ++nrec;
+                fb |= rp[s].w;
+                gm |= rp[s].y & 3u;
+                if (nt < 2) t[nt] = rp[s].y >> 2;
+                ++nt;
+                if (rp[s].z) {
+                    if (nt < 2) t[nt] = rp[s].z - 1;
+                    ++nt;
+                }
+            }
+        }
+        // one record keeps its own group mask; tiles from several records are
+        // checked in both groups
+        if (nrec > 1) gm = 3u;
+        rec = make_uint4(ymin, (t[0] << 2) | gm, nt > 1 ? t[1] + 1 : 0u,
+                         (fb || nt > 2) ? 1u : 0u);
     }
     const bool fbk = rec.w != 0;
     unsigned long long best = ~0ull;
@@ -403,17 +435,35 @@ __global__ __launch_bounds__(256) void k_brute_list(DevIndex ix, FrameBatch fb, 
 template <int DP>
 hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                          unsigned long long *stats, hipStream_t st) {
-    int64_t blocks = 2 * ((fb.Q + kBlockQ - 1) / kBlockQ);
-    if (blocks < 2) blocks = 2;
     constexpr int ST = DP <= 64 ? 8 : 4;
     static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
+    // Split the reference range over nsplit blocks per query chunk only when
+    // there are too few chunks to give every resident block slot one (small
+    // frames); measured on a 720p frame (1,773 chunks, 768 slots) splitting
+    // costs more -- the query patches are read once per part -- than its
+    // shorter last round gains.
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(&k_dense_rows<DP, ST>), kBlock, 0);
+        resident = std::max(1, cus) * std::max(1, per);
+    }
+    const int64_t chunks = std::max<int64_t>(1, (fb.Q + kBlockQ - 1) / kBlockQ);
+    int nsplit = (int)std::min<int64_t>(kMaxSplit, (resident + chunks - 1) / chunks);
+#if RIANN_ROWS_SPLIT > 0
+    nsplit = RIANN_ROWS_SPLIT;
+#endif
+    const int64_t blocks = nsplit * chunks;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks), dim3(kBlock),
-                       0, st, ix, fb, w);
+                       0, st, ix, fb, w, nsplit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t rb = (fb.Q + 15) / 16;          // 16 queries per 256-thread block
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)(rb < 1 ? 1 : rb)), dim3(256),
-                       0, st, ix, fb, w, stats);
+                       0, st, ix, fb, w, stats, nsplit);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the fallback list is short; at most 256 blocks walk it

@@ -100,7 +100,8 @@ struct Work {
     uint4 *rec;          // Q ring records {c, kstar, st, en}, by query; after the
                          // ring scan, row-layout dense: the first reference
                          // half's result, by dense-list position
-    uint4 *rec2;         // Q, row-layout dense: the second half's, likewise
+    uint4 *rec2;         // 3 x capacity, row-layout dense: parts 1..3 of the
+                         // reference range, likewise
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
     uint32_t *fb_list;   // Q, queries the row-layout resolve step leaves open
