@@ -130,6 +130,57 @@ def paper_mode(idx, frames, hq, wq, dev, log_fn, nframes=12, timed=6):
             "frames": f"{nframes} from a random field, last {timed} timed"}
 
 
+def extras(args, result, idx, wl, frames, field, H, Wd, hq, wq, Q, K, W, dev, stream, log):
+    """Figures beside the headline: reconstruction (Sec. 4) with E, exact
+    k-NN fields, and the paper's approximate search."""
+    import torch
+    import paper_1508_07953_amd as riann
+    rf, rg = field, frames[W + K]
+    out_r, err_r = idx.reconstruct(rf, H, Wd, gt=rg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 20
+    e0.record(stream)
+    for _ in range(nrep):
+        idx.reconstruct(rf, H, Wd, gt=rg, out=out_r)
+    e1.record(stream)
+    e1.synchronize()
+    ms_r = e0.elapsed_time(e1) / nrep
+    Cc = wl.channels
+    rbytes = Q * 4 + H * Wd * Cc * (1 + 4) + int(idx.params.n_ref) * wl.D
+    result["reconstruct"] = {"ms": ms_r, "E": float(err_r[0].item()),
+                             "algorithmic_bytes": rbytes,
+                             "GBps": rbytes / (ms_r * 1e-3) / 1e9,
+                             "note": "field 4 B/query + frame 1 B and output 4 B per value + "
+                                     "appearance set once; gathers served by L2"}
+    # exact k-NN fields (k = 4) on the same frames, where the key range allows
+    try:
+        kk = 4
+        kout = [torch.empty((hq, wq, kk), dtype=torch.int32, device=dev) for _ in range(2)]
+        kss = torch.empty((hq, wq, kk), dtype=torch.int32, device=dev)
+        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
+        e1.record(stream)
+        e1.synchronize()
+        full_ms = e0.elapsed_time(e1)
+        nk = min(10, K)
+        kc = 0
+        e0.record(stream)
+        for i in range(nk):
+            idx.match_knn(frames[W + 1 + i], kk, prev=kout[kc], out=kout[1 - kc], ssd=kss)
+            kc = 1 - kc
+        e1.record(stream)
+        e1.synchronize()
+        result["knn"] = {"k": kk, "full_frame_ms": full_ms,
+                         "ring_frame_ms": e0.elapsed_time(e1) / nk, "frames": nk}
+    except riann.RiannError as ex:
+        result["knn"] = {"k": 4, "unsupported": str(ex)}
+    if not args.no_paper_mode:
+        result["paper_mode"] = paper_mode(idx, frames, hq, wq, dev, log)
+
+
 def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=None,
                     label=None):
     """Serving (continuous batching) vs plain (one frame at a time) on a
@@ -217,6 +268,9 @@ def main():
                          "library default); column: always queries as MFMA rows")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default routing threshold")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed per-frame path: no reconstruction, k-NN or paper-mode "
+                         "figures (used for kernel traces and counters)")
     ap.add_argument("--no-paper-mode", action="store_true",
                     help="skip the paper's approximate search (needs n x n tables)")
     ap.add_argument("--no-serving", action="store_true",
@@ -349,51 +403,8 @@ def main():
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
                                           for k, v in prof.items() if v["launches"]}
-    # reconstruction of the last timed frame from its field (Sec. 4), with E
-    rf, rg = bufs[cur], frames[W + K]
-    out_r, err_r = idx.reconstruct(rf, H, Wd, gt=rg)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    nrep = 20
-    e0.record(stream)
-    for _ in range(nrep):
-        idx.reconstruct(rf, H, Wd, gt=rg, out=out_r)
-    e1.record(stream)
-    e1.synchronize()
-    ms_r = e0.elapsed_time(e1) / nrep
-    Cc = wl.channels
-    rbytes = Q * 4 + H * Wd * Cc * (1 + 4) + int(idx.params.n_ref) * wl.D
-    result["reconstruct"] = {"ms": ms_r, "E": float(err_r[0].item()),
-                             "algorithmic_bytes": rbytes,
-                             "GBps": rbytes / (ms_r * 1e-3) / 1e9,
-                             "note": "field 4 B/query + frame 1 B and output 4 B per value + "
-                                     "appearance set once; gathers served by L2"}
-    # exact k-NN fields (k = 4) on the same frames, where the key range allows
-    try:
-        kk = 4
-        kout = [torch.empty((hq, wq, kk), dtype=torch.int32, device=dev) for _ in range(2)]
-        kss = torch.empty((hq, wq, kk), dtype=torch.int32, device=dev)
-        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        idx.match_knn(frames[0], kk, full=True, out=kout[0], ssd=kss)
-        e1.record(stream)
-        e1.synchronize()
-        full_ms = e0.elapsed_time(e1)
-        nk = min(10, K)
-        kc = 0
-        e0.record(stream)
-        for i in range(nk):
-            idx.match_knn(frames[W + 1 + i], kk, prev=kout[kc], out=kout[1 - kc], ssd=kss)
-            kc = 1 - kc
-        e1.record(stream)
-        e1.synchronize()
-        result["knn"] = {"k": kk, "full_frame_ms": full_ms,
-                         "ring_frame_ms": e0.elapsed_time(e1) / nk, "frames": nk}
-    except riann.RiannError as ex:
-        result["knn"] = {"k": 4, "unsupported": str(ex)}
-    if not args.no_paper_mode:
-        result["paper_mode"] = paper_mode(idx, frames, hq, wq, dev, log)
+    if not args.no_extras:
+        extras(args, result, idx, wl, frames, bufs[cur], H, Wd, hq, wq, Q, K, W, dev, stream, log)
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)
