@@ -81,11 +81,21 @@ def cpu_baseline(wl, f0, f1, target_s):
         if dt >= target_s * 0.5 or len(sel) >= Q:
             break
         m = int(min(Q, max(2 * m, m * target_s / max(dt, 1e-3))))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.set_threads(0)
+    # the same search on one core, on a smaller part of the sample
+    sel1 = sel[: max(1, min(len(sel) // 10, 16384))]
+    prev1, _ = oracle.brute_force(P0[sel1], wl.ref)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    tabs.riann(P1[sel1], prev1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {"value": done / elapsed, "unit": "patches/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} random queries of frame 1 ({Q} per frame), exact-mode RIANN "
                       f"with the oracle's brute-force field of frame 0 as prev; "
-                      f"{elapsed:.2f} s wall, table build excluded"}
+                      f"{elapsed:.2f} s wall, table build excluded",
+            "single_core_value": len(sel1) / dt1,
+            "single_core_sample": f"{len(sel1)} of the same queries on 1 thread, {dt1:.2f} s"}
 
 
 def paper_mode(idx, frames, hq, wq, dev, log_fn, nframes=12, timed=6):

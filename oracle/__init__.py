@@ -46,6 +46,8 @@ def lib():
                                        C.POINTER(C.c_uint32), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_uint64))
         L.orc_set_fault.argtypes = [C.c_int]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         L.orc_extract.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int64,
                                   C.c_int, C.c_int, u8p]
         L.orc_ssd.argtypes = [u8p, u8p, C.c_int]
@@ -87,6 +89,12 @@ def _p(a: Optional[np.ndarray], t):
 def set_fault(code: int) -> None:
     """Plant deliberate mistake `code` in the oracle (0 = correct)."""
     lib().orc_set_fault(int(code))
+
+
+def set_threads(n: int) -> int:
+    """Worker threads of the oracle's parallel loops (0: keep); returns the
+    count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def field_shape(H: int, W: int, p: int, s: int) -> Tuple[int, int]:

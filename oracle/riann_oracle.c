@@ -58,6 +58,7 @@
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so riann_oracle.c -lm
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -68,6 +69,14 @@
  * show that their pins catch it.  Zero (the default) is the correct oracle. */
 static int g_fault = 0;
 void orc_set_fault(int code) { g_fault = code; }
+
+/* Worker threads of the parallel loops (n <= 0: the OpenMP default); returns
+ * the number the next parallel loop will use. */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------ */
 /* patches                                                             */
