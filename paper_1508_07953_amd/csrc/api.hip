@@ -39,6 +39,7 @@ struct riann_index {
     std::map<hipStream_t, Work> work;
     std::map<hipStream_t, std::pair<double *, int64_t>> recon_scratch;  // partials, blocks
     void *paper_mem = nullptr;   // Dm | T | P of the paper's search, n x n each
+    std::mutex paper_mu;
     // kernel timing (riann_set_profiling)
     std::atomic<bool> profiling{false};
     std::mutex pmu;
@@ -782,6 +783,7 @@ riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
 
 riann_status_t riann_build_paper_tables(riann_index_t h, void *hip_stream) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    std::lock_guard<std::mutex> lk(h->paper_mu);     // one build per index
     if (h->paper_mem) return RIANN_OK;
     const int64_t n = h->n;
     const int D = h->D;
@@ -846,7 +848,12 @@ riann_status_t riann_match_paper(riann_index_t h, const uint8_t *frame_dev, int3
                                  uint32_t *ssd_dev, int32_t *iters_dev, int32_t L, uint64_t seed,
                                  uint64_t t, void *hip_stream) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
-    if (!h->paper_mem) return fail(RIANN_E_INVALID, "call riann_build_paper_tables first");
+    const void *pmem;
+    {
+        std::lock_guard<std::mutex> lk(h->paper_mu);
+        pmem = h->paper_mem;
+    }
+    if (!pmem) return fail(RIANN_E_INVALID, "call riann_build_paper_tables first");
     if (L < 1) return fail(RIANN_E_INVALID, "L must be >= 1");
     FrameBatch fb;
     fb.n = 1;
@@ -872,7 +879,7 @@ riann_status_t riann_match_paper(riann_index_t h, const uint8_t *frame_dev, int3
     hipError_t e = launch_extract(h->dix, fb, w, st);
     if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     const size_t nn = (size_t)h->n * (size_t)h->n;
-    const char *b = (const char *)h->paper_mem;
+    const char *b = (const char *)pmem;
     PaperArgs pa{(const uint32_t *)b, (const uint32_t *)(b + nn * 4), (const int32_t *)(b + nn * 8),
                  L, 0, seed, t, iters_dev};
     e = launch_paper(h->dix, fb, w, pa, st);
