@@ -374,15 +374,17 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
 }
 
 // Exhaustive exact search for the few queries of a list: one block per query
-// (grid-stride over the list, whose length is read on the device), each
-// thread takes every 256th reference with v_dot4, and a block reduction
-// keeps the (SSD, index) minimum.  Every block leaves the loop once its index
-// passes the count.
+// (grid-stride over the list, whose length is read on the device), each of
+// its 1024 threads takes every 1024th reference with v_dot4, and a block
+// reduction keeps the (SSD, index) minimum.  Every block leaves the loop once
+// its index passes the count.
+constexpr int kBruteT = 1024;
+
 template <int DP>
-__global__ __launch_bounds__(256) void k_brute_list(DevIndex ix, FrameBatch fb, Work w,
+__global__ __launch_bounds__(kBruteT) void k_brute_list(DevIndex ix, FrameBatch fb, Work w,
                                                     const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ count_ptr) {
-    __shared__ unsigned long long s_red[4];
+    __shared__ unsigned long long s_red[kBruteT / 64];
     const uint32_t count = *count_ptr;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(256) void k_brute_list(DevIndex ix, FrameBatch fb, 
         }
         const int Qc = w.qc[q];
         unsigned long long best = ~0ull;
-        for (int64_t r = tid; r < ix.n; r += 256) {
+        for (int64_t r = tid; r < ix.n; r += kBruteT) {
             const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + r * DP);
             int d = 0;
 #pragma unroll
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(256) void k_brute_list(DevIndex ix, FrameBatch fb, 
         __syncthreads();
         if (tid == 0) {
             unsigned long long b = s_red[0];
-            for (int k = 1; k < 4; ++k) b = s_red[k] < b ? s_red[k] : b;
+            for (int k = 1; k < kBruteT / 64; ++k) b = s_red[k] < b ? s_red[k] : b;
             const FrameDesc *fdp = &fb.f[w.fid[q]];
             const int64_t ql = (int64_t)q - fdp->qbase;
             fdp->out[ql] = (int32_t)(uint32_t)b;
@@ -468,7 +470,7 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
     if (e != hipSuccess) return e;
     // the fallback list is short; at most 256 blocks walk it
     const int64_t fbl = fb.Q < 256 ? (fb.Q < 1 ? 1 : fb.Q) : 256;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_brute_list<DP>), dim3((unsigned)fbl), dim3(256), 0, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_brute_list<DP>), dim3((unsigned)fbl), dim3(kBruteT), 0, st,
                        ix, fb, w, (const uint32_t *)w.fb_list, (const uint32_t *)(w.counters + 2));
     return hipGetLastError();
 }
