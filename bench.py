@@ -413,6 +413,26 @@ def main():
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
                                           for k, v in prof.items() if v["launches"]}
+        # the other per-frame kernels against the HBM roofline (algorithmic
+        # bytes per frame; both are bound elsewhere, see the notes)
+        Dp = (wl.D + 31) // 32 * 32
+        sec = {}
+        if prof["ring"]["launches"]:
+            rb = Q * (Dp + 4 + 4 + wl.D + 16 + 4)
+            rms = prof["ring"]["ms"] / prof["ring"]["launches"]
+            sec["k_ring"] = {"bound": "alu", "algorithmic_bytes": rb, "ms": rms,
+                             "GBps": rb / (rms * 1e-3) / 1e9, "hbm_frac": rb / (rms * 1e-3) / 1e9
+                             / HBM_PEAK_GBS,
+                             "note": "patch, Qc, prev, r_prev row, record and list entry per "
+                                     "query; VALU-bound (key distances and binary searches)"}
+        if prof["extract"]["launches"]:
+            eb = H * Wd * wl.channels + Q * (Dp + 4 + 1)
+            ems = prof["extract"]["ms"] / prof["extract"]["launches"]
+            sec["k_extract"] = {"bound": "hbm", "algorithmic_bytes": eb, "ms": ems,
+                                "GBps": eb / (ems * 1e-3) / 1e9,
+                                "hbm_frac": eb / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "note": "frame read once, encoded patch + Qc + frame id written"}
+        result["secondary_kernels"] = sec
     if not args.no_extras:
         extras(args, result, idx, wl, frames, bufs[cur], H, Wd, hq, wq, Q, K, W, dev, stream, log)
     if not args.no_serving:
