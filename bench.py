@@ -403,7 +403,7 @@ def main():
         ops = 2.0 * dense_q_per_launch * n * D
         achieved = ops / (ms_per_launch * 1e-3) / 1e12
         rows = args.dense_layout == "auto" and wl.D <= 96
-        kname = ("k_dense_rows + k_resolve (int8 MFMA, references as rows)" if rows else
+        kname = ("k_dense_rows (int8 MFMA, references as rows, own candidate check)" if rows else
                  "k_dense (int8 MFMA, queries as rows)")
         result["roofline"] = {"bound": "mfma", "kernel": kname,
                               "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",

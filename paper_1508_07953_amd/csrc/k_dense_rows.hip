@@ -8,16 +8,18 @@
 // exactly.  Per (query, tile) a lane holds 16 rows of one query column: a
 // v_min3 tree gives the tile minimum of Y (about 0.5 VALU op per pair) and a
 // few compares keep, per query, the smallest Y and the first tile attaining
-// it.  A resolve kernel then recomputes the exact SSDs of that tile's rows in
-// the lane group(s) that reached the minimum and takes their (SSD, index)
-// minimum -- the global one, because every row elsewhere has a larger Y,
-// hence a larger SSD (2Y + p grows with Y).  The smallest Y can occur in
-// several tiles (references whose SSDs differ by one share a Y), so each lane
-// also keeps the latest later tile with an equal minimum and a count of them;
-// the resolve kernel then checks up to two tiles, and the rare query whose
-// minimum Y sits in three or more tiles is answered by an exhaustive
+// it.  After its last tile the wavefront recomputes the exact SSDs of that
+// tile's rows in the lane group(s) that reached the minimum and takes their
+// (SSD, index) minimum -- the global one, because every row elsewhere has a
+// larger Y, hence a larger SSD (2Y + p grows with Y); these gathers overlap
+// the matrix work of the other wavefronts on the SIMD.  The smallest Y can
+// occur in several tiles (references whose SSDs differ by one share a Y), so
+// each lane also keeps the latest later tile with an equal minimum and a
+// count of them; the check then covers up to two tiles, and the rare query
+// whose minimum Y sits in three or more tiles is answered by an exhaustive
 // per-query search (fallback list).  For small frames the reference range is
-// split over up to four blocks per query chunk, which the resolve step merges.
+// split over up to four blocks per query chunk; the parts then leave records
+// that a resolve kernel merges before the same check.
 #include "riann_internal.h"
 
 #include <algorithm>
@@ -152,9 +154,118 @@ struct RowState {
     }
 };
 
+// Candidate check of one dense query by a 16-lane group: lane r takes
+// accumulator row r of each recorded (tile, lane group) -- tile row
+// 8(r/4) + 4g + r%4 -- forms its exact SSD with v_dot4, and a 16-lane
+// reduction keeps the (SSD, index) minimum, which is the global one since
+// every other row has a larger Y.  rec = {Y, T1 << 2 | group mask, T2 + 1
+// (0: none), fallback}.  load() issues the query patch and the first
+// candidate row, finish() does the rest, so a caller can issue the loads of
+// two queries before either waits.  Queries flagged for the fallback are
+// appended to the fallback list and counted; finish() is called by every lane
+// of the wavefront (the append is a wave-wide ballot).
+template <int DP>
+struct RowCheck {
+    uint4 a[DP / 16];       // query patch
+    uint4 v[DP / 16];       // first candidate row of this lane
+    int64_t ref0;           // its index (-1: none)
+    int qc;
+
+    __device__ __forceinline__ void load(const DevIndex &ix, const Work &w, uint32_t q,
+                                         const uint4 &rec, bool live, int r) {
+        ref0 = -1;
+        if (!live || rec.w) return;
+        const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 16; ++k) a[k] = src[k];
+        qc = w.qc[q];
+        // the first candidate is always tile T1, in the first masked group
+        const int g = (rec.y & 1u) ? 0 : 1;
+        const int64_t ref = (int64_t)(rec.y >> 2) * kTile + 8 * (r >> 2) + 4 * g + (r & 3);
+        if (ref < ix.n) {
+            ref0 = ref;
+            const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + ref * DP);
+#pragma unroll
+            for (int k = 0; k < DP / 16; ++k) v[k] = row[k];
+        }
+    }
+
+    __device__ __forceinline__ static int dot(const uint4 (&a)[DP / 16], const uint4 (&v)[DP / 16]) {
+        int d = 0;
+#pragma unroll
+        for (int k = 0; k < DP / 16; ++k) {
+            d = __builtin_amdgcn_sdot4((int)a[k].x, (int)v[k].x, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[k].y, (int)v[k].y, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[k].z, (int)v[k].z, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[k].w, (int)v[k].w, d, false);
+        }
+        return d;
+    }
+
+    __device__ __forceinline__ void finish(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                                           unsigned long long *stats, uint32_t q,
+                                           const uint4 &rec, bool live, int lane) {
+        const int r = lane & 15;
+        const bool fbk = rec.w != 0;
+        unsigned long long best = ~0ull;
+        if (live && !fbk) {
+            if (ref0 >= 0) {
+                const uint32_t ssd = (uint32_t)(qc + ix.Rc[ref0] + 2 * dot(a, v));
+                best = ((unsigned long long)ssd << 32) | (uint32_t)ref0;
+            }
+            // the other candidates: the second group of T1, then T2 (rare)
+            const uint32_t gm = rec.y & 3u;
+            const uint32_t tiles[2] = {rec.y >> 2, rec.z - 1};
+            const int ntl = rec.z ? 2 : 1;
+            const int c0 = (gm & 1u) ? 0 : 1;
+#pragma unroll
+            for (int c = 1; c < 4; ++c) {
+                const int tt = c >> 1, g = c & 1;
+                const int64_t ref = (int64_t)tiles[tt] * kTile + 8 * (r >> 2) + 4 * g + (r & 3);
+                if (c > c0 && tt < ntl && ((gm >> g) & 1u) && ref < ix.n) {
+                    uint4 u[DP / 16];
+                    const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + ref * DP);
+#pragma unroll
+                    for (int k = 0; k < DP / 16; ++k) u[k] = row[k];
+                    const uint32_t ssd = (uint32_t)(qc + ix.Rc[ref] + 2 * dot(a, u));
+                    const unsigned long long key = ((unsigned long long)ssd << 32) | (uint32_t)ref;
+                    best = key < best ? key : best;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            const unsigned lo = __shfl_xor((unsigned)best, m, 64);
+            const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
+            const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+            best = o < best ? o : best;
+        }
+        if (live && !fbk && r == 0) {
+            const FrameDesc *fdp = &fb.f[w.fid[q]];
+            const int64_t ql = (int64_t)q - fdp->qbase;
+            fdp->out[ql] = (int32_t)(uint32_t)best;
+            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
+        }
+        const bool mine = live && fbk && r == 0;
+        const unsigned long long fmask = __ballot(mine);
+        if (fmask) {
+            uint32_t base = 0;
+            if (lane == 0) {
+                base = atomicAdd(&w.counters[2], (uint32_t)__popcll(fmask));
+                atomicAdd(&stats[ST_FALLBACK], (unsigned long long)__popcll(fmask));
+            }
+            base = __shfl(base, 0, 64);
+            if (mine) {
+                const unsigned lo = __builtin_amdgcn_mbcnt_lo((unsigned)fmask, 0u);
+                w.fb_list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32), lo)] = q;
+            }
+        }
+    }
+};
+
 template <int DP, int ST>
 __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
-                                                       int nsplit) {
+                                                       unsigned long long *stats, int nsplit) {
     constexpr int KB = DP / 32;
     constexpr int STAGE = ST * KB * 1024;
     __shared__ __attribute__((aligned(16))) int8_t s_f0[STAGE];
@@ -209,12 +320,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
     }
 
     // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
-    // accumulator order) and hand the result to the resolve kernel through
-    // the record at the query's dense-list position (the records are free
-    // once the ring scan has run): rec = {Y, T1 << 2 | group mask, T2 + 1
-    // (0: none), fallback}.
-    // The minimum Y sits in tile T1 (and T2) within the masked groups' rows;
+    // accumulator order) into one record per query, the same in both groups:
+    // rec = {Y, T1 << 2 | group mask, T2 + 1 (0: none), fallback}.  The
+    // minimum Y sits in tile T1 (and T2) within the masked groups' rows;
     // three or more tiles go to the fallback.
+    uint4 rc[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
         const uint32_t y = S.bY[qb], t = S.bT[qb], t2 = S.bT2[qb], c = S.cnt[qb];
@@ -231,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
             if (cc == 1) T2p = (own ? t2 : oT2) + 1;
             if (cc > 1) fbk = 1;
         } else if (c > 1 || oC > 1) {
-            T1 = t; gm = 3u; fbk = 1;
+            T1 = min(t, oT); gm = 3u; fbk = 1;
         } else {
             // distinct tiles among t (< t2) and oT (< oT2)
             const uint32_t a1 = t, a2 = c ? t2 : t, b1 = oT, b2 = oC ? oT2 : oT;
@@ -248,21 +358,53 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
             if (n == 2) T2p = hi + 1;
             if (n > 2) fbk = 1;
         }
-        const uint32_t slot = qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col);
-        if (slot < count && grp == 0) {
-            uint4 *dst = split ? w.rec2 + (int64_t)(split - 1) * w.capacity : w.rec;
-            dst[slot] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
+        rc[qb] = make_uint4(min(y, oY), (T1 << 2) | gm, T2p, fbk);
+    }
+
+    const uint32_t wbase = qbase + (uint32_t)(wv * kWaveQ);
+    if (nsplit > 1) {
+        // one part of the reference range: the record goes to the resolve
+        // kernel at the query's dense-list position (the records are free
+        // once the ring scan has run)
+        uint4 *dst = split ? w.rec2 + (int64_t)(split - 1) * w.capacity : w.rec;
+#pragma unroll
+        for (int qb = 0; qb < kQB; ++qb) {
+            const uint32_t slot = wbase + (uint32_t)(qb * 32 + col);
+            if (slot < count && grp == 0) dst[slot] = rc[qb];
+        }
+        return;
+    }
+    // the whole reference range: the wavefront checks its own queries, four
+    // at a time (one per 16-lane group), the loads of two such passes in
+    // flight together; the records and query ids come from the owning lanes
+    const int sub = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb) {
+        for (int h = 0; h < 32; h += 8) {
+            const int ca = h + sub, cb = h + 4 + sub;
+            const uint4 ra = make_uint4(__shfl(rc[qb].x, ca, 64), __shfl(rc[qb].y, ca, 64),
+                                        __shfl(rc[qb].z, ca, 64), __shfl(rc[qb].w, ca, 64));
+            const uint4 rb = make_uint4(__shfl(rc[qb].x, cb, 64), __shfl(rc[qb].y, cb, 64),
+                                        __shfl(rc[qb].z, cb, 64), __shfl(rc[qb].w, cb, 64));
+            const uint32_t qa = (uint32_t)__shfl((int)qid[qb], ca, 64);
+            const uint32_t qbq = (uint32_t)__shfl((int)qid[qb], cb, 64);
+            const bool la = wbase + (uint32_t)(qb * 32 + ca) < count;
+            const bool lb = wbase + (uint32_t)(qb * 32 + cb) < count;
+            RowCheck<DP> A, B;
+            A.load(ix, w, qa, ra, la, r);
+            B.load(ix, w, qbq, rb, lb, r);
+            A.finish(ix, fb, w, stats, qa, ra, la, lane);
+            B.finish(ix, fb, w, stats, qbq, rb, lb, lane);
         }
     }
 }
 
-// Resolve step: 16 lanes per dense query, lane r taking accumulator row r of
-// each recorded (tile, lane group) -- tile row 8(r/4) + 4g + r%4 -- so the
-// loads of one query's candidate rows are issued together.  Each lane forms
-// the exact SSD with v_dot4; a 16-lane reduction keeps the (SSD, index)
-// minimum, which is the global one since every other row has a larger Y.
-// Queries flagged for the fallback are appended to the fallback list and
-// counted.
+// Resolve step of a launch whose reference range is split over several
+// blocks per query chunk: 16 lanes per dense query merge the parts' records
+// (the smallest Y wins; parts that tie on it contribute their tiles, disjoint
+// ranges, checked in both lane groups -- more than two tiles in all go to the
+// fallback) and run the candidate check.  The records sit at the list
+// position, so they load alongside the list.
 template <int DP>
 __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w,
                                                  unsigned long long *stats, int nsplit) {
@@ -272,16 +414,12 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
     const uint32_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = i < count;
     const uint32_t q = live ? (list ? list[i] : i) : 0u;
-    // merge the parts of the reference range: the smallest Y wins; parts
-    // that tie on it contribute their tiles (disjoint ranges), checked in
-    // both lane groups -- more than two tiles in all go to the fallback.  The
-    // records sit at the list position, so they load alongside the list.
     uint4 rec = make_uint4(0u, 0u, 0u, 1u);
     if (live) {
-        uint4 rp[4];
+        uint4 rp[kMaxSplit];
         uint32_t ymin = ~0u;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < kMaxSplit; ++s) {
             if (s < nsplit) {
                 rp[s] = s ? w.rec2[(int64_t)(s - 1) * w.capacity + i] : w.rec[i];
                 ymin = min(ymin, rp[s].x);
@@ -290,7 +428,7 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
         uint32_t t[2] = {0u, 0u}, gm = 0u, fb = 0u;
         int nt = 0, nrec = 0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < kMaxSplit; ++s) {
             if (s < nsplit && rp[s].x == ymin) {
                 ++nrec;
                 fb |= rp[s].w;
@@ -309,68 +447,9 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
         rec = make_uint4(ymin, (t[0] << 2) | gm, nt > 1 ? t[1] + 1 : 0u,
                          (fb || nt > 2) ? 1u : 0u);
     }
-    const bool fbk = rec.w != 0;
-    unsigned long long best = ~0ull;
-    if (!fbk) {
-        const uint32_t gm = rec.y & 3u;
-        const uint32_t tiles[2] = {rec.y >> 2, rec.z - 1};
-        const int ntl = rec.z ? 2 : 1;
-        uint32_t a[DP / 4];
-        const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP);
-#pragma unroll
-        for (int k = 0; k < DP / 16; ++k) {
-            const uint4 v = src[k];
-            a[4 * k] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
-        }
-        const int Qc = w.qc[q];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int tt = c >> 1, g = c & 1;
-            const int64_t ref = (int64_t)tiles[tt] * kTile + 8 * (r >> 2) + 4 * g + (r & 3);
-            if (tt < ntl && ((gm >> g) & 1u) && ref < ix.n) {
-                const uint4 *row = reinterpret_cast<const uint4 *>(ix.Rv + ref * DP);
-                int d = 0;
-#pragma unroll
-                for (int k = 0; k < DP / 16; ++k) {
-                    const uint4 v = row[k];
-                    d = __builtin_amdgcn_sdot4((int)a[4 * k], (int)v.x, d, false);
-                    d = __builtin_amdgcn_sdot4((int)a[4 * k + 1], (int)v.y, d, false);
-                    d = __builtin_amdgcn_sdot4((int)a[4 * k + 2], (int)v.z, d, false);
-                    d = __builtin_amdgcn_sdot4((int)a[4 * k + 3], (int)v.w, d, false);
-                }
-                const uint32_t ssd = (uint32_t)(Qc + ix.Rc[ref] + 2 * d);
-                const unsigned long long key = ((unsigned long long)ssd << 32) | (uint32_t)ref;
-                best = key < best ? key : best;
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) {
-        const unsigned lo = __shfl_xor((unsigned)best, m, 64);
-        const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
-        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-        best = o < best ? o : best;
-    }
-    if (live && !fbk && r == 0) {
-        const FrameDesc *fdp = &fb.f[w.fid[q]];
-        const int64_t ql = (int64_t)q - fdp->qbase;
-        fdp->out[ql] = (int32_t)(uint32_t)best;
-        if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
-    }
-    const bool mine = live && fbk && r == 0;
-    const unsigned long long fmask = __ballot(mine);
-    if (fmask) {
-        uint32_t base = 0;
-        if (lane == 0) {
-            base = atomicAdd(&w.counters[2], (uint32_t)__popcll(fmask));
-            atomicAdd(&stats[ST_FALLBACK], (unsigned long long)__popcll(fmask));
-        }
-        base = __shfl(base, 0, 64);
-        if (mine) {
-            const unsigned lo = __builtin_amdgcn_mbcnt_lo((unsigned)fmask, 0u);
-            w.fb_list[base + __builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32), lo)] = q;
-        }
-    }
+    RowCheck<DP> C;
+    C.load(ix, w, q, rec, live, r);
+    C.finish(ix, fb, w, stats, q, rec, live, lane);
 }
 
 // Exhaustive exact search for the few queries of a list: one block per query
@@ -460,14 +539,18 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
 #endif
     const int64_t blocks = nsplit * chunks;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks), dim3(kBlock),
-                       0, st, ix, fb, w, nsplit);
+                       0, st, ix, fb, w, stats, nsplit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t rb = (fb.Q + 15) / 16;          // 16 queries per 256-thread block
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)(rb < 1 ? 1 : rb)), dim3(256),
-                       0, st, ix, fb, w, stats, nsplit);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (nsplit > 1) {
+        // the parts meet in a resolve step (one part: the row kernel checks
+        // its own candidates)
+        const int64_t rb = (fb.Q + 15) / 16;      // 16 queries per 256-thread block
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)(rb < 1 ? 1 : rb)),
+                           dim3(256), 0, st, ix, fb, w, stats, nsplit);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     // the fallback list is short; at most 256 blocks walk it
     const int64_t fbl = fb.Q < 256 ? (fb.Q < 1 ? 1 : fb.Q) : 256;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_brute_list<DP>), dim3((unsigned)fbl), dim3(kBruteT), 0, st,

@@ -98,9 +98,9 @@ struct Work {
     int32_t *qc;         // Q, Qc of each query
     uint8_t *fid;        // Q, frame of each query within its launch
     uint4 *rec;          // Q ring records {c, kstar, st, en}, by query; after the
-                         // ring scan, row-layout dense: the first reference
-                         // half's result, by dense-list position
-    uint4 *rec2;         // 3 x capacity, row-layout dense: parts 1..3 of the
+                         // ring scan, row-layout dense with a split reference
+                         // range: part 0's result, by dense-list position
+    uint4 *rec2;         // 3 x capacity, row-layout dense: parts 1..3 of a split
                          // reference range, likewise
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
@@ -126,9 +126,11 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // device-side count.  Reads the query patches written by launch_extract.
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st);
-// Row-layout dense search (D <= 96): the row kernel, the resolve kernel and
-// the exhaustive search of the rare queries it cannot resolve (w.fb_list,
-// count w.counters[2], which must start at 0; counted in ST_FALLBACK).
+// Row-layout dense search (D <= 96): the row kernel (which checks its own
+// candidates unless the reference range is split, when a resolve kernel
+// merges the parts) and the exhaustive search of the rare queries neither
+// can resolve (w.fb_list, count w.counters[2], which must start at 0; counted
+// in ST_FALLBACK).
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              unsigned long long *stats, hipStream_t st);
