@@ -390,7 +390,6 @@ def main():
         "p99_frame_ms": float(np.percentile(lat, 99)),
         "routing": {"ring_queries": st["ring_queries"], "dense_queries": st["dense_queries"],
                     "mean_mstar": st["sum_mstar"] / max(1, st["queries"]),
-                    "dense_fallback_per_frame": st["dense_fallback"] / max(1, K),
                     "dense_threshold": int(idx.params.dense_threshold),
                     "autotune_ms_per_frame": tuned["ms"] if tuned else None},
     }

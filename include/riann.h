@@ -120,9 +120,6 @@ typedef struct riann_stats {
     uint64_t sum_survivors;    /* sum over ring-scanned queries of |S|, the
                                   number of references inside all K rings     */
     uint64_t sum_mstar_ring;   /* sum of m* over ring-scanned queries only     */
-    uint64_t dense_fallback;   /* row-layout dense search only: queries whose
-                                  minimum the tile-resolve step could not pin
-                                  down, answered by an exhaustive search      */
 } riann_stats_t;
 
 /*

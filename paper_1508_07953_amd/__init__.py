@@ -66,7 +66,7 @@ class Profile(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in
                 ("frames", "queries", "ring_queries", "dense_queries", "no_prior",
-                 "sum_mstar", "sum_survivors", "sum_mstar_ring", "dense_fallback")]
+                 "sum_mstar", "sum_survivors", "sum_mstar_ring")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

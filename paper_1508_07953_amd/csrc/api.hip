@@ -103,15 +103,32 @@ int64_t default_threshold(int64_t n) {
     return t < 64 ? 64 : t;
 }
 
+// Rows of the row-layout dense search's reference order (even Rc, then odd
+// Rc, each class padded to whole tiles, the whole to kRefAlign), or 0 where
+// that layout is not used: Dp > 96, or more tiles than its parts can key.
+// With Rc == nullptr: the most rows any reference set of this size can take.
+int64_t row_layout_rows(int64_t n, int Dp, const std::vector<int32_t> *Rc) {
+    if (Dp > 96) return 0;
+    int64_t n0 = n;
+    if (Rc) {
+        n0 = 0;
+        for (int64_t r = 0; r < n; ++r) n0 += ((*Rc)[(size_t)r] & 1) == 0;
+    }
+    const int64_t rows = Rc ? round_up(round_up(n0, kTile) + round_up(n - n0, kTile), kRefAlign)
+                            : round_up(round_up(n, kTile) + kTile, kRefAlign);
+    return rows / kTile > ((int64_t)kRowMaxParts << kRowTileBits) ? 0 : rows;
+}
+
 int64_t index_bytes(int64_t n, int D, int K) {
     const int Dp = (int)round_up(D, 32);
     const int64_t n_pad = round_up(n, kRefAlign);
     const int64_t n16 = round_up(n, 16), Kp = round_up(std::max(K, 1), 4);
+    const int64_t n_rows = row_layout_rows(n, Dp, nullptr);
     return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
-           (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
+           n_rows * (Dp + 12) + (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 64 + 12) + 8192; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 64 + 8) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -182,20 +199,6 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         Rc[(size_t)r] = s;
         Rk[(size_t)r] = (uint32_t)(s + bias) << jb;
     }
-    // row-layout tables, permuted per tile to the accumulator row order
-    std::vector<int32_t> Hf((size_t)n_pad, 1 << 30);
-    for (int64_t t = 0; t < n_pad / kTile; ++t)
-        for (int g = 0; g < 2; ++g)
-            for (int r = 0; r < 16; ++r) {
-                const int m = 8 * (r / 4) + 4 * g + r % 4;
-                const int64_t ref = t * kTile + m;
-                const size_t o = (size_t)(t * kTile + g * 16 + r);
-                if (ref < n) {
-                    const int64_t rc = Rc[(size_t)ref];
-                    const int64_t p = rc & 1;
-                    Hf[o] = (int32_t)((rc + bias - p) / 2);
-                }
-            }
     const int KB = Dp / 32;
     for (int64_t r = 0; r < n_pad; ++r)
         for (int kb = 0; kb < KB; ++kb)
@@ -204,6 +207,39 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                 std::memcpy(&Rf[(size_t)(((t * KB + kb) * 64 + l) * 16)],
                             &Rv[(size_t)(r * Dp + kb * 32 + 16 * g)], 16);
             }
+    // row-layout tables over the class order (even Rc, then odd Rc)
+    const int64_t n_rows = row_layout_rows(n, Dp, &Rc);
+    std::vector<int8_t> Rfr((size_t)n_rows * Dp, 0);
+    std::vector<int32_t> Hf((size_t)n_rows, kRowPadY);
+    std::vector<int32_t> Rci((size_t)n_rows * 2, 0);
+    if (n_rows > 0) {
+        std::vector<int64_t> order((size_t)n_rows, -1);
+        int64_t pos = 0;
+        for (int cls = 0; cls < 2; ++cls) {
+            for (int64_t r = 0; r < n; ++r)
+                if ((Rc[(size_t)r] & 1) == cls) order[(size_t)pos++] = r;
+            pos = round_up(pos, kTile);
+        }
+        for (int64_t i = 0; i < n_rows; ++i) {
+            const int64_t r = order[(size_t)i];
+            Rci[(size_t)(2 * i)] = r < 0 ? 0 : Rc[(size_t)r];
+            Rci[(size_t)(2 * i + 1)] = (int32_t)r;
+            if (r < 0) continue;
+            const int64_t t = i / kTile;
+            for (int kb = 0; kb < KB; ++kb)
+                for (int g = 0; g < 2; ++g)
+                    std::memcpy(&Rfr[(size_t)(((t * KB + kb) * 64 + (i % kTile) + 32 * g) * 16)],
+                                &Rv[(size_t)(r * Dp + kb * 32 + 16 * g)], 16);
+        }
+        for (int64_t t = 0; t < n_rows / kTile; ++t)
+            for (int g = 0; g < 2; ++g)
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t ref = order[(size_t)(t * kTile + 8 * (r / 4) + 4 * g + r % 4)];
+                    if (ref < 0) continue;
+                    const int64_t rc = Rc[(size_t)ref];
+                    Hf[(size_t)(t * kTile + g * 16 + r)] = (int32_t)((rc + bias - (rc & 1)) / 2);
+                }
+    }
     // ring-phase tables: T padded to 16-entry lines, LDS samples, padded Piv
     const int64_t n16 = round_up(n, 16);
     int64_t s0l = 1;   // sample stride in lines: samples of all keys fit 64 KB
@@ -223,9 +259,10 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szP = (size_t)std::max<int64_t>(K * n, 1) * 4,
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
                  szS = ST_COUNT * 8, szTs = Ts.size() * 4;
-    size_t off[11], tot = 0;
-    const size_t sz[11] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szRc};
-    for (int i = 0; i < 11; ++i) {
+    const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8;
+    size_t off[13], tot = 0;
+    const size_t sz[13] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci};
+    for (int i = 0; i < 13; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -249,6 +286,9 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.bias = (int32_t)bias;
     h->dix.Ts = (const uint32_t *)(b + off[9]);
     h->dix.Hf = (const int32_t *)(b + off[10]);
+    h->dix.Rfr = (const int8_t *)(b + off[11]);
+    h->dix.Rci = (const int2 *)(b + off[12]);
+    h->dix.n_rows = n_rows;
     h->dix.n16 = (int32_t)n16;
     h->dix.ns = (int32_t)ns;
     h->dix.s0l = (int32_t)s0l;
@@ -268,7 +308,9 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         {b + off[5], h->keys.data(), (size_t)K * 4},
         {b + off[7], Rf.data(), szRv},          {b + off[8], Rk.data(), szRc},
         {b + off[9], Ts.data(), (size_t)K * ns * 4},
-        {b + off[10], Hf.data(), szRc},
+        {b + off[10], Hf.data(), szHf},
+        {b + off[11], Rfr.data(), szRfr},
+        {b + off[12], Rci.data(), szRci},
     };
     for (auto &c : cp) {
         if (c.n == 0) continue;
@@ -335,7 +377,6 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 48, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
-    nw.fb_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
     nw.counters = (uint32_t *)(b + o);
     nw.capacity = cap;
     h->work[st] = nw;
@@ -425,7 +466,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     if (s != RIANN_OK) return s;
     hipError_t e;
     const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
-    if (!all_full || rows) {
+    if (!all_full) {
         e = launch_zero_u32(w.counters, 4, st);
         if (e != hipSuccess) return hip_fail(e, "counter clear");
     }
@@ -455,7 +496,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
         if (knn > 1) {
             e = launch_dense_knn(h->dix, fb, w, st);
         } else if (rows) {
-            e = launch_dense_rows(h->dix, fb, w, h->dstats, st);
+            e = launch_dense_rows(h->dix, fb, w, st);
         } else {
             e = launch_dense(h->dix, fb, w, st);
         }
@@ -624,7 +665,6 @@ riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
     s->sum_mstar = v[ST_MSTAR];
     s->sum_survivors = v[ST_SURV];
     s->sum_mstar_ring = v[ST_MSTAR_RING];
-    s->dense_fallback = v[ST_FALLBACK];
     return RIANN_OK;
 }
 

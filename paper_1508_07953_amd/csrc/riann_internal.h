@@ -15,6 +15,13 @@ namespace riann {
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
 constexpr int kRefAlign = 512;   // n is padded to whole 16-tile dense stages
+// Row-layout dense search: a query's running minimum is the key
+// (Y << kRowTileBits) | tile, tile counted from the start of its block's part
+// of the reference range, so a part holds at most 2^kRowTileBits tiles and a
+// launch at most kRowMaxParts parts.
+constexpr int kRowTileBits = 10;
+constexpr int kRowMaxParts = 4;
+constexpr int32_t kRowPadY = (1 << (32 - kRowTileBits)) - 1;
 constexpr int kMaxKeys = 64;
 constexpr int kMaxPatch = 16;    // p <= 16 (D = p*p*C <= 256)
 
@@ -34,13 +41,25 @@ struct DevIndex {
                           // 32t + (l & 31), columns 32kb + 16(l >> 5) .. +16,
                           // at byte offset ((t * Dp/32 + kb) * 64 + l) * 16
     const uint32_t *Rk;   // n_pad dense key bases (see above)
-    // Row-layout dense search (references as MFMA rows, queries as columns):
-    // per tile t, 32 entries ordered [g][r] = reference 32t + 8(r/4) + 4g + r%4,
-    // the row the accumulator register r of lane group g holds.
-    //   Hf  = (Rc + bias - p) / 2 with p = Rc & 1, so that
-    //         Y = Hf + <a, v> and SSD - Qc + bias = 2Y + p (exact);
-    //         padding rows get 2^30, above every real Y
+    // Row-layout dense search (references as MFMA rows, queries as columns,
+    // Dp <= 96), over its own reference order: first every reference with
+    // even Rc, then every one with odd Rc, index order within each class, each
+    // class padded to whole tiles and the whole to kRefAlign (n_rows rows;
+    // 0 when the layout is not built).  With p = Rc & 1 constant per tile,
+    // the lexicographic (Y, tile) minimum lies in the tile that holds the
+    // (SSD, index) minimum.
+    //   Rfr  n_rows x Dp, those rows in MFMA fragment order (as Rf)
+    //   Hf   n_rows, per tile t 32 entries ordered [g][r] = row 32t +
+    //        8(r/4) + 4g + r%4, the row accumulator register r of lane group g
+    //        holds: Hf = (Rc + bias - p) / 2, so that Y = Hf + <a, v> and
+    //        SSD - Qc + bias = 2Y + p (exact); Y < 2^22 for D <= 96, padding
+    //        rows get 2^22 - 1, above every real Y
+    //   Rci  n_rows, {Rc, reference index} per row in tile order ({0, -1}
+    //        for padding rows)
+    const int8_t *Rfr;
     const int32_t *Hf;
+    const int2 *Rci;
+    int64_t n_rows;
     const uint32_t *T;    // K x n16, SSD(key_k, r) ascending; each key's list is
                           // padded to whole 16-entry (64-byte) lines with
                           // 0xFFFFFFFF, above every ring bound
@@ -104,14 +123,13 @@ struct Work {
                          // reference range, likewise
     uint32_t *ring_list; // Q
     uint32_t *dense_list;// Q
-    uint32_t *fb_list;   // Q, queries the row-layout resolve step leaves open
-    uint32_t *counters;  // [0] ring count, [1] dense count, [2] fallback count
+    uint32_t *counters;  // [0] ring count, [1] dense count
     int64_t capacity;    // Q capacity
 };
 
 // device stats block (uint64 counters, same order as riann_stats_t after `frames`)
 enum StatSlot {
-    ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING, ST_FALLBACK,
+    ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING,
     ST_COUNT
 };
 
@@ -126,14 +144,12 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // device-side count.  Reads the query patches written by launch_extract.
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                         hipStream_t st);
-// Row-layout dense search (D <= 96): the row kernel (which checks its own
-// candidates unless the reference range is split, when a resolve kernel
-// merges the parts) and the exhaustive search of the rare queries neither
-// can resolve (w.fb_list, count w.counters[2], which must start at 0; counted
-// in ST_FALLBACK).
+// Row-layout dense search (ix.n_rows > 0): the row kernel, which checks its
+// own candidates unless the reference range is split over several blocks,
+// when a resolve kernel merges the parts first.
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                             unsigned long long *stats, hipStream_t st);
+                             hipStream_t st);
 // T planar frames (each H x W x C, common row pitch) -> one H x W x (T*C)
 // frame whose channel t*C + c is channel c of frame t (k_extract.hip).
 constexpr int kMaxStack = 16;

@@ -187,10 +187,6 @@ def test_ties_and_constant_frame(torch_dev, riann, flags):
         torch.cuda.synchronize()
         bi, bd = check_exact(out, ssd, P, ref, "full ties")
         assert bi[0] == 7 and bd[0] == 0
-        # equal minima in three tiles (7, 100, 250) leave the row layout's
-        # tile-resolve step undecided: those queries take its fallback
-        fbk = idx.stats()["dense_fallback"]
-        assert (fbk == 0) if flags else (fbk > 0)
         hq, wq = oracle.field_shape(20, 24, 8, 1)
         assert bi[10 * wq + 14] == 3 and bd[10 * wq + 14] == 0   # lowest of 3, 150, 200
         prev = np.full((hq, wq), 250, np.int32)
@@ -525,4 +521,113 @@ def test_spatiotemporal_patches(torch_dev, riann):
         P = oracle.extract3d([wl.frame(k) for k in range(t - T + 1, t + 1)], p, 1)
         check_exact(out, ssd, P, ref, f"3D t={t}")
         prev = out.clone()
+    idx.close()
+
+
+def _near(p, d):
+    """A patch at SSD d (<= 3 changed bytes) from p."""
+    r = p.astype(np.int64).copy()
+    r[:d] += 1
+    return r.astype(np.uint8)
+
+
+def _with_sum_parity(q, par):
+    q = q.copy()
+    if int(q.astype(np.int64).sum()) % 2 != par:
+        q[-1] += 1
+    return q
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_class_order_ties(torch_dev, riann, flags):
+    """The row layout orders references by the parity of Rc (even first).
+    For one query a reference's class is fixed by its SSD's parity, and SSDs
+    s and s + 1 share the half-distance Y when s - Qc is even: here the
+    smaller SSD always belongs to the later index, in the other class, and
+    equal SSDs (one class) must still resolve to the lower index."""
+    torch, dev = torch_dev
+    print_case("class-order ties")
+    rng = np.random.default_rng(41)
+    n = 700
+    ref = rng.integers(0, 256, (n, 64), dtype=np.uint8)
+    q = rng.integers(20, 236, (4, 64), dtype=np.uint8)
+    q[0] = _with_sum_parity(q[0], 0)     # X(2) even: SSD 2 and 3 share Y
+    q[1] = _with_sum_parity(q[1], 1)     # X(1) even: SSD 1 and 2 share Y
+    q[2] = _with_sum_parity(q[2], 0)     # X(0) even: SSD 0 and 1 share Y
+    q[3] = _with_sum_parity(q[3], 1)     # X(0) odd: SSD 0 alone
+    plan = [(0, 30, 3), (0, 600, 2), (1, 50, 2), (1, 650, 1),
+            (2, 10, 1), (2, 60, 0), (2, 200, 0), (3, 90, 0), (3, 95, 1), (3, 400, 0)]
+    for qi, r, d in plan:
+        ref[r] = _near(q[qi], d)
+    f = np.zeros((8, 4 * 8, 1), np.uint8)
+    for qi in range(4):
+        f[:, 8 * qi:8 * qi + 8, 0] = q[qi].reshape(8, 8)
+    P = oracle.extract(f, 8, 1)
+    idx = riann.Index.build(ref, [0, 1, 2], patch=8, channels=1, stride=1, flags=flags,
+                            dense_threshold=-1)
+    fd = to_dev(torch, dev, f)
+    out, ssd = idx.full_search(fd)
+    torch.cuda.synchronize()
+    bi, bd = check_exact(out, ssd, P, ref, "class ties")
+    assert list(bi[[0, 8, 16, 24]]) == [600, 650, 60, 90]
+    assert list(bd[[0, 8, 16, 24]]) == [2, 1, 0, 0]
+    hq, wq = oracle.field_shape(8, 32, 8, 1)
+    prev = rng.integers(0, n, (hq, wq)).astype(np.int32)
+    out2, ssd2 = idx.match_frame(fd, prev=to_dev(torch, dev, prev))
+    torch.cuda.synchronize()
+    check_exact(out2, ssd2, P, ref, "class ties, ring frame")
+    idx.close()
+
+
+def test_row_layout_split_reference_range(torch_dev, riann):
+    """n = 40,000 at D = 64: more tiles than one part's 10-bit tile field
+    keys, so every launch splits the reference range (two parts at least)
+    and the resolve kernel merges them; a duplicate in the second part must
+    lose to its lower-index twin."""
+    torch, dev = torch_dev
+    print_case("row layout split n=40000")
+    rng = np.random.default_rng(43)
+    n = 40000
+    ref = rng.integers(0, 256, (n, 64), dtype=np.uint8)
+    base = rng.integers(0, 256, (32, 48, 1), dtype=np.uint8)
+    R0 = oracle.extract(base, 8, 1)
+    ref[5] = R0[100]
+    ref[39000] = R0[100]
+    ref[20001] = R0[700]
+    ref[39999] = R0[707]
+    f = np.clip(base.astype(np.int32) + rng.integers(-1, 2, base.shape), 0, 255).astype(np.uint8)
+    f[:8, :8] = base[:8, :8]
+    P = oracle.extract(f, 8, 1)
+    idx = riann.Index.build(ref, [0, 7, 9000, 30000], patch=8, channels=1, stride=1,
+                            dense_threshold=-1)
+    fd = to_dev(torch, dev, f)
+    out, ssd = idx.full_search(fd)
+    torch.cuda.synchronize()
+    bi, bd = check_exact(out, ssd, P, ref, "split full")
+    hq, wq = oracle.field_shape(32, 48, 8, 1)
+    prev = rng.integers(-1, n, (hq, wq)).astype(np.int32)
+    out2, ssd2 = idx.match_frame(fd, prev=to_dev(torch, dev, prev))
+    torch.cuda.synchronize()
+    check_exact(out2, ssd2, P, ref, "split ring")
+    idx.close()
+
+
+def test_reference_set_beyond_row_keys(torch_dev, riann):
+    """n = 140,000 at D = 32 exceeds what four 10-bit-keyed parts cover: the
+    dense search takes the column layout, still exact."""
+    torch, dev = torch_dev
+    print_case("n=140000 D=32 column layout")
+    rng = np.random.default_rng(47)
+    n = 140000
+    ref = rng.integers(0, 256, (n, 32), dtype=np.uint8)
+    base = rng.integers(0, 256, (20, 24, 2), dtype=np.uint8)
+    R0 = oracle.extract(base, 4, 1)
+    ref[139999] = R0[40]
+    ref[77] = R0[41]
+    P = oracle.extract(base, 4, 1)
+    idx = riann.Index.build(ref, [0, 1], patch=4, channels=2, stride=1, dense_threshold=-1)
+    out, ssd = idx.full_search(to_dev(torch, dev, base))
+    torch.cuda.synchronize()
+    bi, bd = check_exact(out, ssd, P, ref, "n=140000")
+    assert bi[40] == 139999 and bd[40] == 0
     idx.close()
