@@ -163,6 +163,22 @@ def extras(args, result, idx, wl, frames, field, H, Wd, hq, wq, Q, K, W, dev, st
                              "GBps": rbytes / (ms_r * 1e-3) / 1e9,
                              "note": "field 4 B/query + frame 1 B and output 4 B per value + "
                                      "appearance set once; gathers served by L2"}
+    # the same frames by the exhaustive search alone (no ring phase): exact
+    # as well, so this is what the ring intersection buys on this workload
+    nf = min(10, K)
+    fo = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    fs = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    idx.full_search(frames[W + 1], out=fo, ssd=fs)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(nf):
+        idx.full_search(frames[W + 1 + i], out=fo, ssd=fs)
+    e1.record(stream)
+    e1.synchronize()
+    result["full_search_every_frame"] = {
+        "ms_per_frame": e0.elapsed_time(e1) / nf, "frames": nf,
+        "note": "riann_full_search on the timed frames: the same exact field without the "
+                "ring phase (HIP events on the launch stream)"}
     # exact k-NN fields (k = 4) on the same frames, where the key range allows
     try:
         kk = 4
