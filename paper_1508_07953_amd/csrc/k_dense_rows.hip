@@ -37,35 +37,51 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
 #ifndef RIANN_ROWS_WAVES
-#define RIANN_ROWS_WAVES 4
+#define RIANN_ROWS_WAVES 0                     // 0: four
 #endif
 #ifndef RIANN_ROWS_QB
-#define RIANN_ROWS_QB 4
+#define RIANN_ROWS_QB 0                        // 0: four
 #endif
-constexpr int kWaves = RIANN_ROWS_WAVES;
-constexpr int kBlock = 64 * kWaves;
-constexpr int kQB = RIANN_ROWS_QB;     // 32-query column blocks per wavefront
-static_assert(kQB >= 2, "the LDS prefetch runs one query block ahead");
-constexpr int kWaveQ = 32 * kQB;
-constexpr int kBlockQ = kWaveQ * kWaves;
+
+// Block shape: wavefronts per block and 32-query column blocks per
+// wavefront.  Measured on the 720p workload (D = 64, dense step): four column
+// blocks and four wavefronts 0.73-0.75 ms; three or five column blocks
+// 0.78-0.80 ms; six 0.73-0.76 ms; two 0.84 ms; eight wavefronts per block
+// 0.75-0.83 ms.  Every variant passed the row-layout parity tests first.
+template <int DP>
+struct RowCfg {
+    static constexpr int waves = RIANN_ROWS_WAVES > 0 ? RIANN_ROWS_WAVES : 4;
+    static constexpr int qb = RIANN_ROWS_QB > 0 ? RIANN_ROWS_QB : 4;
+    static constexpr int block = 64 * waves;
+    static constexpr int wave_q = 32 * qb;
+    static constexpr int block_q = wave_q * waves;
+    static_assert(qb >= 2, "the LDS prefetch runs one query block ahead");
+};
 #ifndef RIANN_ROWS_SPLIT
 #define RIANN_ROWS_SPLIT 0                     // 0: chosen per launch
 #endif
+#ifndef RIANN_ROWS_INFLIGHT
+#define RIANN_ROWS_INFLIGHT 0                  // 0: two
+#endif
+#ifndef RIANN_ROWS_LOOKAHEAD
+#define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
+#endif                                         // (2: within 1 %, 25 more registers)
+constexpr int kLookahead = RIANN_ROWS_LOOKAHEAD;
 
-template <int KB, int ST>
+template <int KB, int ST, int WAVES>
 __device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
                                           const int32_t *__restrict__ gh, int sg, int8_t *lf,
                                           int32_t *lh, int wv, int lane) {
     constexpr int CH = ST * KB;
     const int8_t *src = gf + (int64_t)sg * CH * 1024;
 #pragma unroll
-    for (int i = 0; i < (CH + kWaves - 1) / kWaves; ++i) {
-        const int c = wv + kWaves * i;
+    for (int i = 0; i < (CH + WAVES - 1) / WAVES; ++i) {
+        const int c = wv + WAVES * i;
         if (c < CH)
             __builtin_amdgcn_global_load_lds((glb_void *)(src + c * 1024 + lane * 16),
                                              (lds_void *)(lf + c * 1024), 16, 0, 0);
     }
-    if (wv == kWaves - 1 && lane < ST * 8)
+    if (wv == WAVES - 1 && lane < ST * 8)
         __builtin_amdgcn_global_load_lds((glb_void *)(gh + (int64_t)sg * ST * kTile + lane * 4),
                                          (lds_void *)lh, 16, 0, 0);
 }
@@ -81,11 +97,11 @@ __device__ __forceinline__ uint32_t min16(const v16i &a) {
     return min(m0, m3);
 }
 
-template <int DP, int ST>
+template <int DP, int ST, int QB>
 struct RowState {
     static constexpr int KB = DP / 32;
-    v4i Bq[kQB][KB];        // query fragments (MFMA B operand)
-    uint32_t key[kQB];      // min over tiles of (Y << kRowTileBits) | tile
+    v4i Bq[QB][KB];         // query fragments (MFMA B operand)
+    uint32_t key[QB];       // min over tiles of (Y << kRowTileBits) | tile
 
     // A fragments and accumulator initial values (Hf) of tile u of a stage
     __device__ __forceinline__ void load_tile(const int8_t *lf, const int32_t *lh, int u,
@@ -110,29 +126,32 @@ struct RowState {
         key[qb] = min(key[qb], (min16(acc) << kRowTileBits) | t);
     }
 
-    // all tiles of one LDS stage; the MFMA chain of the next query block (or
-    // of the next tile's first block) is issued before the current block's
-    // minimum tree, so the matrix core and the VALU overlap.  The next tile's
-    // LDS operands are read one query block ahead.
+    // all tiles of one LDS stage, as a sequence of (tile, query block) items:
+    // the MFMA chain of item i + LA is issued before the minimum tree of
+    // item i, so the tree reads an accumulator whose chain has finished while
+    // the later chains run (LA + 1 accumulators, used in turn).  The next
+    // tile's LDS operands are read one item before its first chain.
     __device__ __forceinline__ void stage(const int8_t *lf, const int32_t *lh, uint32_t t0s,
                                           int lane, int grp) {
+        constexpr int LA = kLookahead;
+        static_assert(QB >= LA + 1, "the next tile's operands load inside the current tile");
         v4i Af[2][KB];
         v16i H[2];
-        v16i acc[2];
+        v16i acc[LA + 1];
         load_tile(lf, lh, 0, lane, grp, Af[0], H[0]);
-        mma(0, Af[0], H[0], acc[0]);
+#pragma unroll
+        for (int j = 0; j < LA; ++j) mma(j, Af[0], H[0], acc[j]);
 #pragma unroll
         for (int u = 0; u < ST; ++u) {
             const int cur = u & 1;
 #pragma unroll
-            for (int qb = 0; qb < kQB; ++qb) {
-                if (qb == kQB - 2 && u + 1 < ST)
+            for (int qb = 0; qb < QB; ++qb) {
+                const int it = u * QB + qb, nx = it + LA;
+                if (qb == QB - 1 - LA && u + 1 < ST)
                     load_tile(lf, lh, u + 1, lane, grp, Af[cur ^ 1], H[cur ^ 1]);
-                if (qb + 1 < kQB)
-                    mma(qb + 1, Af[cur], H[cur], acc[(qb + 1) & 1]);
-                else if (u + 1 < ST)
-                    mma(0, Af[cur ^ 1], H[cur ^ 1], acc[0]);
-                track(qb, acc[qb & 1], t0s + (uint32_t)u);
+                if (nx < ST * QB)
+                    mma(nx % QB, Af[(nx / QB) & 1], H[(nx / QB) & 1], acc[nx % (LA + 1)]);
+                track(qb, acc[it % (LA + 1)], t0s + (uint32_t)u);
                 // one MFMA, then half of the tree, then the chain's other
                 // MFMAs and the rest: the wave keeps issuing VALU work while
                 // each MFMA of the chain executes
@@ -241,9 +260,11 @@ struct RowCheck {
 };
 
 template <int DP, int ST>
-__global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
+__global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
                                                        int nsplit) {
     constexpr int KB = DP / 32;
+    constexpr int kWaves = RowCfg<DP>::waves, kQB = RowCfg<DP>::qb;
+    constexpr int kWaveQ = RowCfg<DP>::wave_q, kBlockQ = RowCfg<DP>::block_q;
     constexpr int STAGE = ST * KB * 1024;
     // the two reference stages; after the last tile, the query patches
     constexpr int PATCHES = kBlockQ * DP;
@@ -270,9 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
     const int s_begin = (int)((int64_t)split * ns_all / nsplit);
     const int s_end = (int)((int64_t)(split + 1) * ns_all / nsplit);
 
-    if (s_begin < s_end) stage_dma<KB, ST>(ix.Rfr, ix.Hf, s_begin, s_f0, s_h0, wv, lane);
+    if (s_begin < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, s_begin, s_f0, s_h0, wv, lane);
 
-    RowState<DP, ST> S;
+    RowState<DP, ST, kQB> S;
     uint32_t qid[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
@@ -287,11 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
     __syncthreads();
 
     for (int sg = s_begin; sg < s_end; sg += 2) {
-        if (sg + 1 < s_end) stage_dma<KB, ST>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
+        if (sg + 1 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
         S.stage(s_f0, s_h0, (uint32_t)((sg - s_begin) * ST), lane, grp);
         __syncthreads();
         if (sg + 1 < s_end) {
-            if (sg + 2 < s_end) stage_dma<KB, ST>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
+            if (sg + 2 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
             S.stage(s_f1, s_h1, (uint32_t)((sg + 1 - s_begin) * ST), lane, grp);
             __syncthreads();
         }
@@ -339,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(DevIndex ix, FrameBatch f
         for (int kb = 0; kb < KB; ++kb)
             *reinterpret_cast<v4i *>(sp + (qb * 32 + col) * DP + kb * 32 + grp * 16) = S.Bq[qb][kb];
     __syncthreads();
-    constexpr int kInFlight = DP <= 64 ? 4 : 2;
+    constexpr int kInFlight = RIANN_ROWS_INFLIGHT > 0 ? RIANN_ROWS_INFLIGHT : 2;
     const int sub = lane >> 4, r = lane & 15;
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
@@ -416,12 +437,13 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&k_dense_rows<DP, ST>), kBlock, 0);
+            &per, reinterpret_cast<const void *>(&k_dense_rows<DP, ST>), RowCfg<DP>::block, 0);
         resident = std::max(1, cus) * std::max(1, per);
     }
     const int64_t stages = ix.n_rows / (kTile * ST);
     const int64_t min_parts = (stages + ((1 << kRowTileBits) / ST) - 1) / ((1 << kRowTileBits) / ST);
     if (min_parts > kRowMaxParts) return hipErrorInvalidValue;
+    constexpr int kBlockQ = RowCfg<DP>::block_q;
     const int64_t chunks = std::max<int64_t>(1, (fb.Q + kBlockQ - 1) / kBlockQ);
     int nsplit = (int)std::min<int64_t>(kRowMaxParts, (resident + chunks - 1) / chunks);
 #if RIANN_ROWS_SPLIT > 0
@@ -429,7 +451,8 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
 #endif
     nsplit = std::max<int>(nsplit, (int)min_parts);
     const int64_t blocks = nsplit * chunks;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks), dim3(kBlock),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks),
+                       dim3(RowCfg<DP>::block),
                        0, st, ix, fb, w, nsplit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit == 1) return e;
