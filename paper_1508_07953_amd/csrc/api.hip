@@ -83,8 +83,10 @@ riann_status_t check_params(const riann_params_t *p) {
     const int64_t D = (int64_t)p->patch * p->patch * p->channels;
     if (D > 256) return fail(RIANN_E_UNSUPPORTED, "patch dimension p*p*C must be <= 256");
     // the extraction kernel stages a (kExtTY - 1)s + p by (kExtTX - 1)s + p pixel window
+    // (rows padded to whole words, plus one spare word) in 64 KB of LDS
     if ((int64_t)((kExtTY - 1) * (int64_t)p->stride + p->patch) *
-            ((kExtTX - 1) * (int64_t)p->stride + p->patch) * p->channels > 65536)
+                ((((kExtTX - 1) * (int64_t)p->stride + p->patch) * p->channels + 3) & ~3) +
+            4 > 65536)
         return fail(RIANN_E_UNSUPPORTED, "stride too large for the extraction tile");
     if (p->n_ref < 1 || p->n_ref > (int64_t)0x7FFFFF00)
         return fail(RIANN_E_INVALID, "n_ref must be in [1, 2^31 - 256]");

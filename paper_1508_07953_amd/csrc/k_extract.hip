@@ -8,7 +8,10 @@
 // then each thread assembles one query's patch in (dy, dx, c) order, encodes
 // every byte as a = q ^ 0x7F (127 - q as int8), pads it with zeros to Dp
 // bytes and writes it as Dp/16 aligned 16-byte stores, plus
-// Qc = sum over the D real bytes of (a + 1)^2.
+// Qc = sum over the D real bytes of (a + 1)^2.  When a window row holds a
+// whole number of 32-bit words (p*C % 4 == 0: 8x8 gray, 8x8x3, 12x12, ...)
+// a template instance reads each row as aligned LDS words and funnel-shifts
+// them into place (v_alignbyte); other shapes assemble byte by byte.
 #include "riann_internal.h"
 
 namespace riann {
@@ -17,31 +20,69 @@ namespace {
 
 constexpr int kTX = kExtTX, kTY = kExtTY;     // query columns x rows per block
 
+// LDS row pitch of a tile's frame region: its widest row, rounded up to
+// whole words; ext_lds_bytes adds one spare word (see k_extract_rows).
+__host__ __device__ __forceinline__ int ext_ldw(int p, int C, int s) {
+    return ((((kTX - 1) * s + p) * C) + 3) & ~3;
+}
+__host__ __device__ __forceinline__ size_t ext_lds_bytes(int p, int C, int s) {
+    return (size_t)((kTY - 1) * s + p) * ext_ldw(p, C, s) + 4;
+}
+
+// The block's tile: its frame, first query position and extent, and the
+// frame region its windows cover, copied into LDS (row pitch ldw).
+struct ExtTile {
+    int f, qx0, qy0, nqx, nqy, ldw;
+    const FrameDesc *fa;
+};
+
+__device__ __forceinline__ ExtTile load_tile(const DevIndex &ix, const FrameBatch &fb,
+                                             uint8_t *s_tile) {
+    const int p = ix.p, C = ix.C, s = ix.s;
+    ExtTile t;
+    // frame of this tile (tile ranges are consecutive per frame)
+    t.f = 0;
+    while (t.f + 1 < fb.n && (int)blockIdx.x >= fb.f[t.f + 1].tbase) ++t.f;
+    t.fa = &fb.f[t.f];
+    const FrameDesc &fa = *t.fa;
+    const int lt = (int)blockIdx.x - fa.tbase;
+    const int tiles_x = (fa.Wq + kTX - 1) / kTX;
+    t.qx0 = (lt % tiles_x) * kTX;
+    t.qy0 = (lt / tiles_x) * kTY;
+    t.nqx = min(kTX, fa.Wq - t.qx0);
+    t.nqy = min(kTY, fa.Hq - t.qy0);
+    const int rw = ((t.nqx - 1) * s + p) * C;   // bytes per region row
+    const int rh = (t.nqy - 1) * s + p;
+    t.ldw = ext_ldw(p, C, s);                   // LDS row pitch (fixed, whole words)
+    const uint8_t *src = fa.frame + (int64_t)(t.qy0 * s) * fa.pitch + (int64_t)(t.qx0 * s) * C;
+    // whole words where the frame rows allow it (the region's first byte and
+    // the pitch word-aligned), then each row's last rw % 4 bytes; nothing is
+    // read beyond a region row
+    const bool wa = ((fa.pitch | reinterpret_cast<uintptr_t>(src)) & 3) == 0;
+    const int nw = wa ? rw >> 2 : 0, tail = rw - 4 * nw;
+    for (int e = threadIdx.x; e < nw * rh; e += kTX * kTY) {
+        const int r = e / nw, c = e - r * nw;
+        reinterpret_cast<uint32_t *>(s_tile + r * t.ldw)[c] =
+            reinterpret_cast<const uint32_t *>(src + (int64_t)r * fa.pitch)[c];
+    }
+    for (int e = threadIdx.x; e < tail * rh; e += kTX * kTY) {
+        const int r = e / tail, c = 4 * nw + (e - r * tail);
+        s_tile[r * t.ldw + c] = src[(int64_t)r * fa.pitch + c];
+    }
+    __syncthreads();
+    return t;
+}
+
 template <int DP>
 __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb, Work w) {
     extern __shared__ uint8_t s_tile[];
     const int p = ix.p, C = ix.C, s = ix.s, D = ix.D;
-    // frame of this tile (tile ranges are consecutive per frame)
-    int f = 0;
-    while (f + 1 < fb.n && (int)blockIdx.x >= fb.f[f + 1].tbase) ++f;
-    const FrameDesc &fa = fb.f[f];
-    const int lt = (int)blockIdx.x - fa.tbase;
-    const int tiles_x = (fa.Wq + kTX - 1) / kTX;
-    const int qx0 = (lt % tiles_x) * kTX, qy0 = (lt / tiles_x) * kTY;
-    const int nqx = min(kTX, fa.Wq - qx0), nqy = min(kTY, fa.Hq - qy0);
-    // frame region covered by this block's windows
-    const int rw = ((nqx - 1) * s + p) * C;     // bytes per region row
-    const int rh = (nqy - 1) * s + p;
-    const int ldw = ((kTX - 1) * s + p) * C;    // LDS row pitch (fixed)
-    const uint8_t *src = fa.frame + (int64_t)(qy0 * s) * fa.pitch + (int64_t)(qx0 * s) * C;
-    for (int e = threadIdx.x; e < rw * rh; e += kTX * kTY) {
-        const int r = e / rw, cidx = e - r * rw;
-        s_tile[r * ldw + cidx] = src[(int64_t)r * fa.pitch + cidx];
-    }
-    __syncthreads();
+    const ExtTile t = load_tile(ix, fb, s_tile);
+    const FrameDesc &fa = *t.fa;
+    const int f = t.f, qx0 = t.qx0, qy0 = t.qy0, ldw = t.ldw;
 
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    if (tx >= nqx || ty >= nqy) return;
+    if (tx >= t.nqx || ty >= t.nqy) return;
     const uint8_t *win = s_tile + (ty * s) * ldw + (tx * s) * C;
     const int rowlen = p * C;
     uint32_t wd[DP / 4];
@@ -75,12 +116,78 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb
     w.fid[q] = (uint8_t)f;
 }
 
+// Window rows of P*C bytes, a whole number of words: row dy of the window
+// starts at LDS byte b (its own alignment per row); the aligned words b/4 ..
+// b/4 + PC/4 hold it, and v_alignbyte by b % 4 takes each output word from
+// two of them.  The LDS allocation has a spare word for the last row's extra
+// word, whose bytes beyond the row are shifted out.
+template <int DP, int P, int C>
+__global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBatch fb, Work w) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t s_tile[];
+    constexpr int PC = P * C, NW = PC / 4, D = P * PC;
+    static_assert(PC % 4 == 0 && D <= DP, "whole-word window rows");
+    const int s = ix.s;
+    const ExtTile t = load_tile(ix, fb, s_tile);
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    if (tx >= t.nqx || ty >= t.nqy) return;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(s_tile);
+    const int base = (ty * s) * t.ldw + (tx * s) * C;
+    uint32_t wd[DP / 4];
+    int sa2 = 0, sa = 0;
+#pragma unroll
+    for (int dy = 0; dy < P; ++dy) {
+        // each row has its own alignment (the LDS row pitch is any byte count)
+        const int b = base + dy * t.ldw, a0 = b >> 2;
+        const uint32_t sh = (uint32_t)(b & 3);
+        uint32_t x[NW + 1];
+#pragma unroll
+        for (int j = 0; j <= NW; ++j) x[j] = words[a0 + j];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const uint32_t word = __builtin_amdgcn_alignbyte(x[j + 1], x[j], sh) ^ 0x7F7F7F7Fu;
+            wd[dy * NW + j] = word;
+            sa2 = __builtin_amdgcn_sdot4((int)word, (int)word, sa2, false);
+            sa = __builtin_amdgcn_sdot4((int)word, 0x01010101, sa, false);
+        }
+    }
+#pragma unroll
+    for (int i = D / 4; i < DP / 4; ++i) wd[i] = 0u;
+    const FrameDesc &fa = *t.fa;
+    const int64_t q = fa.qbase + (int64_t)(t.qy0 + ty) * fa.Wq + (t.qx0 + tx);
+    uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
+#pragma unroll
+    for (int i = 0; i < DP / 16; ++i)
+        dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
+    w.qc[q] = sa2 + 2 * sa + D;
+    w.fid[q] = (uint8_t)t.f;
+}
+
 template <int DP>
 hipError_t launch_extract_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                             hipStream_t st) {
-    const size_t lds = (size_t)((kTY - 1) * ix.s + ix.p) * ((kTX - 1) * ix.s + ix.p) * ix.C;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), dim3((unsigned)fb.ntiles),
-                       dim3(kTX * kTY), lds, st, ix, fb, w);
+    const size_t lds = ext_lds_bytes(ix.p, ix.C, ix.s);
+    const dim3 grid((unsigned)fb.ntiles), block(kTX * kTY);
+    // whole-word window rows of the common shapes
+    bool fast = false;
+    if constexpr (DP == 64) {
+        if ((fast = ix.p == 8 && ix.C == 1))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 8, 1>), grid, block, lds,
+                               st, ix, fb, w);
+    } else if constexpr (DP == 192) {
+        if ((fast = ix.p == 8 && ix.C == 3))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 8, 3>), grid, block, lds,
+                               st, ix, fb, w);
+    } else if constexpr (DP == 160) {
+        if ((fast = ix.p == 12 && ix.C == 1))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 12, 1>), grid, block, lds,
+                               st, ix, fb, w);
+    } else if constexpr (DP == 256) {
+        if ((fast = ix.p == 16 && ix.C == 1))
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 16, 1>), grid, block, lds,
+                               st, ix, fb, w);
+    }
+    if (!fast)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), grid, block, lds, st, ix, fb, w);
     return hipGetLastError();
 }
 
