@@ -290,8 +290,8 @@ def main():
     ap.add_argument("--workload", default="hd720", choices=["hd720", "fhd_rgb", "uhd_mix"],
                     help="per-frame workload of the timed loop (hd720 is the headline)")
     ap.add_argument("--dense-layout", default="auto", choices=["auto", "column"],
-                    help="auto: references as MFMA rows where the patch allows it (the "
-                         "library default); column: always queries as MFMA rows")
+                    help="auto: references as MFMA rows (the library default); column: "
+                         "queries as MFMA rows (RIANN_FLAG_COLUMN_DENSE)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default routing threshold")
     ap.add_argument("--no-extras", action="store_true",
@@ -417,7 +417,7 @@ def main():
         ms_per_launch = (prof["dense"]["ms"] + prof["full"]["ms"]) / max(1, launches)
         ops = 2.0 * dense_q_per_launch * n * D
         achieved = ops / (ms_per_launch * 1e-3) / 1e12
-        rows = args.dense_layout == "auto" and wl.D <= 96
+        rows = args.dense_layout == "auto"
         kname = ("k_dense_rows (int8 MFMA, references as rows, own candidate check)" if rows else
                  "k_dense (int8 MFMA, queries as rows)")
         result["roofline"] = {"bound": "mfma", "kernel": kname,

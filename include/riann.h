@@ -85,9 +85,9 @@ typedef struct riann_params {
 } riann_params_t;
 
 /* riann_params_t.flags: answer dense queries with the column-layout search
- * (queries as MFMA rows) also where the row layout (references as MFMA rows,
- * patches of at most 96 padded bytes) is the default.  Results are identical;
- * this exists for measurement and as a cross-check of the two kernels. */
+ * (queries as MFMA rows) instead of the default row layout (references as
+ * MFMA rows).  Results are identical; this exists for measurement and as a
+ * cross-check of the two kernels. */
 #define RIANN_FLAG_COLUMN_DENSE 1u
 
 /* One frame of a batch (riann_match_batch). */

@@ -106,26 +106,23 @@ int64_t default_threshold(int64_t n) {
 }
 
 // Rows of the row-layout dense search's reference order (even Rc, then odd
-// Rc, each class padded to whole tiles, the whole to kRefAlign), or 0 where
-// that layout is not used: Dp > 96, or more tiles than its parts can key.
-// With Rc == nullptr: the most rows any reference set of this size can take.
-int64_t row_layout_rows(int64_t n, int Dp, const std::vector<int32_t> *Rc) {
-    if (Dp > 96) return 0;
+// Rc, each class padded to whole tiles, the whole to kRefAlign).  With
+// Rc == nullptr: the most rows any reference set of this size can take.
+int64_t row_layout_rows(int64_t n, const std::vector<int32_t> *Rc) {
     int64_t n0 = n;
     if (Rc) {
         n0 = 0;
         for (int64_t r = 0; r < n; ++r) n0 += ((*Rc)[(size_t)r] & 1) == 0;
     }
-    const int64_t rows = Rc ? round_up(round_up(n0, kTile) + round_up(n - n0, kTile), kRefAlign)
-                            : round_up(round_up(n, kTile) + kTile, kRefAlign);
-    return rows / kTile > ((int64_t)kRowMaxParts << kRowTileBits) ? 0 : rows;
+    return Rc ? round_up(round_up(n0, kTile) + round_up(n - n0, kTile), kRefAlign)
+              : round_up(round_up(n, kTile) + kTile, kRefAlign);
 }
 
 int64_t index_bytes(int64_t n, int D, int K) {
     const int Dp = (int)round_up(D, 32);
     const int64_t n_pad = round_up(n, kRefAlign);
     const int64_t n16 = round_up(n, 16), Kp = round_up(std::max(K, 1), 4);
-    const int64_t n_rows = row_layout_rows(n, Dp, nullptr);
+    const int64_t n_rows = row_layout_rows(n, nullptr);
     return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
            n_rows * (Dp + 12) + (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
 }
@@ -210,11 +207,11 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                             &Rv[(size_t)(r * Dp + kb * 32 + 16 * g)], 16);
             }
     // row-layout tables over the class order (even Rc, then odd Rc)
-    const int64_t n_rows = row_layout_rows(n, Dp, &Rc);
+    const int64_t n_rows = row_layout_rows(n, &Rc);
     std::vector<int8_t> Rfr((size_t)n_rows * Dp, 0);
-    std::vector<int32_t> Hf((size_t)n_rows, kRowPadY);
+    std::vector<int32_t> Hf((size_t)n_rows, row_pad_y(Dp));
     std::vector<int32_t> Rci((size_t)n_rows * 2, 0);
-    if (n_rows > 0) {
+    {
         std::vector<int64_t> order((size_t)n_rows, -1);
         int64_t pos = 0;
         for (int cls = 0; cls < 2; ++cls) {

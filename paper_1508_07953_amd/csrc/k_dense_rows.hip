@@ -1,6 +1,6 @@
 // k_dense_rows.hip -- exact exhaustive search with references as the MFMA
-// rows and queries as the columns (v_mfma_i32_32x32x32_i8), for narrow
-// patches (Dp <= 96) where the column layout is bound by its epilogue.
+// rows and queries as the columns (v_mfma_i32_32x32x32_i8), the default dense
+// search at every patch width.
 //
 // With a = 127 - q, v = r - 128 and p = Rc & 1, the per-reference value
 // Hf = (Rc + bias - p) / 2 enters as the MFMA's C operand, read straight from
@@ -10,19 +10,19 @@
 // class padded to whole tiles -- so p is constant over a tile.  Per (query,
 // tile) a lane holds 16 rows of one query column: a v_min3 tree gives the
 // tile minimum of Y (about 0.5 VALU op per pair) and one v_lshl_or plus one
-// v_min keep the key (Y << 10) | tile, whose minimum over the lane's tiles is
-// the smallest Y and the first tile reaching it.  Over both lane groups the
-// lexicographic (Y, tile) minimum is in the tile holding the (SSD, index)
-// minimum: a row with smaller SSD would have a smaller Y, or the same Y and
-// p = 0 (an even-class tile, hence an earlier one); a row with the same SSD
-// and a lower index sits in the same class, in the same or an earlier tile.
-// The wavefront then recomputes the exact SSDs of that tile's rows in the
-// lane group(s) that reached the minimum and takes their (SSD, index)
-// minimum; these gathers overlap the matrix work of the other wavefronts on
-// the SIMD.  For small frames the reference range is split over up to four
-// blocks per query chunk (and over as many as the 10-bit tile field needs);
-// the parts then leave records that a resolve kernel merges before the same
-// check.
+// v_min keep the key (Y << b) | tile over a segment of 2^b tiles (b = 11 to 8
+// as the widest Y grows with the patch); at each segment's end the key folds
+// into the query's (Y, tile) minimum, an earlier segment keeping a tie.  Over
+// both lane groups the lexicographic (Y, tile) minimum is in the tile holding
+// the (SSD, index) minimum: a row with smaller SSD would have a smaller Y, or
+// the same Y and p = 0 (an even-class tile, hence an earlier one); a row with
+// the same SSD and a lower index sits in the same class, in the same or an
+// earlier tile.  The wavefront then recomputes the exact SSDs of that tile's
+// rows in the lane group(s) that reached the minimum and takes their (SSD,
+// index) minimum; these gathers overlap the matrix work of the other
+// wavefronts on the SIMD.  For small frames the reference range is split over
+// up to four blocks per query chunk; the parts then leave records that a
+// resolve kernel merges before the same check.
 #include "riann_internal.h"
 
 #include <algorithm>
@@ -42,6 +42,9 @@ typedef __attribute__((address_space(1))) void glb_void;
 #ifndef RIANN_ROWS_QB
 #define RIANN_ROWS_QB 0                        // 0: four
 #endif
+#ifndef RIANN_ROWS_INFLIGHT
+#define RIANN_ROWS_INFLIGHT 0                  // 0: by patch width
+#endif
 
 // Block shape: wavefronts per block and 32-query column blocks per
 // wavefront.  Measured on the 720p workload (D = 64, dense step): four column
@@ -51,7 +54,10 @@ typedef __attribute__((address_space(1))) void glb_void;
 template <int DP>
 struct RowCfg {
     static constexpr int waves = RIANN_ROWS_WAVES > 0 ? RIANN_ROWS_WAVES : 4;
-    static constexpr int qb = RIANN_ROWS_QB > 0 ? RIANN_ROWS_QB : 4;
+    static constexpr int qb = RIANN_ROWS_QB > 0 ? RIANN_ROWS_QB : (DP <= 192 ? 4 : 2);
+    // check passes in flight: the wide patches' rows need the registers
+    static constexpr int inflight =
+        RIANN_ROWS_INFLIGHT > 0 ? RIANN_ROWS_INFLIGHT : (DP <= 96 ? 2 : 1);
     static constexpr int block = 64 * waves;
     static constexpr int wave_q = 32 * qb;
     static constexpr int block_q = wave_q * waves;
@@ -59,9 +65,6 @@ struct RowCfg {
 };
 #ifndef RIANN_ROWS_SPLIT
 #define RIANN_ROWS_SPLIT 0                     // 0: chosen per launch
-#endif
-#ifndef RIANN_ROWS_INFLIGHT
-#define RIANN_ROWS_INFLIGHT 0                  // 0: two
 #endif
 #ifndef RIANN_ROWS_LOOKAHEAD
 #define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
@@ -99,9 +102,23 @@ __device__ __forceinline__ uint32_t min16(const v16i &a) {
 
 template <int DP, int ST, int QB>
 struct RowState {
-    static constexpr int KB = DP / 32;
+    static constexpr int KB = DP / 32, TB = row_tile_bits(DP);
     v4i Bq[QB][KB];         // query fragments (MFMA B operand)
-    uint32_t key[QB];       // min over tiles of (Y << kRowTileBits) | tile
+    uint32_t key[QB];       // min over the current segment of (Y << TB) | tile
+    uint32_t bY[QB], bT[QB];// (Y, tile) minimum of the earlier segments
+
+    // fold the segment starting at tile t0 into (bY, bT); an earlier segment
+    // keeps a tie (its tiles come first)
+    __device__ __forceinline__ void fold(uint32_t t0) {
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            const uint32_t y = key[qb] >> TB, t = t0 + (key[qb] & ((1u << TB) - 1u));
+            const bool lt = y < bY[qb];
+            bY[qb] = lt ? y : bY[qb];
+            bT[qb] = lt ? t : bT[qb];
+            key[qb] = ~0u;
+        }
+    }
 
     // A fragments and accumulator initial values (Hf) of tile u of a stage
     __device__ __forceinline__ void load_tile(const int8_t *lf, const int32_t *lh, int u,
@@ -123,7 +140,7 @@ struct RowState {
     }
 
     __device__ __forceinline__ void track(int qb, const v16i &acc, uint32_t t) {
-        key[qb] = min(key[qb], (min16(acc) << kRowTileBits) | t);
+        key[qb] = min(key[qb], (min16(acc) << TB) | t);
     }
 
     // all tiles of one LDS stage, as a sequence of (tile, query block) items:
@@ -266,9 +283,13 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, F
     constexpr int kWaves = RowCfg<DP>::waves, kQB = RowCfg<DP>::qb;
     constexpr int kWaveQ = RowCfg<DP>::wave_q, kBlockQ = RowCfg<DP>::block_q;
     constexpr int STAGE = ST * KB * 1024;
-    // the two reference stages; after the last tile, the query patches
-    constexpr int PATCHES = kBlockQ * DP;
+    // the two reference stages; after the last tile, the query patches of
+    // narrow patches (wide ones are read from global memory by the check)
+    constexpr bool kStagePatches = DP <= 96;
+    constexpr int PATCHES = kStagePatches ? kBlockQ * DP : 0;
     constexpr int BUF = 2 * STAGE > PATCHES ? 2 * STAGE : PATCHES;
+    constexpr int SPS = (1 << row_tile_bits(DP)) / ST;  // stages per key segment
+    static_assert(SPS % 2 == 0, "stage pairs never straddle a segment");
     __shared__ __attribute__((aligned(16))) int8_t s_buf[BUF];
     int8_t *const s_f0 = s_buf;
     int8_t *const s_f1 = s_buf + STAGE;
@@ -304,34 +325,43 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, F
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) S.Bq[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
         S.key[qb] = ~0u;
+        S.bY[qb] = ~0u;
+        S.bT[qb] = 0u;
     }
     __syncthreads();
 
+    int seg0 = s_begin;                           // first stage of the key segment
     for (int sg = s_begin; sg < s_end; sg += 2) {
+        if (sg - seg0 == SPS) {
+            S.fold((uint32_t)(seg0 * ST));
+            seg0 = sg;
+        }
         if (sg + 1 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
-        S.stage(s_f0, s_h0, (uint32_t)((sg - s_begin) * ST), lane, grp);
+        S.stage(s_f0, s_h0, (uint32_t)((sg - seg0) * ST), lane, grp);
         __syncthreads();
         if (sg + 1 < s_end) {
             if (sg + 2 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
-            S.stage(s_f1, s_h1, (uint32_t)((sg + 1 - s_begin) * ST), lane, grp);
+            S.stage(s_f1, s_h1, (uint32_t)((sg + 1 - seg0) * ST), lane, grp);
             __syncthreads();
         }
     }
+    S.fold((uint32_t)(seg0 * ST));
 
     // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
-    // accumulator order): the smaller key wins; equal keys mean the same Y in
-    // the same tile, checked in both groups.  rec = {Y, tile << 2 | group
-    // mask}, the tile counted over the whole class order, the same in both
-    // groups.
+    // accumulator order): the lexicographically smaller (Y, tile) wins; equal
+    // pairs mean the same Y in the same tile, checked in both groups.
+    // rec = {Y, tile << 2 | group mask}, the tile counted over the whole class
+    // order, the same in both groups.
     uint2 rc[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t k = S.key[qb];
-        const uint32_t o = (uint32_t)__shfl_xor((int)k, 32, 64);
-        const uint32_t m = min(k, o);
-        const uint32_t gm = (k == m ? (1u << grp) : 0u) | (o == m ? (2u >> grp) : 0u);
-        const uint32_t tile = (uint32_t)(s_begin * ST) + (m & ((1u << kRowTileBits) - 1u));
-        rc[qb] = make_uint2(m >> kRowTileBits, (tile << 2) | gm);
+        const uint32_t y = S.bY[qb], t = S.bT[qb];
+        const uint32_t oy = (uint32_t)__shfl_xor((int)y, 32, 64);
+        const uint32_t ot = (uint32_t)__shfl_xor((int)t, 32, 64);
+        const bool same = y == oy && t == ot;
+        const bool mine = y < oy || (y == oy && t < ot);
+        const uint32_t gm = same ? 3u : (mine ? (1u << grp) : (2u >> grp));
+        rc[qb] = make_uint2(mine || same ? y : oy, ((mine || same ? t : ot) << 2) | gm);
     }
 
     const uint32_t wbase = qbase + (uint32_t)(wv * kWaveQ);
@@ -352,15 +382,18 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, F
     // passes issued before any waits.  The records and query ids come from
     // the owning lanes by shuffles, the query patches from the MFMA operand
     // registers through the (now free) stage buffers.
-    __syncthreads();                              // every wavefront is past its last tile
     int8_t *const sp = s_buf + wv * (kWaveQ * DP);
+    if constexpr (kStagePatches) {
+        __syncthreads();                          // every wavefront is past its last tile
 #pragma unroll
-    for (int qb = 0; qb < kQB; ++qb)
+        for (int qb = 0; qb < kQB; ++qb)
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-            *reinterpret_cast<v4i *>(sp + (qb * 32 + col) * DP + kb * 32 + grp * 16) = S.Bq[qb][kb];
-    __syncthreads();
-    constexpr int kInFlight = RIANN_ROWS_INFLIGHT > 0 ? RIANN_ROWS_INFLIGHT : 2;
+            for (int kb = 0; kb < KB; ++kb)
+                *reinterpret_cast<v4i *>(sp + (qb * 32 + col) * DP + kb * 32 + grp * 16) =
+                    S.Bq[qb][kb];
+        __syncthreads();
+    }
+    constexpr int kInFlight = RowCfg<DP>::inflight;
     const int sub = lane >> 4, r = lane & 15;
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
@@ -381,8 +414,11 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, F
 #pragma unroll
             for (int p = 0; p < kInFlight; ++p) {
                 const int c = h + 4 * p + sub;
+                const int8_t *patch = kStagePatches ? sp + (qb * 32 + c) * DP
+                                                    : reinterpret_cast<const int8_t *>(w.patches) +
+                                                          (int64_t)qq[p] * DP;
                 C[p].finish(ix, fb, w, qq[p], rr[p], ll[p], lane,
-                            reinterpret_cast<const uint4 *>(sp + (qb * 32 + c) * DP));
+                            reinterpret_cast<const uint4 *>(patch));
             }
         }
     }
@@ -425,12 +461,11 @@ template <int DP>
 hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
     constexpr int ST = DP <= 64 ? 8 : 4;
     static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
-    static_assert(((1 << kRowTileBits) % ST) == 0, "a part must hold whole stages");
     // Split the reference range over nsplit blocks per query chunk when there
     // are too few chunks to give every resident block slot one (small
     // frames); measured on a 720p frame (1,773 chunks, 768 slots) splitting
     // costs more -- the query patches are read once per part -- than its
-    // shorter last round gains.  A part holds at most 2^kRowTileBits tiles.
+    // shorter last round gains.
     static int resident = 0;
     if (resident == 0) {
         int dev = 0, cus = 0, per = 0;
@@ -440,16 +475,12 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
             &per, reinterpret_cast<const void *>(&k_dense_rows<DP, ST>), RowCfg<DP>::block, 0);
         resident = std::max(1, cus) * std::max(1, per);
     }
-    const int64_t stages = ix.n_rows / (kTile * ST);
-    const int64_t min_parts = (stages + ((1 << kRowTileBits) / ST) - 1) / ((1 << kRowTileBits) / ST);
-    if (min_parts > kRowMaxParts) return hipErrorInvalidValue;
     constexpr int kBlockQ = RowCfg<DP>::block_q;
     const int64_t chunks = std::max<int64_t>(1, (fb.Q + kBlockQ - 1) / kBlockQ);
     int nsplit = (int)std::min<int64_t>(kRowMaxParts, (resident + chunks - 1) / chunks);
 #if RIANN_ROWS_SPLIT > 0
     nsplit = RIANN_ROWS_SPLIT;
 #endif
-    nsplit = std::max<int>(nsplit, (int)min_parts);
     const int64_t blocks = nsplit * chunks;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks),
                        dim3(RowCfg<DP>::block),
@@ -464,7 +495,7 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
 
 }  // namespace
 
-bool dense_rows_supported(const DevIndex &ix) { return ix.Dp <= 96 && ix.n_rows > 0; }
+bool dense_rows_supported(const DevIndex &ix) { return ix.n_rows > 0; }
 
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              hipStream_t st) {
@@ -472,6 +503,11 @@ hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Wor
     case 32: return launch_rows_t<32>(ix, fb, w, st);
     case 64: return launch_rows_t<64>(ix, fb, w, st);
     case 96: return launch_rows_t<96>(ix, fb, w, st);
+    case 128: return launch_rows_t<128>(ix, fb, w, st);
+    case 160: return launch_rows_t<160>(ix, fb, w, st);
+    case 192: return launch_rows_t<192>(ix, fb, w, st);
+    case 224: return launch_rows_t<224>(ix, fb, w, st);
+    case 256: return launch_rows_t<256>(ix, fb, w, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -15,13 +15,21 @@ namespace riann {
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
 constexpr int kRefAlign = 512;   // n is padded to whole 16-tile dense stages
-// Row-layout dense search: a query's running minimum is the key
-// (Y << kRowTileBits) | tile, tile counted from the start of its block's part
-// of the reference range, so a part holds at most 2^kRowTileBits tiles and a
-// launch at most kRowMaxParts parts.
-constexpr int kRowTileBits = 10;
+// Row-layout dense search: a query's running minimum over a segment of
+// 2^row_tile_bits(Dp) tiles is the key (Y << bits) | tile; every real Y is
+// below row_pad_y(Dp) = 2^(32 - bits) - 1 (Y <= Dp * 81409 / 2), the value
+// padding rows get.  A launch splits the reference range over at most
+// kRowMaxParts blocks per query chunk.
+__host__ __device__ constexpr int row_y_bits(int Dp) {
+    int b = 1;
+    while (((int64_t)1 << b) < (int64_t)Dp * 81409 / 2 + 2) ++b;
+    return b;
+}
+__host__ __device__ constexpr int row_tile_bits(int Dp) { return 32 - row_y_bits(Dp); }
+__host__ __device__ constexpr int32_t row_pad_y(int Dp) {
+    return (int32_t)(((int64_t)1 << row_y_bits(Dp)) - 1);
+}
 constexpr int kRowMaxParts = 4;
-constexpr int32_t kRowPadY = (1 << (32 - kRowTileBits)) - 1;
 constexpr int kMaxKeys = 64;
 constexpr int kMaxPatch = 16;    // p <= 16 (D = p*p*C <= 256)
 
@@ -41,19 +49,18 @@ struct DevIndex {
                           // 32t + (l & 31), columns 32kb + 16(l >> 5) .. +16,
                           // at byte offset ((t * Dp/32 + kb) * 64 + l) * 16
     const uint32_t *Rk;   // n_pad dense key bases (see above)
-    // Row-layout dense search (references as MFMA rows, queries as columns,
-    // Dp <= 96), over its own reference order: first every reference with
-    // even Rc, then every one with odd Rc, index order within each class, each
-    // class padded to whole tiles and the whole to kRefAlign (n_rows rows;
-    // 0 when the layout is not built).  With p = Rc & 1 constant per tile,
-    // the lexicographic (Y, tile) minimum lies in the tile that holds the
-    // (SSD, index) minimum.
+    // Row-layout dense search (references as MFMA rows, queries as columns),
+    // over its own reference order: first every reference with even Rc, then
+    // every one with odd Rc, index order within each class, each class padded
+    // to whole tiles and the whole to kRefAlign (n_rows rows).  With
+    // p = Rc & 1 constant per tile, the lexicographic (Y, tile) minimum lies
+    // in the tile that holds the (SSD, index) minimum.
     //   Rfr  n_rows x Dp, those rows in MFMA fragment order (as Rf)
     //   Hf   n_rows, per tile t 32 entries ordered [g][r] = row 32t +
     //        8(r/4) + 4g + r%4, the row accumulator register r of lane group g
     //        holds: Hf = (Rc + bias - p) / 2, so that Y = Hf + <a, v> and
-    //        SSD - Qc + bias = 2Y + p (exact); Y < 2^22 for D <= 96, padding
-    //        rows get 2^22 - 1, above every real Y
+    //        SSD - Qc + bias = 2Y + p (exact); padding rows get
+    //        row_pad_y(Dp), above every real Y
     //   Rci  n_rows, {Rc, reference index} per row in tile order ({0, -1}
     //        for padding rows)
     const int8_t *Rfr;

@@ -407,11 +407,11 @@ def test_large_workloads_sampled(torch_dev, riann, name, nsamp):
     idx.close()
 
 
-@pytest.mark.parametrize("name", ["hd720", "tiny"])
+@pytest.mark.parametrize("name", ["hd720", "tiny", "fhd_rgb"])
 def test_row_and_column_dense_agree_everywhere(torch_dev, riann, name):
-    """Whole-frame full search by the row-layout dense kernel (with its tie
-    fallback) and by the column-layout kernel: identical at every query; a
-    sample also against brute force."""
+    """Whole-frame full search by the row-layout dense kernel (class-ordered
+    references, candidate check) and by the column-layout kernel (index-order
+    keys): identical at every query; a sample also against brute force."""
     torch, dev = torch_dev
     print_case(f"row vs column dense {name}")
     wl = gen.make_workload(name, frames=2)
@@ -579,11 +579,12 @@ def test_class_order_ties(torch_dev, riann, flags):
     idx.close()
 
 
-def test_row_layout_split_reference_range(torch_dev, riann):
-    """n = 40,000 at D = 64: more tiles than one part's 10-bit tile field
-    keys, so every launch splits the reference range (two parts at least)
-    and the resolve kernel merges them; a duplicate in the second part must
-    lose to its lower-index twin."""
+def test_row_layout_two_key_segments(torch_dev, riann):
+    """n = 40,000 at D = 64: more tiles than one 10-bit tile field keys, so
+    each query's running key is folded into its (Y, tile) minimum between two
+    segments (and small frames also split the range over blocks, merged by
+    the resolve kernel); a duplicate in the second segment must lose to its
+    lower-index twin."""
     torch, dev = torch_dev
     print_case("row layout split n=40000")
     rng = np.random.default_rng(43)
@@ -612,11 +613,12 @@ def test_row_layout_split_reference_range(torch_dev, riann):
     idx.close()
 
 
-def test_reference_set_beyond_row_keys(torch_dev, riann):
-    """n = 140,000 at D = 32 exceeds what four 10-bit-keyed parts cover: the
-    dense search takes the column layout, still exact."""
+def test_row_layout_three_key_segments(torch_dev, riann):
+    """n = 140,000 at D = 32: three segments of 2,048 tiles (11-bit tile
+    field); duplicates in the first and last segments resolve to the lower
+    index, and a reference that only the last segment holds is found."""
     torch, dev = torch_dev
-    print_case("n=140000 D=32 column layout")
+    print_case("n=140000 D=32 three key segments")
     rng = np.random.default_rng(47)
     n = 140000
     ref = rng.integers(0, 256, (n, 32), dtype=np.uint8)
@@ -624,10 +626,19 @@ def test_reference_set_beyond_row_keys(torch_dev, riann):
     R0 = oracle.extract(base, 4, 1)
     ref[139999] = R0[40]
     ref[77] = R0[41]
+    ref[5] = R0[42]
+    ref[139998] = R0[42]
     P = oracle.extract(base, 4, 1)
     idx = riann.Index.build(ref, [0, 1], patch=4, channels=2, stride=1, dense_threshold=-1)
     out, ssd = idx.full_search(to_dev(torch, dev, base))
     torch.cuda.synchronize()
     bi, bd = check_exact(out, ssd, P, ref, "n=140000")
     assert bi[40] == 139999 and bd[40] == 0
+    assert bi[42] == 5 and bd[42] == 0
+    b2 = riann.Index.build(ref, [0, 1], patch=4, channels=2, stride=1,
+                           flags=riann.FLAG_COLUMN_DENSE)
+    o2, s2 = b2.full_search(to_dev(torch, dev, base))
+    torch.cuda.synchronize()
+    assert torch.equal(out, o2) and torch.equal(ssd, s2)
+    b2.close()
     idx.close()
