@@ -301,7 +301,7 @@ def main():
                     help="skip the paper's approximate search (needs n x n tables)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-vs-plain comparison")
-    ap.add_argument("--serving-streams", type=int, default=12)
+    ap.add_argument("--serving-streams", type=int, default=64)
     ap.add_argument("--serving-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="after the timed region, run one plain device copy of this many "
