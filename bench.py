@@ -447,6 +447,21 @@ def main():
                                 "GBps": eb / (ems * 1e-3) / 1e9,
                                 "hbm_frac": eb / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "note": "frame read once, encoded patch + Qc + frame id written"}
+        if prof["scan"]["launches"] and st["ring_queries"]:
+            # ring-routed queries: record, list entry, patch, Qc read and the
+            # match written; the smallest ring's P entries and pivot rows; the
+            # survivors' rows (device counters, summed over the timed frames)
+            Kp = (len(wl.keys) + 3) // 4 * 4
+            sb = (st["ring_queries"] * (16 + 4 + Dp + 4 + 8) +
+                  st["sum_mstar_ring"] * (4 + 4 * Kp) + st["sum_survivors"] * Dp) / K
+            sms = prof["scan"]["ms"] / prof["scan"]["launches"]
+            sec["k_scan"] = {"bound": "hbm", "algorithmic_bytes": sb, "ms": sms,
+                             "GBps": sb / (sms * 1e-3) / 1e9,
+                             "hbm_frac": sb / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "ring_queries_per_frame": st["ring_queries"] / K,
+                             "note": "per ring query 32 B + patch; per candidate of the "
+                                     "smallest ring 4 B index + the Kp-word pivot row; per "
+                                     "survivor its row"}
         result["secondary_kernels"] = sec
     if not args.no_extras:
         extras(args, result, idx, wl, frames, bufs[cur], H, Wd, hq, wq, Q, K, W, dev, stream, log)
