@@ -202,11 +202,16 @@ riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *desc
  *           radius (the exact result is still returned).  Ignored in FULL mode.
  *   out     device Hq x Wq x k int32;  ssd  device Hq x Wq x k uint32 or NULL
  *   mode    RIANN_MODE_RING or RIANN_MODE_FULL (exhaustive)
- * For k > 1 the dense search keeps its keys in 32 bits, which limits the
- * reference set to n <= 32 * 2^jb (rounded up to 512) with
- * jb = 32 - ceil(log2(81409 * D + 2)): n <= 32768 for D <= 32, 16384 for
- * D <= 64, 8192 for D <= 192, 4096 for D <= 256; larger sets return
- * RIANN_E_UNSUPPORTED.  The row-layout dense search is not used for k > 1.
+ * For k > 1 the dense search keeps 32-bit keys over the whole reference set.
+ * The default row layout takes the class-ordered set (each parity class of
+ * Rc padded to whole 32-row tiles, the whole to 512 rows) up to 2^b tiles,
+ * b = 32 - ceil(log2(Dp * 81409 / 2 + 2)) with Dp = D rounded up to 32: about
+ * 65,472 references for Dp = 32, 32,704 for Dp <= 96, 16,320 for Dp <= 192
+ * and 8,128 for Dp <= 256.  With RIANN_FLAG_COLUMN_DENSE (or beyond those
+ * sizes) the column layout takes n <= 32 * 2^jb (rounded up to 512),
+ * jb = 32 - ceil(log2(81409 * D + 2)): 32768 for D <= 32, 16384 for D <= 64,
+ * 8192 for D <= 192, 4096 for D <= 256.  Larger sets return
+ * RIANN_E_UNSUPPORTED.
  * Asynchronous on hip_stream; prev must not overlap out or ssd.
  */
 riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame, int32_t H, int32_t W,

@@ -493,7 +493,8 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     {
         KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
         if (knn > 1) {
-            e = launch_dense_knn(h->dix, fb, w, st);
+            e = h->dense_rows && knn_rows_supported(h->dix) ? launch_dense_rows_knn(h->dix, fb, w, st)
+                                                            : launch_dense_knn(h->dix, fb, w, st);
         } else if (rows) {
             e = launch_dense_rows(h->dix, fb, w, st);
         } else {
@@ -589,9 +590,9 @@ riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame_dev, int32_
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
     if (k < 1 || k > kMaxKnn) return fail(RIANN_E_INVALID, "k must be in [1, 8]");
     if (k > h->n) return fail(RIANN_E_INVALID, "k exceeds the number of references");
-    if (k > 1 && !knn_dense_supported(h->dix))
+    if (k > 1 && !(h->dense_rows && knn_rows_supported(h->dix)) && !knn_dense_supported(h->dix))
         return fail(RIANN_E_UNSUPPORTED,
-                    "k-NN fields need n <= 32 * 2^jb for this patch size (see riann.h)");
+                    "k-NN fields: reference set too large for this patch size (see riann.h)");
     FrameBatch fb;
     fb.n = 1;
     riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, prev_dev, out_dev, ssd_dev, mode,

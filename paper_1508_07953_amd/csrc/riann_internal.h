@@ -193,6 +193,11 @@ constexpr int kMaxKnn = 8;
 hipError_t launch_scan_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                            unsigned long long *stats, hipStream_t st);
 bool knn_dense_supported(const DevIndex &ix);
+// Row-layout k-NN (k_dense_rows.hip): one key segment of tiles, see
+// knn_rows_supported; same contract as launch_dense_knn.
+bool knn_rows_supported(const DevIndex &ix);
+hipError_t launch_dense_rows_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                                 hipStream_t st);
 hipError_t launch_dense_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                             hipStream_t st);
 

@@ -101,10 +101,12 @@ SHAPES = [  # p, C, s, n, K, H, W, k
 ]
 
 
+@pytest.mark.parametrize("flags", [0, 1])
 @pytest.mark.parametrize("p,C,s,n,K,H,W,k", SHAPES)
-def test_knn_shapes(torch_dev, riann, p, C, s, n, K, H, W, k):
+def test_knn_shapes(torch_dev, riann, p, C, s, n, K, H, W, k, flags):
+    """Row layout (default) and column layout (flag 1) alike."""
     torch, d = torch_dev
-    print_case(f"knn shape p={p} C={C} s={s} n={n} K={K} k={k}")
+    print_case(f"knn shape p={p} C={C} s={s} n={n} K={K} k={k} flags={flags}")
     rng = np.random.default_rng(p * 100 + n)
     base = rng.integers(0, 256, (H + 8, W + 8, C), dtype=np.uint8)
     f = base[:H, :W].copy()
@@ -114,7 +116,8 @@ def test_knn_shapes(torch_dev, riann, p, C, s, n, K, H, W, k):
     ref = R[np.sort(rng.choice(len(R), n, replace=False))]
     ref[7] = ref[3]                                        # duplicates: index order
     keys = np.sort(rng.choice(n, K, replace=False))
-    idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=s, dense_threshold=100)
+    idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=s, dense_threshold=100,
+                            flags=flags)
     hq, wq = oracle.field_shape(H, W, p, s)
     out, ssd = idx.match_knn(dev(torch, d, f), k, full=True)
     prev, _ = check_knn(torch, out, ssd, oracle.extract(f, p, s), ref, k, "full")
@@ -155,9 +158,67 @@ def test_knn_errors(torch_dev, riann):
     with pytest.raises(riann.RiannError):
         small.match_knn(f, 9, full=True)                   # k > 8
     small.close()
-    big = riann.Index.build(rng.integers(0, 256, (16385, 64), dtype=np.uint8), [0], patch=8)
+    # n = 16,385 at D = 64: beyond the column layout's 32-bit keys, within
+    # the row layout's one key segment
+    ref = rng.integers(0, 256, (16385, 64), dtype=np.uint8)
+    mid = riann.Index.build(ref, [0], patch=8)
+    out, ssd = mid.match_knn(f, 3, full=True)
+    check_knn(torch, out, ssd, oracle.extract(f.cpu().numpy(), 8, 1), ref, 3, "n=16385")
+    mid.close()
+    col = riann.Index.build(ref, [0], patch=8, flags=riann.FLAG_COLUMN_DENSE)
     with pytest.raises(riann.RiannError):
-        big.match_knn(f, 2, full=True)                     # key range exceeded at D = 64
+        col.match_knn(f, 2, full=True)                     # column key range exceeded
+    col.close()
+    big = riann.Index.build(rng.integers(0, 256, (33000, 64), dtype=np.uint8), [0], patch=8)
+    with pytest.raises(riann.RiannError):
+        big.match_knn(f, 2, full=True)                     # both key ranges exceeded
     out, ssd = big.match_knn(f, 1, full=True)              # k = 1 has no limit
     torch.cuda.synchronize()
     big.close()
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_knn_row_and_column_agree_hd720(torch_dev, riann, k):
+    """Whole 720p frame, exhaustive k-NN by the row layout (k smallest
+    class-ordered tiles, rechecked exactly) and by the column layout
+    (32-bit index-order keys): identical fields and SSDs everywhere."""
+    torch, d = torch_dev
+    print_case(f"knn row vs column hd720 k={k}")
+    wl = gen.make_workload("hd720", frames=2)
+    a = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    b = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1,
+                          flags=riann.FLAG_COLUMN_DENSE)
+    f = dev(torch, d, wl.frame(1))
+    oa, sa = a.match_knn(f, k, full=True)
+    ob, sb = b.match_knn(f, k, full=True)
+    torch.cuda.synchronize()
+    assert torch.equal(oa, ob) and torch.equal(sa, sb)
+    a.close()
+    b.close()
+
+
+def test_knn_class_order_ties(torch_dev, riann):
+    """Duplicates and SSD neighbours that share the row layout's half
+    distance Y across the two Rc classes: the k nearest still come in
+    (SSD, index) order."""
+    torch, d = torch_dev
+    print_case("knn class-order ties")
+    rng = np.random.default_rng(23)
+    n = 900
+    ref = rng.integers(0, 256, (n, 64), dtype=np.uint8)
+    q = rng.integers(20, 236, (2, 64), dtype=np.uint8)
+    for qi, base in ((0, 0), (1, 400)):
+        for j, dd in enumerate((0, 1, 1, 2, 2, 3, 0, 1)):
+            r = q[qi].astype(np.int64).copy()
+            r[:dd] += 1
+            if j % 2:
+                r[-1] -= 1 if dd else 0
+            ref[base + 37 * j + 5] = np.clip(r, 0, 255).astype(np.uint8)
+    f = np.zeros((8, 16, 1), np.uint8)
+    f[:, :8, 0] = q[0].reshape(8, 8)
+    f[:, 8:, 0] = q[1].reshape(8, 8)
+    idx = riann.Index.build(ref, [0, 1], patch=8)
+    for k in (2, 5, 8):
+        out, ssd = idx.match_knn(dev(torch, d, f), k, full=True)
+        check_knn(torch, out, ssd, oracle.extract(f, 8, 1), ref, k, f"ties k={k}")
+    idx.close()
