@@ -66,6 +66,17 @@ struct RowCfg {
 #ifndef RIANN_ROWS_SPLIT
 #define RIANN_ROWS_SPLIT 0                     // 0: chosen per launch
 #endif
+#ifndef RIANN_ROWS_SCHED
+// MFMA/VALU interleave: 2 = each MFMA of a chain followed by a share of the
+// minimum tree (1: one MFMA, half the tree, the rest; 0: the compiler's
+// order).  Measured: 2 and 1 equal at D = 64, 2 faster by 1.8 % at D = 192;
+// 0 slower by 3 % at D = 64.  Raising the wave priority around the MFMA
+// issue (RIANN_ROWS_SETPRIO) gained nothing.
+#define RIANN_ROWS_SCHED 2
+#endif
+#ifndef RIANN_ROWS_SETPRIO
+#define RIANN_ROWS_SETPRIO 0                   // 1: raise wave priority while issuing MFMAs
+#endif
 #ifndef RIANN_ROWS_LOOKAHEAD
 #define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
 #endif                                         // (2: within 1 %, 25 more registers)
@@ -178,18 +189,31 @@ struct RowState {
                 const int it = u * QB + qb, nx = it + LA;
                 if (qb == QB - 1 - LA && u + 1 < ST)
                     load_tile(lf, lh, u + 1, lane, grp, Af[cur ^ 1], H[cur ^ 1]);
+                if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(1);
                 if (nx < ST * QB)
                     mma(nx % QB, Af[(nx / QB) & 1], H[(nx / QB) & 1], acc[nx % (LA + 1)]);
+                if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(0);
                 track(qb, acc[it % (LA + 1)], t0s + (uint32_t)u);
-                // one MFMA, then half of the tree, then the chain's other
-                // MFMAs and the rest: the wave keeps issuing VALU work while
-                // each MFMA of the chain executes
-                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, KB - 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
-                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (RIANN_ROWS_SCHED == 1) {
+                    // one MFMA, then half of the tree, then the chain's other
+                    // MFMAs and the rest: the wave keeps issuing VALU work
+                    // while each MFMA of the chain executes
+                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, KB - 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                } else if constexpr (RIANN_ROWS_SCHED == 2) {
+                    // each MFMA of the chain followed by a share of the tree
+                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x002, (10 + KB - 1) / KB, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
     }
