@@ -241,8 +241,30 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     }
     // ring-phase tables: T padded to 16-entry lines, LDS samples, padded Piv
     const int64_t n16 = round_up(n, 16);
-    int64_t s0l = 1;   // sample stride in lines: samples of all keys fit 64 KB
-    while ((int64_t)K * ((n + 16 * s0l - 1) / (16 * s0l)) * 4 > 65536) s0l *= 2;
+    // ring-size lower bounds: per key, B value buckets of width 2^shift from
+    // the key's smallest distance vmin, and cdf[j] = #{entries < vmin +
+    // j 2^shift}, j = 0..B; row k = {vmin, shift, cdf[0..B]} padded to lbS
+    const int lbB = lb_buckets(K), lbS = lb_stride(K);
+    std::vector<uint32_t> Lb((size_t)std::max(K, 1) * lbS, 0u);
+    for (int k = 0; k < K; ++k) {
+        const uint32_t *t = &h->T[(size_t)k * n];
+        const uint64_t vmin = t[0], vmax = t[n - 1];
+        int sh = 0;
+        while (((vmax - vmin) >> sh) >= (uint64_t)lbB) ++sh;
+        uint32_t *row = &Lb[(size_t)k * lbS];
+        row[0] = (uint32_t)vmin;
+        row[1] = (uint32_t)sh;
+        for (int j = 0; j <= lbB; ++j) {
+            const uint64_t edge = vmin + ((uint64_t)j << sh);
+            row[2 + j] = (uint32_t)(std::lower_bound(t, t + n, edge,
+                                                     [](uint32_t x, uint64_t e) { return x < e; }) - t);
+        }
+    }
+    int64_t s0l = 1;   // sample stride in lines: samples, bound rows, key rows and
+                       // key Rc of all keys fit 64 KB of LDS
+    while ((int64_t)K * (((n + 16 * s0l - 1) / (16 * s0l) + 3) / 4 * 4 + lbS + Dp / 4 + 1) * 4 >
+           65536)
+        s0l *= 2;
     const int64_t ns = (n + 16 * s0l - 1) / (16 * s0l);
     const int Kp = (int)round_up(std::max(K, 1), 4);
     std::vector<uint32_t> Tl((size_t)K * n16, 0xFFFFFFFFu), Ts((size_t)std::max<int64_t>(K * ns, 1));
@@ -257,11 +279,12 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szT = (size_t)std::max<int64_t>(K * n16, 1) * 4,
                  szP = (size_t)std::max<int64_t>(K * n, 1) * 4,
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
-                 szS = ST_COUNT * 8, szTs = Ts.size() * 4;
+                 szS = ST_COUNT * 8, szTs = Ts.size() * 4, szLb = Lb.size() * 4;
     const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8;
-    size_t off[13], tot = 0;
-    const size_t sz[13] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci};
-    for (int i = 0; i < 13; ++i) {
+    size_t off[14], tot = 0;
+    const size_t sz[14] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
+                           szLb};
+    for (int i = 0; i < 14; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -284,6 +307,9 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.jb = jb;
     h->dix.bias = (int32_t)bias;
     h->dix.Ts = (const uint32_t *)(b + off[9]);
+    h->dix.Lb = (const uint32_t *)(b + off[13]);
+    h->dix.lbB = lbB;
+    h->dix.lbS = lbS;
     h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.Rfr = (const int8_t *)(b + off[11]);
     h->dix.Rci = (const int2 *)(b + off[12]);
@@ -307,6 +333,7 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         {b + off[5], h->keys.data(), (size_t)K * 4},
         {b + off[7], Rf.data(), szRv},          {b + off[8], Rk.data(), szRc},
         {b + off[9], Ts.data(), (size_t)K * ns * 4},
+        {b + off[13], Lb.data(), szLb},
         {b + off[10], Hf.data(), szHf},
         {b + off[11], Rfr.data(), szRfr},
         {b + off[12], Rci.data(), szRci},

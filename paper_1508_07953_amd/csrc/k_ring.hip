@@ -3,10 +3,12 @@
 // k_ring (one lane per query) follows the per-query steps of Algorithm 1:
 //   extract q; c = SSD(q, R[prev]) (radius^2 from the previous match);
 //   b_k = SSD(q, key_k); ring k = [lo_k, hi_k] in key-distance space with
-//   integer bounds (no rounding slack); two binary searches in key k's
-//   sorted list give [st_k, en_k) (Sec. 3.3: "two binary searches"); the
-//   smallest ring k* is kept; the query is routed to the ring scan when
-//   m* = en - st is small and to the dense search otherwise.
+//   integer bounds (no rounding slack); a lower and an upper position bound
+//   in key k's sorted list give [st_k, en_k) (Sec. 3.3: a ring costs two
+//   binary searches); the smallest ring k* is kept; the query is routed to
+//   the ring scan when m* = en - st is small and to the dense search
+//   otherwise.  Per-key bucket counts bound every m_k first, so the binary
+//   searches run only for the keys that can still hold the smallest ring.
 // k_scan (one wavefront per routed query) scans key k*'s ring, keeps the
 //   references inside all K rings (the intersection S) and takes the argmin
 //   of the exact SSD over S with a wavefront reduction (lowest index on ties).
@@ -120,6 +122,55 @@ __device__ __forceinline__ uint32_t exact_pos(int i, const uint32_t *__restrict_
     return 16u * (uint32_t)L + cnt;
 }
 
+// b = SSD(q, key k) from the key rows staged in LDS (k rows of Dp bytes,
+// then the keys' Rc).
+template <int DP>
+__device__ __forceinline__ uint32_t key_dist(const uint32_t (&a)[DP / 4], int Qc,
+                                             const uint32_t *krows, const uint32_t *krc, int k) {
+    const int d = dot_row<DP>(a, reinterpret_cast<const int8_t *>(krows + k * (DP / 4)));
+    return (uint32_t)(Qc + (int)krc[k] + 2 * d);
+}
+
+// An inner and an outer approximation of key k's ring: s = floor(sqrt(4bc))
+// lies in [s_in, s_out] for the fp32 estimate widened by a relative 2^-18
+// (far above the rounding of the product, the square root and the scaling)
+// and one unit, so [lo_in, hi_in] lies inside the exact ring and
+// [lo_out, hi_out] contains it.
+__device__ __forceinline__ void ring_approx(uint32_t b, uint32_t c, uint32_t &lo_in,
+                                            uint32_t &hi_in, uint32_t &lo_out, uint32_t &hi_out) {
+    const float sf = 2.0f * sqrtf((float)b * (float)c);
+    const float si = floorf(sf * (1.0f - 0x1p-18f)) - 1.0f;
+    const float so = ceilf(sf * (1.0f + 0x1p-18f)) + 1.0f;
+    const uint64_t s_in = si > 0.0f ? (uint64_t)si : 0ull, s_out = (uint64_t)so;
+    const uint64_t bc = (uint64_t)b + c;
+    lo_in = b <= c ? 0u : (uint32_t)(bc - min(s_in, bc));
+    hi_in = (uint32_t)min<uint64_t>(bc + s_in, 0xFFFFFFFFull);
+    lo_out = b <= c ? 0u : (uint32_t)(bc - min(s_out, bc));
+    hi_out = (uint32_t)min<uint64_t>(bc + s_out, 0xFFFFFFFFull);
+}
+
+// Bounds on the number of key-list entries inside the exact ring from the
+// key's bucket counts (row {vmin, shift, cdf[0..B]}): the whole buckets
+// inside [lo_in, hi_in] give lb, the buckets meeting [lo_out, hi_out] give ub.
+__device__ __forceinline__ void ring_size_bounds(const uint32_t *row, int B, uint32_t lo_in,
+                                                 uint32_t hi_in, uint32_t lo_out, uint32_t hi_out,
+                                                 uint32_t &lb, uint32_t &ub) {
+    const uint32_t vmin = row[0], sh = row[1];
+    const uint64_t w = 1ull << sh;
+    // entries below vmin + d: d from the interval's ends
+    auto below = [&](uint32_t v, bool incl) -> uint64_t {
+        return v >= vmin ? (uint64_t)(v - vmin) + (incl ? 1ull : 0ull) : 0ull;
+    };
+    const uint64_t dli = below(lo_in, false), dhi = below(hi_in, true);
+    const uint64_t dlo = below(lo_out, false), dho = below(hi_out, true);
+    const uint32_t jl_in = (uint32_t)min<uint64_t>((uint64_t)B, (dli + w - 1) >> sh);
+    const uint32_t jh_in = (uint32_t)min<uint64_t>((uint64_t)B, dhi >> sh);
+    const uint32_t jl_out = (uint32_t)min<uint64_t>((uint64_t)B, dlo >> sh);
+    const uint32_t jh_out = (uint32_t)min<uint64_t>((uint64_t)B, (dho + w - 1) >> sh);
+    lb = jh_in > jl_in ? row[2 + jh_in] - row[2 + jl_in] : 0u;
+    ub = jh_out > jl_out ? row[2 + jh_out] - row[2 + jl_out] : 0u;
+}
+
 __device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
     unsigned m = __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u);
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), m);
@@ -131,40 +182,61 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
 }
 
 // ---------------------------------------------------------------- k_ring
-// One lane per query, 1024 queries per block.  Each block first copies the
-// binary-search samples of all K lists (at most 64 KB) into LDS.  For every
-// key the LDS samples bracket the ring size m_k to an interval [ml, mh]; the
-// exact size (two line reads in global memory) is computed only for keys
-// that can still be the smallest ring: key k is skipped when ml > min over
-// earlier keys of mh (some earlier ring is strictly smaller) or ml >= the
-// smallest exact size so far (an earlier key wins the tie).  The result --
-// the exact smallest ring m*, its key k* (lowest on ties) and its range --
-// is the same as evaluating every key exactly.
+// One lane per query.  Each block first copies into LDS (at most 64 KB): the
+// binary-search samples of all K lists, each key's bucket-count row and the
+// key rows with their Rc.  Then, per query:
+//  1. every key's ring-size bounds [lb_k, ub_k] from its bucket counts, with
+//     an inner and an outer fp32 approximation of the ring (no exact square
+//     root yet); the seed key is the smallest lb (lowest k on ties);
+//  2. the seed's exact ring: exact bounds, the LDS samples bracket the two
+//     positions, two line reads in global memory fix them;
+//  3. the remaining keys whose lower bound can still beat (m, k) -- chosen
+//     against the seed's exact size when the bounds stay in registers (K <= 16,
+//     Dp <= 64), else against the smallest upper bound -- each lane taking
+//     its own keys in turn; a key is searched only while (lb, k) and then its
+//     sample bracket (ml, k) are below the best (m, k), and wins on a smaller
+//     size or an equal one at a lower index.
+// The result -- the exact smallest ring m*, its key k* (lowest on ties) and
+// its range -- is the same as evaluating every key exactly.
 // List appends and statistics are aggregated per block: one atomic per list
 // and per counter per block.
-constexpr int kRingBlock = 1024;
-constexpr int kRingWaves = kRingBlock / 64;
+// Queries per block: 1024, or 512 for the variant that keeps the bounds of
+// up to 16 keys in registers (80 VGPRs: six wavefronts per SIMD fit in three
+// 512-query blocks, not in 1024-query ones).
+__host__ __device__ constexpr int ring_block(int KR) { return KR > 0 ? 512 : 1024; }
 
-template <int DP>
-__global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb, Work w,
+template <int DP, int KR>
+__global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevIndex ix, FrameBatch fb, Work w,
                                                       unsigned long long *__restrict__ stats,
                                                       int64_t threshold) {
+    constexpr int kBlk = ring_block(KR), kWv = kBlk / 64;
     extern __shared__ __attribute__((aligned(16))) uint32_t s_samp[];
-    __shared__ uint32_t s_wcnt[kRingWaves][2];
+    __shared__ uint32_t s_wcnt[kWv][2];
     __shared__ uint32_t s_base[2];
-    __shared__ unsigned long long s_st[kRingWaves][4];
+    __shared__ unsigned long long s_st[kWv][4];
     const int nsamp = ix.K * ix.ns;
     // 16-byte copies (the table is 256-byte aligned): four rounds for 64 KB
-    for (int i = threadIdx.x; i < nsamp / 4; i += kRingBlock)
+    for (int i = threadIdx.x; i < nsamp / 4; i += kBlk)
         reinterpret_cast<uint4 *>(s_samp)[i] = reinterpret_cast<const uint4 *>(ix.Ts)[i];
-    for (int i = (nsamp & ~3) + threadIdx.x; i < nsamp; i += kRingBlock) s_samp[i] = ix.Ts[i];
+    for (int i = (nsamp & ~3) + threadIdx.x; i < nsamp; i += kBlk) s_samp[i] = ix.Ts[i];
+    const int olb = (nsamp + 3) & ~3;             // bound rows after the samples,
+    const int olk = olb + ix.K * ix.lbS;          // then the key rows and their Rc
+    const int olc = olk + ix.K * (DP / 4);
+    for (int i = threadIdx.x; i < ix.K * ix.lbS / 4; i += kBlk)
+        reinterpret_cast<uint4 *>(s_samp + olb)[i] = reinterpret_cast<const uint4 *>(ix.Lb)[i];
+    for (int i = threadIdx.x; i < ix.K * (DP / 16); i += kBlk) {
+        const int k = i / (DP / 16), part = i - k * (DP / 16);
+        reinterpret_cast<uint4 *>(s_samp + olk)[i] =
+            reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)ix.keys[k] * ix.Dp)[part];
+    }
+    for (int k = threadIdx.x; k < ix.K; k += kBlk) s_samp[olc + k] = (uint32_t)ix.Rc[ix.keys[k]];
     __syncthreads();
 
     const int64_t Q = fb.Q;
     const uint32_t n = (uint32_t)ix.n;
     const int nlines = ix.n16 / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t qid = (int64_t)blockIdx.x * kRingBlock + threadIdx.x;
+    const int64_t qid = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const bool valid = qid < Q;
     const int64_t qq = valid ? qid : Q - 1;
     const FrameDesc *fdp = &fb.f[w.fid[qq]];
@@ -201,28 +273,86 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb,
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
     if (!full && !noprior && ix.K > 0) {
-        uint32_t up = 0xFFFFFFFFu;        // min over evaluated keys of mh
-        bool have = false;                // best_m holds an exact size
-        for (int k = 0; k < ix.K; ++k) {
-            const int key = ix.keys[k];
-            int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
-            uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
+        const uint32_t *LB = s_samp + olb, *KR_ = s_samp + olk, *KC = s_samp + olc;
+        const int B = ix.lbB, LS = ix.lbS;
+        // 1. every key's ring-size bounds from its bucket counts: the seed is
+        //    the smallest lower bound (lowest key on ties); keys whose lower
+        //    bound exceeds the smallest upper bound so far cannot hold the
+        //    smallest ring, the others are marked (a superset of the keys
+        //    the exact search below may need)
+        uint32_t k1 = 0, lb1 = 0xFFFFFFFFu, b1 = 0, ubmin = 0xFFFFFFFFu;
+        unsigned long long cand = 0;
+        uint32_t lbv[KR > 0 ? KR : 1];            // KR > 0: every key's lower bound
+        auto bound_key = [&](int k) {
+            const uint32_t b = key_dist<DP>(a, Qc, KR_, KC, k);
+            uint32_t li, hi_, lo_, ho;
+            ring_approx(b, c, li, hi_, lo_, ho);
+            uint32_t lb, ub;
+            ring_size_bounds(LB + k * LS, B, li, hi_, lo_, ho, lb, ub);
+            ubmin = min(ubmin, ub);
+            if (lb < lb1) { lb1 = lb; k1 = (uint32_t)k; b1 = b; }
+            return lb;
+        };
+        if constexpr (KR > 0) {
+            // all K <= KR keys unrolled, so the bounds stay in registers and
+            // the candidates are chosen against the seed's exact size below
+#pragma unroll
+            for (int k = 0; k < KR; ++k) lbv[k] = k < ix.K ? bound_key(k) : 0xFFFFFFFFu;
+        } else {
+            for (int k = 0; k < ix.K; ++k) {
+                const uint32_t lb = bound_key(k);
+                if (lb <= ubmin) cand |= 1ull << k;
+            }
+        }
+        // 2. the seed's exact ring
+        {
+            uint32_t lo1, hi1;
+            ring_bounds(b1, c, lo1, hi1);
+            const uint32_t *S = s_samp + k1 * ix.ns;
+            const int il = sample_count<false>(S, ix.ns, lo1);
+            const int ih = sample_count<true>(S, ix.ns, hi1);
+            const uint32_t *t = ix.T + (int64_t)k1 * ix.n16;
+            best_st = exact_pos<false>(il, t, nlines, ix.s0l, lo1);
+            best_en = exact_pos<true>(ih, t, nlines, ix.s0l, hi1);
+            best_m = best_en - best_st;
+            best_k = k1;
+        }
+        if constexpr (KR > 0) {
+            // keys whose lower bound can still beat (best_m, best_k)
+#pragma unroll
+            for (int k = 0; k < KR; ++k)
+                if (lbv[k] < best_m || (lbv[k] == best_m && (uint32_t)k < best_k))
+                    cand |= 1ull << k;
+        }
+        cand &= ~(1ull << k1);
+        // 3. each lane takes its own remaining keys in turn (the wavefront
+        //    loops as often as its busiest lane needs): a key is searched
+        //    only if its bounds can still beat (best_m, best_k), and wins on
+        //    a smaller size or an equal size at a lower index
+        while (__ballot(cand != 0)) {
+            if (cand == 0) continue;
+            const int k = __builtin_ctzll(cand);
+            cand &= cand - 1;
             uint32_t lo, hi;
-            ring_bounds(b, c, lo, hi);
+            ring_bounds(key_dist<DP>(a, Qc, KR_, KC, k), c, lo, hi);
+            uint32_t lb, ub;
+            ring_size_bounds(LB + k * LS, B, lo, hi, lo, hi, lb, ub);
+            if (lb > best_m || (lb == best_m && (uint32_t)k > best_k)) continue;
             const uint32_t *S = s_samp + k * ix.ns;
             const int il = sample_count<false>(S, ix.ns, lo);
             const int ih = sample_count<true>(S, ix.ns, hi);
             uint32_t sl, sh, el, eh;
             pos_bracket(il, ix.ns, ix.s0l, n, sl, sh);
             pos_bracket(ih, ix.ns, ix.s0l, n, el, eh);
-            const uint32_t ml = el > sh ? el - sh : 0u, mh = eh - sl;
-            if (ml > up || (have && ml >= best_m)) continue;
-            up = min(up, mh);
+            const uint32_t ml = el > sh ? el - sh : 0u;
+            if (ml > best_m || (ml == best_m && (uint32_t)k > best_k)) continue;
             const uint32_t *t = ix.T + (int64_t)k * ix.n16;
             const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo);
             const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi);
             const uint32_t m = en - st;
-            if (!have || m < best_m) { best_m = m; best_k = k; best_st = st; best_en = en; have = true; }
+            if (m < best_m || (m == best_m && (uint32_t)k < best_k)) {
+                best_m = m; best_k = (uint32_t)k; best_st = st; best_en = en;
+            }
         }
     }
     const bool ring = valid && !full && !noprior && ix.K > 0 && (int64_t)best_m <= threshold;
@@ -238,7 +368,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb,
     __syncthreads();
     if (threadIdx.x < 2) {
         uint32_t tot = 0;
-        for (int i = 0; i < kRingWaves; ++i) {
+        for (int i = 0; i < kWv; ++i) {
             const uint32_t c0 = s_wcnt[i][threadIdx.x];
             s_wcnt[i][threadIdx.x] = tot;
             tot += c0;
@@ -262,11 +392,11 @@ __global__ __launch_bounds__(kRingBlock) void k_ring(DevIndex ix, FrameBatch fb,
     __syncthreads();
     if (threadIdx.x < 4) {
         unsigned long long tot = 0;
-        for (int i = 0; i < kRingWaves; ++i) tot += s_st[i][threadIdx.x];
+        for (int i = 0; i < kWv; ++i) tot += s_st[i][threadIdx.x];
         const int slot[4] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE};
         if (tot) atomicAdd(&stats[slot[threadIdx.x]], tot);
         if (threadIdx.x == 3) {
-            const int64_t nv = min<int64_t>(kRingBlock, Q - (int64_t)blockIdx.x * kRingBlock);
+            const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)blockIdx.x * kBlk);
             atomicAdd(&stats[ST_QUERIES], (unsigned long long)nv);
         }
     }
@@ -463,10 +593,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_knn(DevIndex ix, FrameBatch fb,
 template <int DP>
 hipError_t launch_ring_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                          unsigned long long *stats, int64_t threshold, hipStream_t st) {
-    const int64_t blocks = (fb.Q + kRingBlock - 1) / kRingBlock;
-    const size_t lds = (size_t)ix.K * ix.ns * 4;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP>), dim3((unsigned)blocks), dim3(kRingBlock),
-                       lds, st, ix, fb, w, stats, threshold);
+    const size_t lds = ((size_t)((ix.K * ix.ns + 3) & ~3) + (size_t)ix.K * (ix.lbS + DP / 4 + 1)) * 4;
+    // the register-bound variant fits 80 VGPRs without spills up to Dp = 64
+    if constexpr (DP <= 64) {
+        if (ix.K <= 16) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP, 16>),
+                               dim3((unsigned)((fb.Q + ring_block(16) - 1) / ring_block(16))),
+                               dim3(ring_block(16)), lds, st, ix, fb, w, stats, threshold);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP, 0>),
+                       dim3((unsigned)((fb.Q + ring_block(0) - 1) / ring_block(0))),
+                       dim3(ring_block(0)), lds, st, ix, fb, w, stats, threshold);
     return hipGetLastError();
 }
 

@@ -30,6 +30,11 @@ __host__ __device__ constexpr int32_t row_pad_y(int Dp) {
     return (int32_t)(((int64_t)1 << row_y_bits(Dp)) - 1);
 }
 constexpr int kRowMaxParts = 4;
+
+// Ring-size lower bounds (k_ring): buckets per key and the padded row length
+// (vmin, shift, cdf[0..B]); a table of at most ~8.5 KB for K <= 64.
+__host__ __device__ constexpr int lb_buckets(int K) { return K <= 16 ? 128 : (K <= 32 ? 64 : 32); }
+__host__ __device__ constexpr int lb_stride(int K) { return (lb_buckets(K) + 3 + 3) / 4 * 4; }
 constexpr int kMaxKeys = 64;
 constexpr int kMaxPatch = 16;    // p <= 16 (D = p*p*C <= 256)
 
@@ -75,6 +80,9 @@ struct DevIndex {
                           // with zeros (padding keys get the bounds [0, 2^32-1])
     const uint32_t *Ts;   // K x ns binary-search samples Ts[k][i] = T[k][i * 16 * s0l],
                           // copied to LDS by the ring phase
+    const uint32_t *Lb;   // K x lbS ring-size lower-bound rows {vmin, shift,
+                          // cdf[0..lbB]}: cdf[j] = #{T[k] < vmin + j 2^shift};
+                          // copied to LDS after the samples (ns rounded to 4)
     const int32_t *keys;  // K key indices
     int64_t n, n_pad;
     int32_t D, Dp, K, p, C, s;
@@ -84,6 +92,7 @@ struct DevIndex {
     int32_t ns;           // samples per key
     int32_t s0l;          // sample stride in 16-entry lines
     int32_t Kp;           // Piv row stride
+    int32_t lbB, lbS;     // lower-bound buckets per key, row stride in words
 };
 
 // One frame of a launch.  A launch takes up to kMaxBatch frames of any sizes;
