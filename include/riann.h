@@ -220,7 +220,9 @@ riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame, int32_t H,
 
 /*
  * riann_footprint -- device bytes an index with parameters p needs, plus the
- * per-stream scratch for frames of H x W (H = W = 0: index only).
+ * per-stream scratch for frames of H x W (H = W = 0: index only).  An upper
+ * bound: the dense search's class-ordered copy of the references is counted
+ * with the most padding any reference set of n can need.
  */
 riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W,
                                int64_t *bytes);
