@@ -642,3 +642,49 @@ def test_row_layout_three_key_segments(torch_dev, riann):
     assert torch.equal(out, o2) and torch.equal(ssd, s2)
     b2.close()
     idx.close()
+
+
+RING_CASES = [  # p, C, K, n: the ring phase's register-bound (K <= 16, Dp <= 64) and general paths
+    (8, 1, 8, 1500),
+    (4, 2, 16, 2000),
+    (8, 1, 24, 1800),
+    (6, 1, 40, 1200),
+    (8, 3, 8, 900),
+    (8, 3, 32, 1300),
+]
+
+
+@pytest.mark.parametrize("p,C,K,n", RING_CASES)
+def test_ring_stats_both_paths(torch_dev, riann, p, C, K, n):
+    """Per-key bucket bounds must leave m* and the survivor counts exactly
+    the oracle's (all K rings evaluated), whichever key-selection path runs;
+    every query with a prior is sent to the ring scan, so a wrong k* or range
+    would also break the exact field."""
+    torch, dev = torch_dev
+    print_case(f"ring stats p={p} C={C} K={K} n={n}")
+    rng = np.random.default_rng(1000 * p + K)
+    H, W = 30, 41
+    base = rng.integers(0, 256, (H + 40, W + 40, C), dtype=np.uint8)
+    f = np.clip(base[2:H + 2, 1:W + 1].astype(np.int32) + rng.integers(-4, 5, (H, W, C)),
+                0, 255).astype(np.uint8)
+    R = oracle.extract(base, p, 1)
+    ref = R[np.sort(rng.choice(len(R), n, replace=False))]
+    ref[11] = ref[3]
+    keys = np.sort(rng.choice(n, K, replace=False))
+    idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=1, dense_threshold=n)
+    P = oracle.extract(f, p, 1)
+    hq, wq = oracle.field_shape(H, W, p, 1)
+    prev = rng.integers(-1, n, (hq, wq)).astype(np.int32)
+    prev[::3] = oracle.brute_force(P[::1], ref)[0].reshape(hq, wq)[::3]   # some exact priors
+    idx.reset_stats()
+    out, ssd = idx.match_frame(to_dev(torch, dev, f), prev=to_dev(torch, dev, prev))
+    torch.cuda.synchronize()
+    check_exact(out, ssd, P, ref, "ring stats")
+    o = oracle.Tables(ref, keys).riann(P, prev.reshape(-1))
+    ring = o["noprior"] == 0
+    st = idx.stats()
+    assert st["sum_mstar"] == int(o["mstar"].sum())
+    assert st["ring_queries"] == int(ring.sum())
+    assert st["sum_survivors"] == int(o["nsurv"][ring].sum())
+    assert st["no_prior"] == int(o["noprior"].sum())
+    idx.close()
