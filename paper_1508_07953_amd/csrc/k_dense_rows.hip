@@ -20,9 +20,11 @@
 // earlier tile.  The wavefront then recomputes the exact SSDs of that tile's
 // rows in the lane group(s) that reached the minimum and takes their (SSD,
 // index) minimum; these gathers overlap the matrix work of the other
-// wavefronts on the SIMD.  For small frames the reference range is split over
-// up to four blocks per query chunk; the parts then leave records that a
-// resolve kernel merges before the same check.
+// wavefronts on the SIMD.  Query chunks that fill whole rounds of the resident
+// block slots run whole; the chunks of a last, partial round (or all of them
+// when there are fewer chunks than slots) split the reference range over up
+// to four blocks each, so the last round runs full and short.  The parts
+// leave records that a resolve kernel merges before the same check.
 #include "riann_internal.h"
 
 #include <algorithm>
@@ -63,9 +65,6 @@ struct RowCfg {
     static constexpr int block_q = wave_q * waves;
     static_assert(qb >= 2, "the LDS prefetch runs one query block ahead");
 };
-#ifndef RIANN_ROWS_SPLIT
-#define RIANN_ROWS_SPLIT 0                     // 0: chosen per launch
-#endif
 #ifndef RIANN_ROWS_SCHED
 // MFMA/VALU interleave: 2 = each MFMA of a chain followed by a share of the
 // minimum tree (1: one MFMA, half the tree, the rest; 0: the compiler's
@@ -312,9 +311,37 @@ struct RowCheck {
     }
 };
 
+// How a launch covers `chunks` query chunks with `slots` resident blocks:
+// the first `whole` chunks run as one block each over every reference; each
+// later chunk is split over `parts` blocks (consecutive blocks, consecutive
+// parts).  With more chunks than slots, only the remainder past whole rounds
+// is split, into as many parts as still fit one round (at most
+// kRowMaxParts); with fewer, every chunk is split so the chunks' parts cover
+// the slots.  Blocks used: whole + (chunks - whole) * parts
+// <= chunks + min(3 * chunks, slots).
+struct RowPlan {
+    uint32_t whole, parts;
+};
+__host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots) {
+    const uint32_t cap = (uint32_t)kRowMaxParts;
+    uint32_t p = 1;
+    if (chunks == 0 || slots == 0) return RowPlan{chunks, 1u};
+    if (chunks <= slots) {
+        p = (slots + chunks - 1) / chunks;
+        p = p < cap ? p : cap;
+        return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
+    }
+    const uint32_t rem = chunks % slots;
+    if (rem) {
+        p = slots / rem;
+        p = p < cap ? p : cap;
+    }
+    return p > 1 ? RowPlan{chunks - rem, p} : RowPlan{chunks, 1u};
+}
+
 template <int DP, int ST>
 __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
-                                                       int nsplit) {
+                                                       uint32_t slots) {
     constexpr int KB = DP / 32;
     constexpr int kWaves = RowCfg<DP>::waves, kQB = RowCfg<DP>::qb;
     constexpr int kWaveQ = RowCfg<DP>::wave_q, kBlockQ = RowCfg<DP>::block_q;
@@ -334,11 +361,17 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, F
 
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    // nsplit blocks per query chunk, each over one part of the reference
-    // stages (consecutive blocks take consecutive parts and land on
-    // different XCDs, so each XCD's L2 holds fewer parts)
-    const uint32_t split = blockIdx.x % (uint32_t)nsplit;
-    const uint32_t qbase = (blockIdx.x / (uint32_t)nsplit) * kBlockQ;
+    // whole chunks first, then the split ones, nsplit blocks per chunk, each
+    // over one part of the reference stages (consecutive blocks take
+    // consecutive parts and land on different XCDs, so each XCD's L2 holds
+    // fewer parts)
+    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
+    const uint32_t bx = blockIdx.x;
+    const bool whole = bx < plan.whole;
+    const int nsplit = whole ? 1 : (int)plan.parts;
+    const uint32_t split = whole ? 0u : (bx - plan.whole) % plan.parts;
+    const uint32_t chunk = whole ? bx : plan.whole + (bx - plan.whole) / plan.parts;
+    const uint32_t qbase = chunk * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
 
     // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
@@ -638,48 +671,55 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows_knn(DevIndex i
     }
 }
 
-// Resolve step of a launch whose reference range is split over several
-// blocks per query chunk: 16 lanes per dense query take the lexicographic
+// Resolve step for the split chunks of a launch (the dense-list positions
+// from whole * block_q on): 16 lanes per dense query take the lexicographic
 // (Y, tile) minimum of the parts' records (disjoint tile ranges, so the first
 // part reaching the smallest Y wins, with its group mask) and run the
 // candidate check.  The records sit at the list position, so they load
-// alongside the list.
+// alongside the list.  A grid-stride loop whose trip count is uniform over
+// the block; with no split chunk every block returns at once.
 template <int DP>
-__global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w, int nsplit) {
+__global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w, uint32_t slots) {
+    constexpr uint32_t kBlockQ = RowCfg<DP>::block_q;
     const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
     const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
+    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
+    const int nsplit = (int)plan.parts;
     const int lane = threadIdx.x & 63, r = lane & 15;
-    const uint32_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
-    const bool live = i < count;
-    const uint32_t q = live ? (list ? list[i] : i) : 0u;
-    uint2 rec = make_uint2(0u, 0u);
-    if (live) {
-        unsigned long long best = ~0ull;
+    for (uint32_t base = plan.whole * kBlockQ + blockIdx.x * 16u; base < count;
+         base += gridDim.x * 16u) {
+        const uint32_t i = base + (threadIdx.x >> 4);
+        const bool live = i < count;
+        const uint32_t q = live ? (list ? list[i] : i) : 0u;
+        uint2 rec = make_uint2(0u, 0u);
+        if (live) {
+            unsigned long long best = ~0ull;
 #pragma unroll
-        for (int s = 0; s < kRowMaxParts; ++s) {
-            if (s < nsplit) {
-                const uint4 p = s ? w.rec2[(int64_t)(s - 1) * w.capacity + i] : w.rec[i];
-                const unsigned long long k = ((unsigned long long)p.x << 32) | p.y;
-                best = k < best ? k : best;
+            for (int s = 0; s < kRowMaxParts; ++s) {
+                if (s < nsplit) {
+                    const uint4 p = s ? w.rec2[(int64_t)(s - 1) * w.capacity + i] : w.rec[i];
+                    const unsigned long long k = ((unsigned long long)p.x << 32) | p.y;
+                    best = k < best ? k : best;
+                }
             }
+            rec = make_uint2((uint32_t)(best >> 32), (uint32_t)best);
         }
-        rec = make_uint2((uint32_t)(best >> 32), (uint32_t)best);
+        RowCheck<DP> C;
+        C.issue(ix, w, q, rec, live, r);
+        C.finish(ix, fb, w, q, rec, live, lane,
+                 reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP));
     }
-    RowCheck<DP> C;
-    C.issue(ix, w, q, rec, live, r);
-    C.finish(ix, fb, w, q, rec, live, lane,
-             reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP));
 }
 
 template <int DP>
 hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
     constexpr int ST = DP <= 64 ? 8 : 4;
     static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
-    // Split the reference range over nsplit blocks per query chunk when there
-    // are too few chunks to give every resident block slot one (small
-    // frames); measured on a 720p frame (1,773 chunks, 768 slots) splitting
-    // costs more -- the query patches are read once per part -- than its
-    // shorter last round gains.
+    // The dense query count is known on the device only: the grid covers the
+    // largest plan any count up to fb.Q can take, and surplus blocks return
+    // at once.  (Splitting every chunk of a 720p frame -- 1,773 chunks on
+    // 768 slots -- costs more than it gains: the query patches are read once
+    // per part and every query goes through the resolve kernel.)
     static int resident = 0;
     if (resident == 0) {
         int dev = 0, cus = 0, per = 0;
@@ -691,19 +731,18 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
     }
     constexpr int kBlockQ = RowCfg<DP>::block_q;
     const int64_t chunks = std::max<int64_t>(1, (fb.Q + kBlockQ - 1) / kBlockQ);
-    int nsplit = (int)std::min<int64_t>(kRowMaxParts, (resident + chunks - 1) / chunks);
-#if RIANN_ROWS_SPLIT > 0
-    nsplit = RIANN_ROWS_SPLIT;
-#endif
-    const int64_t blocks = nsplit * chunks;
+    const uint32_t slots = (uint32_t)resident;
+    const int64_t blocks = chunks + std::min<int64_t>(3 * chunks, resident);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks),
                        dim3(RowCfg<DP>::block),
-                       0, st, ix, fb, w, nsplit);
+                       0, st, ix, fb, w, slots);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nsplit == 1) return e;
-    const int64_t rb = (fb.Q + 15) / 16;          // 16 queries per 256-thread block
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)(rb < 1 ? 1 : rb)), dim3(256),
-                       0, st, ix, fb, w, nsplit);
+    if (e != hipSuccess) return e;
+    // split queries: fewer than min(chunks, slots) chunks' worth
+    const int64_t sq = std::min<int64_t>(chunks, resident) * kBlockQ;
+    const int64_t rb = std::min<int64_t>((sq + 15) / 16, 4096);   // 16 queries per 256-thread block
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)rb), dim3(256),
+                       0, st, ix, fb, w, slots);
     return hipGetLastError();
 }
 
