@@ -405,7 +405,8 @@ def main():
         "p50_frame_ms": float(np.percentile(lat, 50)),
         "p99_frame_ms": float(np.percentile(lat, 99)),
         "routing": {"ring_queries": st["ring_queries"], "dense_queries": st["dense_queries"],
-                    "mean_mstar": st["sum_mstar"] / max(1, st["queries"]),
+                    "bound_routed": st["bound_routed"],
+                    "mean_mstar_evaluated": st["sum_mstar"] / max(1, st["queries"] - st["bound_routed"]),
                     "dense_threshold": int(idx.params.dense_threshold),
                     "autotune_ms_per_frame": tuned["ms"] if tuned else None},
     }

@@ -90,6 +90,15 @@ typedef struct riann_params {
  * cross-check of the two kernels. */
 #define RIANN_FLAG_COLUMN_DENSE 1u
 
+/* riann_params_t.flags: evaluate the smallest ring m* of every ring-phase
+ * query exactly.  By default a query whose ring-size lower bounds (per-key
+ * bucket counts of the sorted distance lists, Sec. 3.3) already exceed the
+ * dense threshold on every key goes to the dense search without its exact
+ * m*: its smallest ring holds more than the threshold's candidates either
+ * way, so routing and results are identical; only riann_stats_t.sum_mstar
+ * then leaves such queries out (they are counted in bound_routed). */
+#define RIANN_FLAG_EXACT_MSTAR 2u
+
 /* One frame of a batch (riann_match_batch). */
 typedef struct riann_frame_desc {
     const uint8_t *frame;      /* device, H x W x C, row pitch `pitch`         */
@@ -115,11 +124,15 @@ typedef struct riann_stats {
     uint64_t ring_queries;     /* queries answered by the ring scan            */
     uint64_t dense_queries;    /* queries answered by the dense search         */
     uint64_t no_prior;         /* queries whose prev entry was -1/out of range  */
-    uint64_t sum_mstar;        /* sum over ring-phase queries of the smallest
-                                  ring size m* (all queries of RING frames)    */
+    uint64_t sum_mstar;        /* sum over ring-phase queries (all queries of
+                                  RING frames) of the smallest ring size m*,
+                                  except those in bound_routed                 */
     uint64_t sum_survivors;    /* sum over ring-scanned queries of |S|, the
                                   number of references inside all K rings     */
     uint64_t sum_mstar_ring;   /* sum of m* over ring-scanned queries only     */
+    uint64_t bound_routed;     /* ring-phase queries sent to the dense search
+                                  by their ring-size lower bounds alone, m*
+                                  not evaluated (0 with RIANN_FLAG_EXACT_MSTAR) */
 } riann_stats_t;
 
 /*

@@ -30,6 +30,7 @@ RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, R
     0, -1, -2, -3, -4, -5)
 MODE_RING, MODE_FULL = 0, 1
 FLAG_COLUMN_DENSE = 1
+FLAG_EXACT_MSTAR = 2
 
 # every symbol include/riann.h declares
 EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
@@ -66,7 +67,7 @@ class Profile(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in
                 ("frames", "queries", "ring_queries", "dense_queries", "no_prior",
-                 "sum_mstar", "sum_survivors", "sum_mstar_ring")]
+                 "sum_mstar", "sum_survivors", "sum_mstar_ring", "bound_routed")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

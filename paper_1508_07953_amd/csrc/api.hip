@@ -93,7 +93,7 @@ riann_status_t check_params(const riann_params_t *p) {
     if (p->n_keys < 0 || p->n_keys > kMaxKeys)
         return fail(RIANN_E_INVALID, "n_keys must be in [0, 64]");
     if (p->n_keys > p->n_ref) return fail(RIANN_E_INVALID, "n_keys exceeds n_ref");
-    if ((p->flags & ~RIANN_FLAG_COLUMN_DENSE) != 0 || p->reserved != 0)
+    if ((p->flags & ~(RIANN_FLAG_COLUMN_DENSE | RIANN_FLAG_EXACT_MSTAR)) != 0 || p->reserved != 0)
         return fail(RIANN_E_INVALID, "unknown flags or nonzero reserved field");
     return RIANN_OK;
 }
@@ -310,6 +310,7 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.Lb = (const uint32_t *)(b + off[13]);
     h->dix.lbB = lbB;
     h->dix.lbS = lbS;
+    h->dix.exact_mstar = (h->prm.flags & RIANN_FLAG_EXACT_MSTAR) ? 1 : 0;
     h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.Rfr = (const int8_t *)(b + off[11]);
     h->dix.Rci = (const int2 *)(b + off[12]);
@@ -492,11 +493,8 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     if (s != RIANN_OK) return s;
     hipError_t e;
     const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
-    if (!all_full) {
-        e = launch_zero_u32(w.counters, 4, st);
-        if (e != hipSuccess) return hip_fail(e, "counter clear");
-    }
     {
+        // the extraction kernel also clears the ring and dense list counters
         KTimer tm(h, RIANN_K_EXTRACT, st);
         e = launch_extract(h->dix, fb, w, st);
         tm.stop();
@@ -692,6 +690,7 @@ riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
     s->sum_mstar = v[ST_MSTAR];
     s->sum_survivors = v[ST_SURV];
     s->sum_mstar_ring = v[ST_MSTAR_RING];
+    s->bound_routed = v[ST_BOUND];
     return RIANN_OK;
 }
 

@@ -11,7 +11,9 @@
 // Qc = sum over the D real bytes of (a + 1)^2.  When a window row holds a
 // whole number of 32-bit words (p*C % 4 == 0: 8x8 gray, 8x8x3, 12x12, ...)
 // a template instance reads each row as aligned LDS words and funnel-shifts
-// them into place (v_alignbyte); other shapes assemble byte by byte.
+// them into place (v_alignbyte); other shapes assemble byte by byte.  Block 0
+// also clears the launch's ring and dense list counters, which the ring
+// kernel after it fills.
 #include "riann_internal.h"
 
 namespace riann {
@@ -76,6 +78,7 @@ __device__ __forceinline__ ExtTile load_tile(const DevIndex &ix, const FrameBatc
 template <int DP>
 __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb, Work w) {
     extern __shared__ uint8_t s_tile[];
+    if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
     const int p = ix.p, C = ix.C, s = ix.s, D = ix.D;
     const ExtTile t = load_tile(ix, fb, s_tile);
     const FrameDesc &fa = *t.fa;
@@ -124,6 +127,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb
 template <int DP, int P, int C>
 __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBatch fb, Work w) {
     extern __shared__ __attribute__((aligned(16))) uint8_t s_tile[];
+    if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
     constexpr int PC = P * C, NW = PC / 4, D = P * PC;
     static_assert(PC % 4 == 0 && D <= DP, "whole-word window rows");
     const int s = ix.s;

@@ -176,18 +176,16 @@ __device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), m);
 }
 
-__global__ void k_zero_u32(uint32_t *p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 // ---------------------------------------------------------------- k_ring
 // One lane per query.  Each block first copies into LDS (at most 64 KB): the
 // binary-search samples of all K lists, each key's bucket-count row and the
 // key rows with their Rc.  Then, per query:
 //  1. every key's ring-size bounds [lb_k, ub_k] from its bucket counts, with
 //     an inner and an outer fp32 approximation of the ring (no exact square
-//     root yet); the seed key is the smallest lb (lowest k on ties);
+//     root yet); the seed key is the smallest lb (lowest k on ties).  If
+//     that lb is above the routing threshold, every ring holds more than the
+//     threshold's candidates: the query goes to the dense list with no exact
+//     ring (unless the index asks for every query's exact m*);
 //  2. the seed's exact ring: exact bounds, the LDS samples bracket the two
 //     positions, two line reads in global memory fix them;
 //  3. the remaining keys whose lower bound can still beat (m, k) -- chosen
@@ -197,7 +195,8 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
 //     sample bracket (ml, k) are below the best (m, k), and wins on a smaller
 //     size or an equal one at a lower index.
 // The result -- the exact smallest ring m*, its key k* (lowest on ties) and
-// its range -- is the same as evaluating every key exactly.
+// its range -- is the same as evaluating every key exactly; the routing
+// decision (m* <= threshold) is the same with or without step 1's shortcut.
 // List appends and statistics are aggregated per block: one atomic per list
 // and per counter per block.
 // Queries per block: 1024, or 512 for the variant that keeps the bounds of
@@ -213,7 +212,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     extern __shared__ __attribute__((aligned(16))) uint32_t s_samp[];
     __shared__ uint32_t s_wcnt[kWv][2];
     __shared__ uint32_t s_base[2];
-    __shared__ unsigned long long s_st[kWv][4];
+    __shared__ unsigned long long s_st[kWv][5];
     const int nsamp = ix.K * ix.ns;
     // 16-byte copies (the table is 256-byte aligned): four rounds for 64 KB
     for (int i = threadIdx.x; i < nsamp / 4; i += kBlk)
@@ -272,6 +271,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
         if (!noprior) c = cm;
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
+    bool by_bound = false;
     if (!full && !noprior && ix.K > 0) {
         const uint32_t *LB = s_samp + olb, *KR_ = s_samp + olk, *KC = s_samp + olc;
         const int B = ix.lbB, LS = ix.lbS;
@@ -304,54 +304,62 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
                 if (lb <= ubmin) cand |= 1ull << k;
             }
         }
-        // 2. the seed's exact ring
-        {
-            uint32_t lo1, hi1;
-            ring_bounds(b1, c, lo1, hi1);
-            const uint32_t *S = s_samp + k1 * ix.ns;
-            const int il = sample_count<false>(S, ix.ns, lo1);
-            const int ih = sample_count<true>(S, ix.ns, hi1);
-            const uint32_t *t = ix.T + (int64_t)k1 * ix.n16;
-            best_st = exact_pos<false>(il, t, nlines, ix.s0l, lo1);
-            best_en = exact_pos<true>(ih, t, nlines, ix.s0l, hi1);
-            best_m = best_en - best_st;
+        // every ring holds more than the threshold's candidates: the query
+        // goes dense whatever its exact m* (unless every m* is asked for)
+        by_bound = !ix.exact_mstar && (int64_t)lb1 > threshold;
+        if (by_bound) {
+            best_m = lb1;
             best_k = k1;
-        }
-        if constexpr (KR > 0) {
-            // keys whose lower bound can still beat (best_m, best_k)
+        } else {
+            // 2. the seed's exact ring
+            {
+                uint32_t lo1, hi1;
+                ring_bounds(b1, c, lo1, hi1);
+                const uint32_t *S = s_samp + k1 * ix.ns;
+                const int il = sample_count<false>(S, ix.ns, lo1);
+                const int ih = sample_count<true>(S, ix.ns, hi1);
+                const uint32_t *t = ix.T + (int64_t)k1 * ix.n16;
+                best_st = exact_pos<false>(il, t, nlines, ix.s0l, lo1);
+                best_en = exact_pos<true>(ih, t, nlines, ix.s0l, hi1);
+                best_m = best_en - best_st;
+                best_k = k1;
+            }
+            if constexpr (KR > 0) {
+                // keys whose lower bound can still beat (best_m, best_k)
 #pragma unroll
-            for (int k = 0; k < KR; ++k)
-                if (lbv[k] < best_m || (lbv[k] == best_m && (uint32_t)k < best_k))
-                    cand |= 1ull << k;
-        }
-        cand &= ~(1ull << k1);
-        // 3. each lane takes its own remaining keys in turn (the wavefront
-        //    loops as often as its busiest lane needs): a key is searched
-        //    only if its bounds can still beat (best_m, best_k), and wins on
-        //    a smaller size or an equal size at a lower index
-        while (__ballot(cand != 0)) {
-            if (cand == 0) continue;
-            const int k = __builtin_ctzll(cand);
-            cand &= cand - 1;
-            uint32_t lo, hi;
-            ring_bounds(key_dist<DP>(a, Qc, KR_, KC, k), c, lo, hi);
-            uint32_t lb, ub;
-            ring_size_bounds(LB + k * LS, B, lo, hi, lo, hi, lb, ub);
-            if (lb > best_m || (lb == best_m && (uint32_t)k > best_k)) continue;
-            const uint32_t *S = s_samp + k * ix.ns;
-            const int il = sample_count<false>(S, ix.ns, lo);
-            const int ih = sample_count<true>(S, ix.ns, hi);
-            uint32_t sl, sh, el, eh;
-            pos_bracket(il, ix.ns, ix.s0l, n, sl, sh);
-            pos_bracket(ih, ix.ns, ix.s0l, n, el, eh);
-            const uint32_t ml = el > sh ? el - sh : 0u;
-            if (ml > best_m || (ml == best_m && (uint32_t)k > best_k)) continue;
-            const uint32_t *t = ix.T + (int64_t)k * ix.n16;
-            const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo);
-            const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi);
-            const uint32_t m = en - st;
-            if (m < best_m || (m == best_m && (uint32_t)k < best_k)) {
-                best_m = m; best_k = (uint32_t)k; best_st = st; best_en = en;
+                for (int k = 0; k < KR; ++k)
+                    if (lbv[k] < best_m || (lbv[k] == best_m && (uint32_t)k < best_k))
+                        cand |= 1ull << k;
+            }
+            cand &= ~(1ull << k1);
+            // 3. each lane takes its own remaining keys in turn (the wavefront
+            //    loops as often as its busiest lane needs): a key is searched
+            //    only if its bounds can still beat (best_m, best_k), and wins on
+            //    a smaller size or an equal size at a lower index
+            while (__ballot(cand != 0)) {
+                if (cand == 0) continue;
+                const int k = __builtin_ctzll(cand);
+                cand &= cand - 1;
+                uint32_t lo, hi;
+                ring_bounds(key_dist<DP>(a, Qc, KR_, KC, k), c, lo, hi);
+                uint32_t lb, ub;
+                ring_size_bounds(LB + k * LS, B, lo, hi, lo, hi, lb, ub);
+                if (lb > best_m || (lb == best_m && (uint32_t)k > best_k)) continue;
+                const uint32_t *S = s_samp + k * ix.ns;
+                const int il = sample_count<false>(S, ix.ns, lo);
+                const int ih = sample_count<true>(S, ix.ns, hi);
+                uint32_t sl, sh, el, eh;
+                pos_bracket(il, ix.ns, ix.s0l, n, sl, sh);
+                pos_bracket(ih, ix.ns, ix.s0l, n, el, eh);
+                const uint32_t ml = el > sh ? el - sh : 0u;
+                if (ml > best_m || (ml == best_m && (uint32_t)k > best_k)) continue;
+                const uint32_t *t = ix.T + (int64_t)k * ix.n16;
+                const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo);
+                const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi);
+                const uint32_t m = en - st;
+                if (m < best_m || (m == best_m && (uint32_t)k < best_k)) {
+                    best_m = m; best_k = (uint32_t)k; best_st = st; best_en = en;
+                }
             }
         }
     }
@@ -381,19 +389,21 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
 
     // ---- statistics: wave sums, then one atomic per counter per block
     // full-search frames count as queries and dense queries only
-    const unsigned long long v0 = wave_sum_u64(valid && !full ? best_m : 0);
+    const unsigned long long v0 = wave_sum_u64(valid && !full && !by_bound ? best_m : 0);
     const unsigned long long v1 = wave_sum_u64(valid && !full && noprior ? 1 : 0);
+    const unsigned long long bmask = __ballot(valid && by_bound);
     if (lane == 0) {
         s_st[wv][0] = v0;
         s_st[wv][1] = v1;
         s_st[wv][2] = (unsigned long long)__popcll(rmask);
         s_st[wv][3] = (unsigned long long)__popcll(dmask);
+        s_st[wv][4] = (unsigned long long)__popcll(bmask);
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < 5) {
         unsigned long long tot = 0;
         for (int i = 0; i < kWv; ++i) tot += s_st[i][threadIdx.x];
-        const int slot[4] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE};
+        const int slot[5] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE, ST_BOUND};
         if (tot) atomicAdd(&stats[slot[threadIdx.x]], tot);
         if (threadIdx.x == 3) {
             const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)blockIdx.x * kBlk);
@@ -635,11 +645,6 @@ hipError_t launch_scan_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
 }
 
 }  // namespace
-
-hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
-    return hipGetLastError();
-}
 
 #define RIANN_DP_SWITCH(DPV, CALL)                 \
     switch (DPV) {                                 \

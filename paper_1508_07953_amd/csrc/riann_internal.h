@@ -93,6 +93,7 @@ struct DevIndex {
     int32_t s0l;          // sample stride in 16-entry lines
     int32_t Kp;           // Piv row stride
     int32_t lbB, lbS;     // lower-bound buckets per key, row stride in words
+    int32_t exact_mstar;  // 1: every ring-phase query's smallest ring is evaluated
 };
 
 // One frame of a launch.  A launch takes up to kMaxBatch frames of any sizes;
@@ -146,10 +147,9 @@ struct Work {
 // device stats block (uint64 counters, same order as riann_stats_t after `frames`)
 enum StatSlot {
     ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING,
-    ST_COUNT
+    ST_BOUND, ST_COUNT
 };
 
-hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
 hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                           hipStream_t st);
 hipError_t launch_ring(const DevIndex &ix, const FrameBatch &fb, const Work &w,

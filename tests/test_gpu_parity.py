@@ -55,7 +55,8 @@ def test_tiny_sequence_exact_and_stats(torch_dev, riann):
     torch, dev = torch_dev
     print_case("tiny sequence")
     wl = gen.make_workload("tiny")
-    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1,
+                            flags=riann.FLAG_EXACT_MSTAR)
     tabs = oracle.Tables(wl.ref, wl.keys)
     thr = idx.params.dense_threshold
     prev = None
@@ -89,6 +90,7 @@ def test_tiny_sequence_exact_and_stats(torch_dev, riann):
     assert st["sum_survivors"] == want["surv"]
     assert st["sum_mstar_ring"] == want["mstar_ring"]
     assert st["no_prior"] == want["noprior"]
+    assert st["bound_routed"] == 0
     idx.close()
 
 
@@ -687,4 +689,55 @@ def test_ring_stats_both_paths(torch_dev, riann, p, C, K, n):
     assert st["ring_queries"] == int(ring.sum())
     assert st["sum_survivors"] == int(o["nsurv"][ring].sum())
     assert st["no_prior"] == int(o["noprior"].sum())
+    assert st["bound_routed"] == 0          # threshold n: no ring bound exceeds it
     idx.close()
+
+
+@pytest.mark.parametrize("p,C,K,n", [(8, 1, 16, 1500), (8, 3, 32, 1300)])
+@pytest.mark.parametrize("thr", [0, 8, 64, 300])
+def test_bound_routing_keeps_routing(torch_dev, riann, p, C, K, n, thr):
+    """By default a query whose ring-size lower bounds all exceed the
+    threshold goes dense without its exact m*.  The field, the ring/dense
+    split, the ring-scanned m* and survivor sums stay exactly the oracle's;
+    the m* left out of the sum belong to bound-routed queries, each above the
+    threshold.  With the exact-m* flag nothing is bound-routed and the sum is
+    the oracle's."""
+    torch, dev = torch_dev
+    print_case(f"bound routing p={p} C={C} K={K} n={n} thr={thr}")
+    rng = np.random.default_rng(7000 + 10 * K + thr)
+    H, W = 30, 41
+    base = rng.integers(0, 256, (H + 40, W + 40, C), dtype=np.uint8)
+    f = np.clip(base[2:H + 2, 1:W + 1].astype(np.int32) + rng.integers(-4, 5, (H, W, C)),
+                0, 255).astype(np.uint8)
+    R = oracle.extract(base, p, 1)
+    ref = R[np.sort(rng.choice(len(R), n, replace=False))]
+    keys = np.sort(rng.choice(n, K, replace=False))
+    P = oracle.extract(f, p, 1)
+    hq, wq = oracle.field_shape(H, W, p, 1)
+    prev = rng.integers(-1, n, (hq, wq)).astype(np.int32)
+    prev[::2] = oracle.brute_force(P, ref)[0].reshape(hq, wq)[::2]      # tight rings too
+    o = oracle.Tables(ref, keys).riann(P, prev.reshape(-1))
+    ring = (o["mstar"] <= thr) & (o["noprior"] == 0)
+    total = int(o["mstar"].sum())
+    for flags in (0, riann.FLAG_EXACT_MSTAR):
+        idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=1, dense_threshold=thr,
+                                flags=flags)
+        out, ssd = idx.match_frame(to_dev(torch, dev, f), prev=to_dev(torch, dev, prev))
+        torch.cuda.synchronize()
+        check_exact(out, ssd, P, ref, f"bound routing flags={flags}")
+        st = idx.stats()
+        assert st["ring_queries"] == int(ring.sum())
+        assert st["dense_queries"] == len(P) - int(ring.sum())
+        assert st["sum_mstar_ring"] == int(o["mstar"][ring].sum())
+        assert st["sum_survivors"] == int(o["nsurv"][ring].sum())
+        assert st["no_prior"] == int(o["noprior"].sum())
+        b = st["bound_routed"]
+        if flags:
+            assert b == 0 and st["sum_mstar"] == total
+        else:
+            assert b <= st["dense_queries"] - st["no_prior"]
+            assert total - st["sum_mstar"] >= (thr + 1) * b
+            assert (b == 0) == (st["sum_mstar"] == total)
+            if thr == 0:
+                assert b > 0                # the shortcut is taken
+        idx.close()
