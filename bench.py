@@ -366,7 +366,9 @@ def main():
         torch.cuda.synchronize()
     idx.reset_stats()
     if not args.no_profile:
-        idx.set_profiling(True)
+        # inside the timed region only the dense step carries event markers
+        # (the roofline figure); the other kernels are timed afterwards
+        idx.set_profiling("dense")
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(K)]
     torch.cuda.synchronize()
@@ -383,6 +385,17 @@ def main():
     prof = idx.profile() if not args.no_profile else None
     idx.set_profiling(False)
     st = idx.stats()
+    prof_all = None
+    if not args.no_profile:
+        # per-kernel breakdown: an untimed pass over the first timed frames
+        # again, every kernel bracketed by events
+        idx.set_profiling(True)
+        for i in range(min(K, 10)):
+            step(W + 1 + i)
+            cur = 1 - cur
+        prof_all = idx.profile()
+        idx.set_profiling(False)
+        torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
 
     result = {
@@ -428,34 +441,36 @@ def main():
                               "ms_per_launch": ms_per_launch,
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
-                                          for k, v in prof.items() if v["launches"]}
+                                          for k, v in prof_all.items() if v["launches"]}
+        result["kernels_note"] = ("dense: HIP events in the timed region; every kernel: an "
+                                  "untimed pass over 10 of the frames after it")
         # the other per-frame kernels against the HBM roofline (algorithmic
         # bytes per frame; both are bound elsewhere, see the notes)
         Dp = (wl.D + 31) // 32 * 32
         sec = {}
-        if prof["ring"]["launches"]:
+        if prof_all["ring"]["launches"]:
             rb = Q * (Dp + 4 + 4 + wl.D + 16 + 4)
-            rms = prof["ring"]["ms"] / prof["ring"]["launches"]
+            rms = prof_all["ring"]["ms"] / prof_all["ring"]["launches"]
             sec["k_ring"] = {"bound": "alu", "algorithmic_bytes": rb, "ms": rms,
                              "GBps": rb / (rms * 1e-3) / 1e9, "hbm_frac": rb / (rms * 1e-3) / 1e9
                              / HBM_PEAK_GBS,
                              "note": "patch, Qc, prev, r_prev row, record and list entry per "
                                      "query; VALU-bound (key distances and binary searches)"}
-        if prof["extract"]["launches"]:
+        if prof_all["extract"]["launches"]:
             eb = H * Wd * wl.channels + Q * (Dp + 4 + 1)
-            ems = prof["extract"]["ms"] / prof["extract"]["launches"]
+            ems = prof_all["extract"]["ms"] / prof_all["extract"]["launches"]
             sec["k_extract"] = {"bound": "hbm", "algorithmic_bytes": eb, "ms": ems,
                                 "GBps": eb / (ems * 1e-3) / 1e9,
                                 "hbm_frac": eb / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "note": "frame read once, encoded patch + Qc + frame id written"}
-        if prof["scan"]["launches"] and st["ring_queries"]:
+        if prof_all["scan"]["launches"] and st["ring_queries"]:
             # ring-routed queries: record, list entry, patch, Qc read and the
             # match written; the smallest ring's P entries and pivot rows; the
             # survivors' rows (device counters, summed over the timed frames)
             Kp = (len(wl.keys) + 3) // 4 * 4
             sb = (st["ring_queries"] * (16 + 4 + Dp + 4 + 8) +
                   st["sum_mstar_ring"] * (4 + 4 * Kp) + st["sum_survivors"] * Dp) / K
-            sms = prof["scan"]["ms"] / prof["scan"]["launches"]
+            sms = prof_all["scan"]["ms"] / prof_all["scan"]["launches"]
             sec["k_scan"] = {"bound": "hbm", "algorithmic_bytes": sb, "ms": sms,
                              "GBps": sb / (sms * 1e-3) / 1e9,
                              "hbm_frac": sb / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -345,10 +345,14 @@ riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out
 riann_status_t riann_destroy(riann_index_t h);
 
 /*
- * Kernel timing (diagnostics).  While enabled, every kernel the index
- * launches is bracketed by two HIP events recorded on the launch stream;
- * riann_get_profile synchronises, converts the pending event pairs into
- * milliseconds and returns the totals per kernel since profiling was enabled.
+ * Kernel timing (diagnostics).  riann_set_profiling(h, level): 0 turns it off;
+ * RIANN_PROFILE_ALL brackets every kernel the index launches by two HIP
+ * events recorded on the launch stream; RIANN_PROFILE_DENSE brackets only the
+ * dense search (RIANN_K_DENSE, RIANN_K_FULL), which keeps the markers out of
+ * the rest of a frame.  Turning it on resets the totals; other levels return
+ * RIANN_E_INVALID.  riann_get_profile synchronises, converts the pending event
+ * pairs into milliseconds and returns the totals per kernel since profiling
+ * was turned on.  Events are reused across calls.
  * Kernels: RIANN_K_RING (ring phase), RIANN_K_SCAN (ring scan and
  * verification), RIANN_K_DENSE (dense search of routed queries),
  * RIANN_K_FULL (dense search of whole frames), RIANN_K_EXTRACT (patch
@@ -360,6 +364,8 @@ riann_status_t riann_destroy(riann_index_t h);
 #define RIANN_K_FULL 3
 #define RIANN_K_EXTRACT 4
 #define RIANN_K_COUNT 5
+#define RIANN_PROFILE_ALL 1
+#define RIANN_PROFILE_DENSE 2
 typedef struct riann_profile {
     uint64_t launches[RIANN_K_COUNT];
     double ms[RIANN_K_COUNT];

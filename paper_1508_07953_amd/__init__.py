@@ -31,6 +31,7 @@ RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, R
 MODE_RING, MODE_FULL = 0, 1
 FLAG_COLUMN_DENSE = 1
 FLAG_EXACT_MSTAR = 2
+PROFILE_ALL, PROFILE_DENSE = 1, 2
 
 # every symbol include/riann.h declares
 EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match_batch",
@@ -375,8 +376,11 @@ class Index:
         _check(_lib.riann_set_dense_threshold(self._h, int(threshold)))
         self.params.dense_threshold = int(threshold)
 
-    def set_profiling(self, enable: bool) -> None:
-        _check(_lib.riann_set_profiling(self._h, 1 if enable else 0))
+    def set_profiling(self, enable=True) -> None:
+        """True: time every kernel; "dense": only the dense search; False: off.
+        Turning it on resets the totals."""
+        level = PROFILE_DENSE if enable == "dense" else (PROFILE_ALL if enable else 0)
+        _check(_lib.riann_set_profiling(self._h, level))
 
     def profile(self) -> dict:
         """Per-kernel launch counts and total milliseconds (HIP events)."""

@@ -41,10 +41,11 @@ struct riann_index {
     void *paper_mem = nullptr;   // Dm | T | P of the paper's search, n x n each
     std::mutex paper_mu;
     // kernel timing (riann_set_profiling)
-    std::atomic<bool> profiling{false};
+    std::atomic<int> profiling{0};   // 0, RIANN_PROFILE_ALL or RIANN_PROFILE_DENSE
     std::mutex pmu;
     struct Pending { int kind; hipEvent_t a, b; };
     std::vector<Pending> pending;
+    std::vector<hipEvent_t> evpool;  // read events, ready to be recorded again
     uint64_t prof_launches[RIANN_K_COUNT] = {};
     double prof_ms[RIANN_K_COUNT] = {};
 };
@@ -359,6 +360,7 @@ void free_index(riann_index *h) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
+    for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
     for (auto &kv : h->work) (void)hipFree(kv.second.patches);
     for (auto &kv : h->recon_scratch) (void)hipFree(kv.second.first);
     if (h->paper_mem) (void)hipFree(h->paper_mem);
@@ -455,17 +457,34 @@ struct KTimer {
     hipStream_t st;
     hipEvent_t a = nullptr;
     KTimer(riann_index *h_, int kind_, hipStream_t st_) : h(h_), kind(kind_), st(st_) {
-        if (!h->profiling.load()) return;
-        if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
-        (void)hipEventRecord(a, st);
+        const int lv = h->profiling.load();
+        if (lv == 0) return;
+        if (lv == RIANN_PROFILE_DENSE && kind != RIANN_K_DENSE && kind != RIANN_K_FULL) return;
+        a = take();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    hipEvent_t take() {
+        {
+            std::lock_guard<std::mutex> lk(h->pmu);
+            if (!h->evpool.empty()) {
+                hipEvent_t e = h->evpool.back();
+                h->evpool.pop_back();
+                return e;
+            }
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
     }
     void stop() {
         if (!a) return;
-        hipEvent_t b = nullptr;
-        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); a = nullptr; return; }
-        (void)hipEventRecord(b, st);
+        hipEvent_t b = take();
         std::lock_guard<std::mutex> lk(h->pmu);
-        h->pending.push_back({kind, a, b});
+        if (!b) {
+            h->evpool.push_back(a);
+        } else {
+            (void)hipEventRecord(b, st);
+            h->pending.push_back({kind, a, b});
+        }
         a = nullptr;
     }
 };
@@ -820,7 +839,25 @@ riann_status_t riann_load(const char *path, void *hip_stream, riann_index_t *out
 
 riann_status_t riann_set_profiling(riann_index_t h, int enable) {
     if (!h) return fail(RIANN_E_INVALID, "index is NULL");
-    h->profiling.store(enable != 0);
+    if (enable != 0 && enable != RIANN_PROFILE_ALL && enable != RIANN_PROFILE_DENSE)
+        return fail(RIANN_E_INVALID, "profiling level must be 0, RIANN_PROFILE_ALL or RIANN_PROFILE_DENSE");
+    if (enable != 0) {
+        // fresh totals; events still pending belong to the old ones
+        DeviceGuard g(h->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "device sync");
+        std::lock_guard<std::mutex> lk(h->pmu);
+        for (auto &p : h->pending) {
+            h->evpool.push_back(p.a);
+            h->evpool.push_back(p.b);
+        }
+        h->pending.clear();
+        for (int k = 0; k < RIANN_K_COUNT; ++k) {
+            h->prof_launches[k] = 0;
+            h->prof_ms[k] = 0.0;
+        }
+    }
+    h->profiling.store(enable);
     return RIANN_OK;
 }
 
@@ -836,8 +873,8 @@ riann_status_t riann_get_profile(riann_index_t h, riann_profile_t *out) {
             h->prof_ms[p.kind] += ms;
             h->prof_launches[p.kind] += 1;
         }
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
+        h->evpool.push_back(p.a);
+        h->evpool.push_back(p.b);
     }
     h->pending.clear();
     for (int k = 0; k < RIANN_K_COUNT; ++k) {

@@ -254,6 +254,36 @@ def test_errors(torch_dev, riann):
     idx.close()
 
 
+def test_profiling_levels(torch_dev, riann):
+    """Every kernel is timed at the full level, only the dense search at the
+    dense level; turning profiling on resets the totals; other levels are
+    rejected; results are unchanged while timing."""
+    torch, dev = torch_dev
+    print_case("profiling levels")
+    wl = gen.make_workload("tiny")
+    idx = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1)
+    f0, f1 = wl.frame(0), wl.frame(1)
+    d0, d1 = to_dev(torch, dev, f0), to_dev(torch, dev, f1)
+    idx.set_profiling(True)
+    o0, _ = idx.full_search(d0)
+    o1, s1 = idx.match_frame(d1, prev=o0)
+    p = idx.profile()
+    assert all(p[k]["launches"] == 1 for k in ("ring", "scan", "dense", "full")), p
+    assert p["extract"]["launches"] == 2, p
+    assert all(p[k]["ms"] > 0 for k in ("dense", "full", "extract")), p
+    idx.set_profiling("dense")
+    idx.match_frame(d1, prev=o0)
+    idx.full_search(d0)
+    p = idx.profile()
+    assert p["dense"]["launches"] == 1 and p["full"]["launches"] == 1, p
+    assert all(p[k]["launches"] == 0 for k in ("ring", "scan", "extract")), p
+    idx.set_profiling(False)
+    assert riann.lib().riann_set_profiling(idx._h, 7) == riann.RIANN_E_INVALID
+    torch.cuda.synchronize()
+    check_exact(o1, s1, oracle.extract(f1, 8, 1), wl.ref, "profiled frame")
+    idx.close()
+
+
 def test_save_load_roundtrip(torch_dev, riann):
     torch, dev = torch_dev
     print_case("save/load")
