@@ -349,8 +349,8 @@ riann_status_t riann_destroy(riann_index_t h);
  * RIANN_PROFILE_ALL brackets every kernel the index launches by two HIP
  * events recorded on the launch stream; RIANN_PROFILE_DENSE brackets only the
  * dense search (RIANN_K_DENSE, RIANN_K_FULL), which keeps the markers out of
- * the rest of a frame.  Turning it on resets the totals; other levels return
- * RIANN_E_INVALID.  riann_get_profile synchronises, converts the pending event
+ * the rest of a frame.  Turning it on synchronises the device and resets the
+ * totals; other levels return RIANN_E_INVALID.  riann_get_profile synchronises, converts the pending event
  * pairs into milliseconds and returns the totals per kernel since profiling
  * was turned on.  Events are reused across calls.
  * Kernels: RIANN_K_RING (ring phase), RIANN_K_SCAN (ring scan and
