@@ -141,12 +141,14 @@ __device__ __forceinline__ void ring_approx(uint32_t b, uint32_t c, uint32_t &lo
     const float sf = 2.0f * sqrtf((float)b * (float)c);
     const float si = floorf(sf * (1.0f - 0x1p-18f)) - 1.0f;
     const float so = ceilf(sf * (1.0f + 0x1p-18f)) + 1.0f;
-    const uint64_t s_in = si > 0.0f ? (uint64_t)si : 0ull, s_out = (uint64_t)so;
-    const uint64_t bc = (uint64_t)b + c;
-    lo_in = b <= c ? 0u : (uint32_t)(bc - min(s_in, bc));
-    hi_in = (uint32_t)min<uint64_t>(bc + s_in, 0xFFFFFFFFull);
-    lo_out = b <= c ? 0u : (uint32_t)(bc - min(s_out, bc));
-    hi_out = (uint32_t)min<uint64_t>(bc + s_out, 0xFFFFFFFFull);
+    // b, c are SSDs (< 2^24): s <= 2^25 + 2 and every end below 2^27, so the
+    // arithmetic stays in 32 bits
+    const uint32_t s_in = si > 0.0f ? (uint32_t)si : 0u, s_out = (uint32_t)so;
+    const uint32_t bc = b + c;
+    lo_in = b <= c ? 0u : bc - min(s_in, bc);
+    hi_in = bc + s_in;
+    lo_out = b <= c ? 0u : bc - min(s_out, bc);
+    hi_out = bc + s_out;
 }
 
 // Bounds on the number of key-list entries inside the exact ring from the
@@ -155,18 +157,21 @@ __device__ __forceinline__ void ring_approx(uint32_t b, uint32_t c, uint32_t &lo
 __device__ __forceinline__ void ring_size_bounds(const uint32_t *row, int B, uint32_t lo_in,
                                                  uint32_t hi_in, uint32_t lo_out, uint32_t hi_out,
                                                  uint32_t &lb, uint32_t &ub) {
+    // ring ends are below 2^27 and the bucket shift is at most 24 (a key's
+    // distances span less than 2^24), so 32-bit arithmetic is exact
     const uint32_t vmin = row[0], sh = row[1];
-    const uint64_t w = 1ull << sh;
+    const uint32_t wm = (1u << sh) - 1u;
     // entries below vmin + d: d from the interval's ends
-    auto below = [&](uint32_t v, bool incl) -> uint64_t {
-        return v >= vmin ? (uint64_t)(v - vmin) + (incl ? 1ull : 0ull) : 0ull;
+    auto below = [&](uint32_t v, bool incl) -> uint32_t {
+        return v >= vmin ? v - vmin + (incl ? 1u : 0u) : 0u;
     };
-    const uint64_t dli = below(lo_in, false), dhi = below(hi_in, true);
-    const uint64_t dlo = below(lo_out, false), dho = below(hi_out, true);
-    const uint32_t jl_in = (uint32_t)min<uint64_t>((uint64_t)B, (dli + w - 1) >> sh);
-    const uint32_t jh_in = (uint32_t)min<uint64_t>((uint64_t)B, dhi >> sh);
-    const uint32_t jl_out = (uint32_t)min<uint64_t>((uint64_t)B, dlo >> sh);
-    const uint32_t jh_out = (uint32_t)min<uint64_t>((uint64_t)B, (dho + w - 1) >> sh);
+    const uint32_t dli = below(lo_in, false), dhi = below(hi_in, true);
+    const uint32_t dlo = below(lo_out, false), dho = below(hi_out, true);
+    const uint32_t ub_ = (uint32_t)B;
+    const uint32_t jl_in = min(ub_, (dli + wm) >> sh);
+    const uint32_t jh_in = min(ub_, dhi >> sh);
+    const uint32_t jl_out = min(ub_, dlo >> sh);
+    const uint32_t jh_out = min(ub_, (dho + wm) >> sh);
     lb = jh_in > jl_in ? row[2 + jh_in] - row[2 + jl_in] : 0u;
     ub = jh_out > jl_out ? row[2 + jh_out] - row[2 + jl_out] : 0u;
 }
