@@ -131,9 +131,14 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
     constexpr int PC = P * C, NW = PC / 4, D = P * PC;
     static_assert(PC % 4 == 0 && D <= DP, "whole-word window rows");
     const int s = ix.s;
+    // 64-byte patches: each row of the tile is staged here and leaves as whole
+    // contiguous kilobytes (four 16-byte stores per lane, lanes adjacent)
+    constexpr bool kStage = DP == 64;
+    __shared__ __attribute__((aligned(16))) uint4 s_out[kStage ? kTY * kTX * (DP / 16) : 1];
     const ExtTile t = load_tile(ix, fb, s_tile);
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    if (tx >= t.nqx || ty >= t.nqy) return;
+    const bool valid = tx < t.nqx && ty < t.nqy;
+    if (!kStage && !valid) return;
     const uint32_t *words = reinterpret_cast<const uint32_t *>(s_tile);
     const int base = (ty * s) * t.ldw + (tx * s) * C;
     uint32_t wd[DP / 4];
@@ -157,11 +162,30 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
 #pragma unroll
     for (int i = D / 4; i < DP / 4; ++i) wd[i] = 0u;
     const FrameDesc &fa = *t.fa;
-    const int64_t q = fa.qbase + (int64_t)(t.qy0 + ty) * fa.Wq + (t.qx0 + tx);
-    uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
+    const int64_t q0 = fa.qbase + (int64_t)(t.qy0 + ty) * fa.Wq + t.qx0;   // row's first query
+    const int64_t q = q0 + tx;
+    if constexpr (kStage) {
+        constexpr int PW = DP / 16;               // 16-byte words per patch
+        uint4 *row = s_out + ty * (kTX * PW);
 #pragma unroll
-    for (int i = 0; i < DP / 16; ++i)
-        dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
+        for (int i = 0; i < PW; ++i)
+            row[tx * PW + i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
+        __syncthreads();
+        if (ty < t.nqy) {
+            uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q0 * DP);
+#pragma unroll
+            for (int i = 0; i < PW; ++i) {
+                const int g = i * kTX + tx;           // word g of the row: patch g / PW
+                if (g / PW < t.nqx) dst[g] = row[g];
+            }
+        }
+        if (!valid) return;
+    } else {
+        uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
+#pragma unroll
+        for (int i = 0; i < DP / 16; ++i)
+            dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
+    }
     w.qc[q] = sa2 + 2 * sa + D;
     w.fid[q] = (uint8_t)t.f;
 }
