@@ -12,7 +12,7 @@ Frames are CUDA (HIP) uint8 tensors of shape (H, W) or (H, W, C); fields are
 int32 (Hq, Wq) with Hq = (H - p) // s + 1, Wq = (W - p) // s + 1.
 
 The library must be built (``__graft_entry__.build()`` or
-``python -m paper_1508_07953_amd._build``); importing this package without it
+``python paper_1508_07953_amd/_build.py``); importing this package without it
 raises ImportError -- there is no fallback implementation.
 """
 from __future__ import annotations
