@@ -133,6 +133,14 @@ typedef struct riann_stats {
     uint64_t bound_routed;     /* ring-phase queries sent to the dense search
                                   by their ring-size lower bounds alone, m*
                                   not evaluated (0 with RIANN_FLAG_EXACT_MSTAR) */
+    uint64_t dense_routed;     /* ring-phase queries routed to the dense search
+                                  (dense_queries without the queries of
+                                  full-search frames)                          */
+    uint64_t bsearch_probes;   /* sorted-table reads of the ring phase's binary
+                                  searches (Sec. 3.3: a ring costs two
+                                  O(log n) searches): one per LDS sample probed,
+                                  per line start probed in device memory and per
+                                  64-byte line counted                         */
 } riann_stats_t;
 
 /*
@@ -203,9 +211,10 @@ riann_status_t riann_match_batch(riann_index_t h, const riann_frame_desc_t *desc
                                  int32_t n, void *hip_stream);
 
 /*
- * riann_match_knn -- exact k-nearest-neighbour field of one frame (the k-NN
- * extension the paper lists as future work, Sec. 6): for every query the k
- * references with the smallest (SSD, index), in ascending order.
+ * riann_match_knn -- exact k-nearest-neighbour field of one frame (the
+ * Conclusion, Sec. 7, states that the method can return several closest
+ * matches instead of one): for every query the k references with the
+ * smallest (SSD, index), in ascending order.
  *   k       1..8; k <= n.  k = 1 is riann_match_frame / riann_full_search.
  *   prev    RING mode: device Hq x Wq x k, the previous frame's k-NN field, or
  *           NULL.  The ring radius is the largest SSD from the query to its k

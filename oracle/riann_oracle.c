@@ -103,11 +103,13 @@ void orc_extract(const uint8_t *frame, int H, int W, int C, int64_t pitch,
 
 uint64_t orc_ssd(const uint8_t *a, const uint8_t *b, int D)
 {
-    int64_t s = 0;
-    for (int i = 0; i < D; ++i) {
-        int64_t d = (int64_t)a[i] - (int64_t)b[i];
-        if (g_fault == 2 && i == D - 1) break;          /* dropped term */
-        s += d * d;
+    /* every term is at most 255^2 = 65025, so the sum is exact in 32 bits
+     * for D < 66051, far above any patch here */
+    const int terms = (g_fault == 2) ? D - 1 : D;        /* planted: dropped term */
+    uint32_t s = 0;
+    for (int i = 0; i < terms; ++i) {
+        const int32_t d = (int32_t)a[i] - (int32_t)b[i];
+        s += (uint32_t)(d * d);
     }
     return (uint64_t)s;
 }
@@ -469,10 +471,13 @@ void orc_paper(const uint8_t *qp, int64_t Q, const uint8_t *ref, int64_t n, int 
             used[e] = 1;
             ++it;
             const int64_t rk = S[e];
-            const uint64_t ck = orc_ssd(q, ref + rk * D, D);
+            /* the anchor's ring: radius d_k = dist(q, r_k), distances from r_k */
+            const uint64_t ck = (g_fault == 12) ? c                  /* planted: radius d_i */
+                                                : orc_ssd(q, ref + rk * D, D);
+            const int64_t rrow = (g_fault == 13) ? ri : rk;          /* planted: r_i's row */
             int64_t m2 = 0;
             for (int64_t f = 0; f < m; ++f)
-                if (orc_in_fat_ring(dm[rk * n + S[f]], ck)) {
+                if (orc_in_fat_ring(dm[rrow * n + S[f]], ck)) {
                     S2[m2] = S[f];
                     used2[m2] = used[f];
                     ++m2;
@@ -580,13 +585,14 @@ void orc_extract3d(const uint8_t *const *frames, int T, int H, int W, int C, int
 /* ------------------------------------------------------------------ */
 /* field: hq x wq match indices; app: n x (p*p*Ca) appearance patches in
  * (dy, dx, c) order (the references themselves, or their transformed
- * versions).  Outputs per pixel of the H x W x Ca frame: the sum of the
+ * versions).  A field entry outside [0, n) names no reference and
+ * contributes no patch.  Outputs per pixel of the H x W x Ca frame: the sum of the
  * covering patches' values and how many patches cover it; f_R = sum / count
  * as float32 (0 where nothing covers).  If gt (H x W x Ca, row pitch
  * W*Ca) is given, err[0] = E, err[1] = sum (gt - f_R)^2, err[2] = sum gt^2,
  * err[3] = number of covered values, all over covered pixels only. */
-void orc_reconstruct(const int32_t *field, int hq, int wq, const uint8_t *app, int p, int Ca,
-                     int s, int H, int W, uint32_t *sum, uint32_t *count, float *fr,
+void orc_reconstruct(const int32_t *field, int hq, int wq, const uint8_t *app, int64_t n, int p,
+                     int Ca, int s, int H, int W, uint32_t *sum, uint32_t *count, float *fr,
                      const uint8_t *gt, double *err)
 {
     const int64_t npx = (int64_t)H * W;
@@ -594,7 +600,9 @@ void orc_reconstruct(const int32_t *field, int hq, int wq, const uint8_t *app, i
     memset(count, 0, sizeof(uint32_t) * npx);
     for (int i = 0; i < hq; ++i)
         for (int j = 0; j < wq; ++j) {
-            const uint8_t *patch = app + (int64_t)field[(int64_t)i * wq + j] * p * p * Ca;
+            const int64_t r = field[(int64_t)i * wq + j];
+            if (r < 0 || r >= n) continue;
+            const uint8_t *patch = app + r * p * p * Ca;
             for (int dy = 0; dy < p; ++dy)
                 for (int dx = 0; dx < p; ++dx) {
                     const int64_t px = (int64_t)(s * i + dy) * W + (s * j + dx);

@@ -68,7 +68,8 @@ class Profile(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in
                 ("frames", "queries", "ring_queries", "dense_queries", "no_prior",
-                 "sum_mstar", "sum_survivors", "sum_mstar_ring", "bound_routed")]
+                 "sum_mstar", "sum_survivors", "sum_mstar_ring", "bound_routed",
+                 "dense_routed", "bsearch_probes")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -350,18 +351,35 @@ class Index:
                                       _stream_ptr(stream)))
         return out, err
 
+    def _batch_desc(self, it: dict) -> FrameDesc:
+        """Checks one batch item (the C ABI cannot see device buffer sizes)
+        and returns its descriptor."""
+        frame = it["frame"]
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        hq, wq = self.field_shape(H, W)
+        mode = int(it.get("mode", MODE_RING))
+        if mode not in (MODE_RING, MODE_FULL):
+            raise ValueError(f"mode must be MODE_RING or MODE_FULL, got {mode}")
+        out, ssd, prev = it["out"], it.get("ssd"), it.get("prev")
+        if prev is not None and mode != MODE_RING:
+            raise ValueError("prev is only taken in MODE_RING")
+        for name, t in (("out", out), ("ssd", ssd), ("prev", prev)):
+            if t is None:
+                continue
+            if (t.numel() != max(hq, 0) * max(wq, 0) or not t.is_contiguous()
+                    or t.element_size() != 4 or t.device != frame.device):
+                raise ValueError(f"{name} must be a contiguous 4-byte ({hq}, {wq}) tensor on "
+                                 f"the frame's device")
+        return FrameDesc(frame.data_ptr(), H, W, pitch,
+                         prev.data_ptr() if prev is not None else None, out.data_ptr(),
+                         ssd.data_ptr() if ssd is not None else None, mode, 0)
+
     def match_batch(self, items: List[dict], stream=None) -> None:
-        """items: dicts with frame, out, ssd (optional), prev (optional), mode."""
-        arr = (FrameDesc * len(items))()
-        for i, it in enumerate(items):
-            H, W, pitch = _frame_geom(it["frame"], self.params.channels)
-            prev = it.get("prev")
-            ssd = it.get("ssd")
-            arr[i] = FrameDesc(it["frame"].data_ptr(), H, W, pitch,
-                               prev.data_ptr() if prev is not None else None,
-                               it["out"].data_ptr(), ssd.data_ptr() if ssd is not None else None,
-                               int(it.get("mode", MODE_RING)), 0)
-        _check(_lib.riann_match_batch(self._h, arr, len(items), _stream_ptr(stream)))
+        """items: dicts with frame, out, ssd (optional), prev (optional, ring
+        mode only), mode.  Every item is checked before anything is launched."""
+        descs = [self._batch_desc(it) for it in items]
+        arr = (FrameDesc * len(descs))(*descs)
+        _check(_lib.riann_match_batch(self._h, arr, len(descs), _stream_ptr(stream)))
 
     def stats(self) -> dict:
         s = Stats()

@@ -559,7 +559,7 @@ const uint32_t kFileVersion = 1;
 
 extern "C" {
 
-uint32_t riann_version(void) { return (1u << 16) | 0u; }
+uint32_t riann_version(void) { return (1u << 16) | 1u; }
 
 const char *riann_last_error(void) { return g_err.c_str(); }
 
@@ -710,6 +710,8 @@ riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
     s->sum_survivors = v[ST_SURV];
     s->sum_mstar_ring = v[ST_MSTAR_RING];
     s->bound_routed = v[ST_BOUND];
+    s->dense_routed = v[ST_DENSE];
+    s->bsearch_probes = v[ST_PROBES];
     return RIANN_OK;
 }
 

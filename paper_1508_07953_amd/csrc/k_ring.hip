@@ -84,10 +84,12 @@ template <bool LE>
 __device__ __forceinline__ bool pred(uint32_t x, uint32_t v) { return LE ? x <= v : x < v; }
 
 template <bool LE>
-__device__ __forceinline__ int sample_count(const uint32_t *S, int ns, uint32_t v) {
+__device__ __forceinline__ int sample_count(const uint32_t *S, int ns, uint32_t v,
+                                            uint32_t &probes) {
     int lo = 0, len = ns;
     while (len > 0) {
         const int half = len >> 1;
+        ++probes;
         if (pred<LE>(S[lo + half], v)) { lo += half + 1; len -= half + 1; }
         else len = half;
     }
@@ -104,14 +106,16 @@ __device__ __forceinline__ void pos_bracket(int i, int ns, int s0l, uint32_t n, 
 
 template <bool LE>
 __device__ __forceinline__ uint32_t exact_pos(int i, const uint32_t *__restrict__ T, int nlines,
-                                              int s0l, uint32_t v) {
+                                              int s0l, uint32_t v, uint32_t &probes) {
     if (i == 0) return 0;
     int L = (i - 1) * s0l, H = min(i * s0l, nlines);
     while (H - L > 1) {
         const int mid = (L + H) >> 1;
+        ++probes;
         if (pred<LE>(T[16 * mid], v)) L = mid;
         else H = mid;
     }
+    ++probes;                                  // the 64-byte line read below
     const uint4 *line = reinterpret_cast<const uint4 *>(T + 16 * L);
     uint32_t cnt = 0;
 #pragma unroll
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     extern __shared__ __attribute__((aligned(16))) uint32_t s_samp[];
     __shared__ uint32_t s_wcnt[kWv][2];
     __shared__ uint32_t s_base[2];
-    __shared__ unsigned long long s_st[kWv][5];
+    __shared__ unsigned long long s_st[kWv][6];
     const int nsamp = ix.K * ix.ns;
     // 16-byte copies (the table is 256-byte aligned): four rounds for 64 KB
     for (int i = threadIdx.x; i < nsamp / 4; i += kBlk)
@@ -276,6 +280,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
         if (!noprior) c = cm;
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
+    uint32_t probes = 0;                      // sorted-table reads of the binary searches
     bool by_bound = false;
     if (!full && !noprior && ix.K > 0) {
         const uint32_t *LB = s_samp + olb, *KR_ = s_samp + olk, *KC = s_samp + olc;
@@ -321,11 +326,11 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
                 uint32_t lo1, hi1;
                 ring_bounds(b1, c, lo1, hi1);
                 const uint32_t *S = s_samp + k1 * ix.ns;
-                const int il = sample_count<false>(S, ix.ns, lo1);
-                const int ih = sample_count<true>(S, ix.ns, hi1);
+                const int il = sample_count<false>(S, ix.ns, lo1, probes);
+                const int ih = sample_count<true>(S, ix.ns, hi1, probes);
                 const uint32_t *t = ix.T + (int64_t)k1 * ix.n16;
-                best_st = exact_pos<false>(il, t, nlines, ix.s0l, lo1);
-                best_en = exact_pos<true>(ih, t, nlines, ix.s0l, hi1);
+                best_st = exact_pos<false>(il, t, nlines, ix.s0l, lo1, probes);
+                best_en = exact_pos<true>(ih, t, nlines, ix.s0l, hi1, probes);
                 best_m = best_en - best_st;
                 best_k = k1;
             }
@@ -351,16 +356,16 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
                 ring_size_bounds(LB + k * LS, B, lo, hi, lo, hi, lb, ub);
                 if (lb > best_m || (lb == best_m && (uint32_t)k > best_k)) continue;
                 const uint32_t *S = s_samp + k * ix.ns;
-                const int il = sample_count<false>(S, ix.ns, lo);
-                const int ih = sample_count<true>(S, ix.ns, hi);
+                const int il = sample_count<false>(S, ix.ns, lo, probes);
+                const int ih = sample_count<true>(S, ix.ns, hi, probes);
                 uint32_t sl, sh, el, eh;
                 pos_bracket(il, ix.ns, ix.s0l, n, sl, sh);
                 pos_bracket(ih, ix.ns, ix.s0l, n, el, eh);
                 const uint32_t ml = el > sh ? el - sh : 0u;
                 if (ml > best_m || (ml == best_m && (uint32_t)k > best_k)) continue;
                 const uint32_t *t = ix.T + (int64_t)k * ix.n16;
-                const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo);
-                const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi);
+                const uint32_t st = exact_pos<false>(il, t, nlines, ix.s0l, lo, probes);
+                const uint32_t en = exact_pos<true>(ih, t, nlines, ix.s0l, hi, probes);
                 const uint32_t m = en - st;
                 if (m < best_m || (m == best_m && (uint32_t)k < best_k)) {
                     best_m = m; best_k = (uint32_t)k; best_st = st; best_en = en;
@@ -397,18 +402,20 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     const unsigned long long v0 = wave_sum_u64(valid && !full && !by_bound ? best_m : 0);
     const unsigned long long v1 = wave_sum_u64(valid && !full && noprior ? 1 : 0);
     const unsigned long long bmask = __ballot(valid && by_bound);
+    const unsigned long long v5 = wave_sum_u64(valid ? probes : 0u);
     if (lane == 0) {
         s_st[wv][0] = v0;
         s_st[wv][1] = v1;
         s_st[wv][2] = (unsigned long long)__popcll(rmask);
         s_st[wv][3] = (unsigned long long)__popcll(dmask);
         s_st[wv][4] = (unsigned long long)__popcll(bmask);
+        s_st[wv][5] = v5;
     }
     __syncthreads();
-    if (threadIdx.x < 5) {
+    if (threadIdx.x < 6) {
         unsigned long long tot = 0;
         for (int i = 0; i < kWv; ++i) tot += s_st[i][threadIdx.x];
-        const int slot[5] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE, ST_BOUND};
+        const int slot[6] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE, ST_BOUND, ST_PROBES};
         if (tot) atomicAdd(&stats[slot[threadIdx.x]], tot);
         if (threadIdx.x == 3) {
             const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)blockIdx.x * kBlk);

@@ -147,7 +147,7 @@ struct Work {
 // device stats block (uint64 counters, same order as riann_stats_t after `frames`)
 enum StatSlot {
     ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING,
-    ST_BOUND, ST_COUNT
+    ST_BOUND, ST_PROBES, ST_COUNT
 };
 
 hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,

@@ -13,6 +13,11 @@ result is exact, so a stream's fields are the same alone and in any mix.
 
 `Server(..., max_batch=1, inflight=1)` is the plain mode: one frame at a time,
 each finished before the next starts.
+
+Frames may be device tensors or host tensors (pinned host memory for
+asynchronous copies).  Host frames are copied into the stream's device frame
+buffer on a copy stream of the server's own, so the copies of one batch
+overlap the search of the batch before it.
 """
 from __future__ import annotations
 
@@ -42,11 +47,14 @@ class Completion:
 
 
 class _Stream:
-    def __init__(self, sid, H, W, hq, wq, device, torch):
+    def __init__(self, sid, H, W, hq, wq, device, torch, channels):
         self.sid, self.H, self.W = sid, H, W
         self.fields = [torch.full((hq, wq), -1, dtype=torch.int32, device=device)
                        for _ in range(2)]
         self.ssd = [torch.empty((hq, wq), dtype=torch.int32, device=device) for _ in range(2)]
+        # device copy of the frame in flight when frames arrive in host memory
+        # (one buffer: a stream has at most one frame in flight)
+        self.dframe = torch.empty((H, W, channels), dtype=torch.uint8, device=device)
         self.cur = 0            # fields[cur] holds the latest finished field
         self.has_field = False
         self.seq = 0
@@ -78,26 +86,71 @@ class Server:
         self.device = device if device is not None else torch.device("cuda")
         self.hip_streams = [torch.cuda.Stream(device=self.device)
                             for _ in range(self.inflight if concurrent else 1)]
+        self.copy_stream = torch.cuda.Stream(device=self.device)
         self.budget = memory_budget
-        self.used = footprint(index.params.n_ref, index.params.n_keys, index.params.patch,
-                              index.params.channels, index.params.stride)
+        p = index.params
+        self._fp = (p.n_ref, p.n_keys, p.patch, p.channels, p.stride)
+        self.index_bytes = footprint(*self._fp)
+        self.used = self.index_bytes          # index + every active stream's buffers
         self.streams: Dict[int, _Stream] = {}
         self.waiting: Deque[Tuple[int, int, int]] = collections.deque()  # (sid, H, W)
         self._pending_queues: Dict[int, Deque] = {}   # frames of waiting streams
         self._next_sid = 0
-        self._batches: List[Tuple[object, int, List[Tuple[int, int, float, int]]]] = []
+        # in flight: (completion event, HIP stream, [(sid, seq, arrival, slot)],
+        # frames referenced until completion)
+        self._batches: List[Tuple[object, object, List[Tuple[int, int, float, int]], list]] = []
         self.completed: List[Completion] = []
 
     # ------------------------------------------------------------ admission
     def stream_bytes(self, H: int, W: int) -> int:
-        """Device bytes a stream holds: two fields, two distance maps."""
+        """Device bytes a stream holds: two fields, two distance maps and
+        its device frame buffer."""
         hq, wq = self.index.field_shape(H, W)
-        return 4 * 4 * hq * wq
+        return 4 * 4 * hq * wq + H * W * int(self.index.params.channels)
+
+    def _scratch_bytes(self, frame_queries: List[int]) -> int:
+        """Search scratch of the server: each HIP stream the server launches
+        on keeps scratch for the largest batch it can form from streams with
+        these per-frame query counts -- one frame per stream, at most
+        max_batch frames, and at most max_batch_queries unless one frame is
+        larger (it goes alone)."""
+        if not frame_queries:
+            return 0
+        qs = sorted(frame_queries, reverse=True)
+        q = sum(qs[:self.max_batch])
+        if self.max_batch_queries is not None:
+            q = min(q, max(self.max_batch_queries, qs[0]))
+        p = self.index.params
+        # the scratch of q queries: a 1 x q field (one patch row of width
+        # patch + (q - 1) * stride)
+        per = footprint(*self._fp, p.patch, p.patch + (q - 1) * p.stride) - self.index_bytes
+        return len(self.hip_streams) * per
+
+    def _queries(self, H, W) -> int:
+        hq, wq = self.index.field_shape(H, W)
+        return hq * wq
+
+    def device_bytes(self, extra: Optional[Tuple[int, int]] = None) -> int:
+        """Device bytes the server needs with its active streams (and one
+        more stream of size `extra`): the index once, every stream's
+        buffers, and the scratch of the largest batch per HIP stream."""
+        shapes = [(s.H, s.W) for s in self.streams.values()]
+        if extra is not None:
+            shapes.append(extra)
+        total = self.index_bytes + sum(self.stream_bytes(H, W) for H, W in shapes)
+        return total + self._scratch_bytes([self._queries(H, W) for H, W in shapes])
 
     def open_stream(self, H: int, W: int) -> int:
         """Returns a stream id.  The stream is active at once if its memory
         fits the budget, otherwise it waits for memory (frames can be
-        submitted meanwhile; they queue)."""
+        submitted meanwhile; they queue).  A stream that could not fit even
+        with no other stream active is rejected (RiannError)."""
+        if self.budget is not None:
+            alone = (self.index_bytes + self.stream_bytes(H, W) +
+                     self._scratch_bytes([self._queries(H, W)]))
+            if alone > self.budget:
+                raise RiannError(-2, f"a {H}x{W} stream needs {alone} device bytes alone, "
+                                     f"above the budget of {self.budget}")
         sid = self._next_sid
         self._next_sid += 1
         if self._fits(H, W):
@@ -110,14 +163,11 @@ class Server:
     def _fits(self, H, W) -> bool:
         if self.budget is None:
             return True
-        scratch = footprint(self.index.params.n_ref, self.index.params.n_keys,
-                            self.index.params.patch, self.index.params.channels,
-                            self.index.params.stride, H, W)
-        return self.used + self.stream_bytes(H, W) + scratch <= self.budget
+        return self.device_bytes(extra=(H, W)) <= self.budget
 
     def _activate(self, sid, H, W):
         hq, wq = self.index.field_shape(H, W)
-        st = _Stream(sid, H, W, hq, wq, self.device, self.torch)
+        st = _Stream(sid, H, W, hq, wq, self.device, self.torch, int(self.index.params.channels))
         pq = self._pending_queues.pop(sid, None)
         if pq:
             st.queue.extend(pq)
@@ -150,7 +200,9 @@ class Server:
     # ------------------------------------------------------------ frames
     def submit(self, sid: int, frame, arrival: Optional[float] = None,
                full: bool = False) -> None:
-        """Queue one device frame (H, W, C) uint8 of stream `sid`.  `full`
+        """Queue one frame (H, W, C) uint8 of stream `sid`, in device memory
+        or in host memory (pinned for an asynchronous copy).  The server
+        keeps a reference until the frame's batch has completed.  `full`
         asks for the exhaustive search (first frame, scene cut)."""
         t = time.perf_counter() if arrival is None else arrival
         st = self.streams.get(sid)
@@ -191,30 +243,46 @@ class Server:
             hs = next(x for x in self.hip_streams if id(x) not in in_use)
         else:
             hs = self.hip_streams[0]
-        items, meta = [], []
+        torch = self.torch
+        items, meta, keep = [], [], []
+        copies = False
         for s in ready:
             frame, t_arr, full = s.queue.popleft()
+            if not frame.is_cuda:
+                # host frame: into the stream's device buffer on the copy
+                # stream (the stream has no frame in flight, so the buffer is free)
+                with torch.cuda.stream(self.copy_stream):
+                    s.dframe.copy_(frame.reshape(s.dframe.shape), non_blocking=True)
+                copies = True
+                keep.append(frame)                    # until the copy has run
+                dframe = s.dframe
+            else:
+                dframe = frame
+                keep.append(frame)                    # until the batch has run
             nxt = 1 - s.cur
             mode = MODE_FULL if (full or not s.has_field) else MODE_RING
-            it = dict(frame=frame, out=s.fields[nxt], ssd=s.ssd[nxt], mode=mode)
+            it = dict(frame=dframe, out=s.fields[nxt], ssd=s.ssd[nxt], mode=mode)
             if mode == MODE_RING:
                 it["prev"] = s.fields[s.cur]
             items.append(it)
             meta.append((s.sid, s.seq, t_arr, nxt))
             s.seq += 1
             s.busy = True
-        # the frames were produced on the current stream; order the batch after them
-        hs.wait_stream(self.torch.cuda.current_stream(self.device))
+        # device frames were produced on the current stream, host frames were
+        # copied on the copy stream: order the batch after both
+        hs.wait_stream(torch.cuda.current_stream(self.device))
+        if copies:
+            hs.wait_stream(self.copy_stream)
         self.index.match_batch(items, stream=hs)
-        ev = self.torch.cuda.Event()
+        ev = torch.cuda.Event()
         ev.record(hs)
-        self._batches.append((ev, hs, meta))
+        self._batches.append((ev, hs, meta, keep))
         return True
 
     def _collect(self, block: bool = False) -> int:
         done = 0
         keep = []
-        for ev, hs, meta in self._batches:
+        for ev, hs, meta, frames in self._batches:
             if block and not keep:
                 ev.synchronize()
             if ev.query():
@@ -230,7 +298,7 @@ class Server:
                         self._free(sid)
                 done += 1
             else:
-                keep.append((ev, hs, meta))
+                keep.append((ev, hs, meta, frames))
         self._batches = keep
         return done
 
@@ -243,9 +311,19 @@ class Server:
             n += 1
         return n
 
+    def _stuck(self) -> bool:
+        """Frames wait, nothing runs and nothing can be launched: only
+        streams waiting for memory hold frames, and no active stream will
+        free any unless the caller closes one."""
+        return (not self._batches and self.pending() > 0 and
+                not any(s.queue for s in self.streams.values()))
+
     def drain(self) -> None:
         while self.pending():
             if not self.step():
+                if self._stuck():
+                    raise RiannError(-2, "frames of streams waiting for memory remain; close "
+                                         "active streams to admit them")
                 self._collect(block=True)
 
 
@@ -271,6 +349,9 @@ def replay(server: Server, trace: List[Tuple[float, int, int]], frame_of: Callab
                           full=full)
             i += 1
         launched = server.step()
+        if i >= len(trace) and server._stuck():
+            raise RiannError(-2, "frames of streams waiting for memory remain; close "
+                                 "active streams to admit them")
         if on_done is not None:
             for c in server.completed[n_done0:]:
                 on_done(c)

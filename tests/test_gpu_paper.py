@@ -118,3 +118,34 @@ def test_paper_errors(torch_dev, riann):
     with pytest.raises(riann.RiannError):
         big.build_paper_tables()                        # n above 32768
     big.close()
+
+
+def test_paper_anchor_golden(torch_dev, riann):
+    """The hand-worked anchor-loop example (tests/golden/paper_anchor_example.txt):
+    1-pixel patches, q = 100 on every query of a 1 x 48 frame, previous
+    match the reference of value 0.  Every query must return the exact copy
+    (index 4, SSD 0) and draw the same anchors as the oracle."""
+    torch, d = torch_dev
+    print_case("paper anchor golden")
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_anchor_example.txt")
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            w = line.split()
+            if w and w[0] in ("ref", "q", "prev", "L"):
+                vals[w[0]] = [int(x) for x in w[1:]]
+    ref = np.array(vals["ref"], np.uint8).reshape(-1, 1)
+    Q = 48
+    idx = riann.Index.build(ref, [], patch=1, channels=1, stride=1)
+    idx.build_paper_tables()
+    pt = oracle.PaperTables(ref)
+    frame = np.full((1, Q), vals["q"][0], np.uint8)
+    prev = np.full((1, Q), vals["prev"][0], np.int32)
+    for seed, t in ((5, 1), (150807953, 7)):
+        out, ssd, iters = idx.match_paper(dev(torch, d, frame), prev=dev(torch, d, prev),
+                                          L=vals["L"][0], seed=seed, t=t)
+        want = pt.search(frame.reshape(Q, 1), prev.reshape(-1), L=vals["L"][0], seed=seed, t=t)
+        assert np.all(want["idx"] == 4) and np.all(want["ssd"] == 0)
+        check(torch, out, ssd, iters, want, f"anchor golden seed {seed}")
+    idx.close()

@@ -137,12 +137,18 @@ def test_reconstruct_field_entries_outside_the_set(torch_dev, riann):
     field = np.full((7, 9), -1, np.int32)
     field[2, 3] = 6
     field[5, 0] = 10          # == n: outside the set
-    out, _ = idx.reconstruct(dev(torch, d, field), 10, 12)
+    field[0, 8] = -7
+    field[6, 6] = 9
+    gt = rng.integers(0, 256, (10, 12), dtype=np.uint8)
+    out, err = idx.reconstruct(dev(torch, d, field), 10, 12, gt=dev(torch, d, gt))
     torch.cuda.synchronize()
     got = out.cpu().numpy()[:, :, 0]
     want = np.zeros((10, 12), np.float32)
     want[2:6, 3:7] = ref[6].reshape(4, 4)
+    want[6:10, 6:10] = ref[9].reshape(4, 4)
     np.testing.assert_array_equal(got, want)
+    # and the oracle, which skips the same entries
+    check(torch, out, err, oracle.reconstruct(field, ref, 4, 1, 10, 12, gt=gt))
     idx.close()
 
 

@@ -93,12 +93,23 @@ def test_admission_and_close(env):
         v = gen.DriftVideo(4, 40, 56, 3, 2, speed=0.5, stream=200 + i)
         vids.append([v.frame(t) for t in range(2)])
     dframes = [[torch.from_numpy(f).to(dev) for f in v] for v in vids]
+    # budget: exactly what two active streams need -- the index once, two
+    # streams' buffers and the scratch of a batch of their two frames
     probe = serve.Server(idx)
-    one = probe.stream_bytes(40, 56)
-    scratch = riann.footprint(300, 6, 8, 3, 1, 40, 56)
-    srv = serve.Server(idx, memory_budget=probe.used + 2 * one + scratch)
+    probe.open_stream(40, 56)
+    probe.open_stream(40, 56)
+    budget = probe.device_bytes()
+    hq, wq = idx.field_shape(40, 56)
+    two_frames = riann.footprint(300, 6, 8, 3, 1, 8, 8 + 2 * hq * wq - 1) - riann.footprint(
+        300, 6, 8, 3, 1)
+    assert budget == probe.index_bytes + 2 * probe.stream_bytes(40, 56) + two_frames
+    assert probe.index_bytes == riann.footprint(300, 6, 8, 3, 1)
+    srv = serve.Server(idx, memory_budget=budget)
     sids = [srv.open_stream(40, 56) for _ in vids]
     assert srv.active_streams == 2 and len(srv.waiting) == 2
+    # a stream that cannot fit even alone is rejected outright
+    with pytest.raises(riann.RiannError):
+        srv.open_stream(400, 560)
     for si, v in zip(sids, dframes):
         srv.submit(si, v[0])
         srv.submit(si, v[1])
@@ -117,4 +128,42 @@ def test_admission_and_close(env):
     for si in sids[1:]:
         assert (si, 0) in done and (si, 1) in done, si
     assert srv.active_streams <= 2
+    idx.close()
+
+
+def test_unreferenced_and_host_frames(env):
+    """Frames the caller does not keep (a fresh device copy per submit, the
+    caller's memory churning meanwhile) and frames in pinned host memory
+    (copied on the server's copy stream) give the exact field of every
+    frame, checked against the oracle's brute force."""
+    torch, riann, serve, dev = env
+    print("[gpu case] serving unreferenced and host frames", flush=True)
+    rng = np.random.default_rng(33)
+    ref, keys = _ref_rgb(rng, n=500, K=8)
+    idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
+    vids = _streams(rng, 6)
+    srv = serve.Server(idx, max_batch=4, inflight=2)
+    sids = [srv.open_stream(v[0].shape[0], v[0].shape[1]) for v in vids]
+    got = {}
+    for t in range(4):
+        n0 = len(srv.completed)
+        for k, (si, v) in enumerate(zip(sids, vids)):
+            if k % 2 == 0:
+                srv.submit(si, torch.from_numpy(v[t]).to(dev))      # no reference kept
+            else:
+                srv.submit(si, torch.from_numpy(v[t]).pin_memory())
+            # churn the caching allocator: same-size blocks freed and reused
+            junk = [torch.full(v[t].shape, 255, dtype=torch.uint8, device=dev)
+                    for _ in range(3)]
+            del junk
+            srv.step()
+        srv.drain()
+        for c in srv.completed[n0:]:
+            got[(c.stream, c.seq)] = (c.field.cpu().numpy().copy(), c.ssd.cpu().numpy().copy())
+    for k, si in enumerate(sids):
+        for t in range(4):
+            bi, bd = oracle.brute_force(oracle.extract(vids[k][t], 8, 1), ref)
+            o, s = got[(si, t)]
+            assert np.array_equal(o.reshape(-1), bi), (k, t)
+            assert np.array_equal(s.reshape(-1).astype(np.uint32), bd), (k, t)
     idx.close()

@@ -423,6 +423,69 @@ def test_paper_hand_examples():
     assert pt.tp[0].tolist() == [0, 4, 1, 2, 3]
 
 
+def _paper_golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_anchor_example.txt")
+    g = {"iters": {}}
+    with open(path) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "iters":
+                # "iters first A [second B] N"
+                key = (int(w[2]),) if w[3] != "second" else (int(w[2]), int(w[4]))
+                g["iters"][key] = int(w[-1])
+            elif w[0] == "answer":
+                g["answer"] = (int(w[2]), int(w[4]))
+            else:
+                g[w[0]] = [int(x) for x in w[1:]]
+    return g
+
+
+def _draw(seed, t, q, it):
+    """The anchor draw: the published SplitMix64 output function (pinned
+    above) chained over (seed, frame, query, iteration)."""
+    m = 2**64 - 1
+    x = oracle.splitmix(seed & m)
+    x = oracle.splitmix((x ^ t) & m)
+    x = oracle.splitmix((x ^ q) & m)
+    return oracle.splitmix((x ^ it) & m)
+
+
+def test_paper_anchor_loop_golden():
+    """The anchor loop of Algorithm 1 against the hand-worked example in
+    tests/golden/paper_anchor_example.txt: r_i's ring holds 7 of the 10
+    references (8 members with r_i, L = 3), and anchors other than r_i,
+    each with its own radius d_k != d_i, remove members until fewer than L
+    remain.  The answer is the exact copy whatever the draws; the anchor
+    count follows the hand-worked transitions from the first two draws.
+    Many queries (each its own draws) walk every kind of path."""
+    g = _paper_golden()
+    ref = np.array(g["ref"], np.uint8).reshape(-1, 1)
+    Q = 48
+    q = np.full((Q, 1), g["q"][0], np.uint8)
+    prev = np.full(Q, g["prev"][0], np.int32)
+    S0 = g["S0"]
+    S1_after_ri = [m for m in S0 if m != g["prev"][0]]
+    seen = set()
+    for seed, t in ((5, 1), (150807953, 7)):
+        _, r = _paper(ref, q, prev, L=g["L"][0], seed=seed, t=t)
+        for i in range(Q):
+            first = S0[_draw(seed, t, i, 0) % len(S0)]
+            if first == g["prev"][0]:
+                second = S1_after_ri[_draw(seed, t, i, 1) % len(S1_after_ri)]
+                key = (first, second)
+            else:
+                key = (first,)
+            seen.add(key)
+            assert (int(r["idx"][i]), int(r["ssd"][i])) == g["answer"], (seed, t, i)
+            assert int(r["iters"][i]) == g["iters"][key], (seed, t, i, key)
+    # the queries reach three-anchor paths and two-anchor paths that start
+    # with an anchor other than r_i
+    assert any(g["iters"][k] == 3 for k in seen)
+    assert any(k[0] != g["prev"][0] and g["iters"][k] == 2 for k in seen)
+
+
 def test_paper_without_anchors_is_the_first_ring():
     """With L above n no anchor is drawn: the answer is the (SSD, index)
     minimum over r_i and the references whose distance to r_i lies in the
@@ -502,6 +565,22 @@ def test_reconstruct_hand_example():
     assert abs(r["E"] - 5.0 / 12.0) < 1e-15
 
 
+def test_reconstruct_field_entries_outside_the_set():
+    """Field entries outside [0, n) name no reference and contribute no
+    patch (worked by hand): 3x3 frame, 2x2 patches, references all-0 and
+    all-4 (n = 2), field [[0, -1], [7, 1]].  Only the top-left patch (0s)
+    and the bottom-right patch (4s) are placed; the centre pixel averages
+    them to 2, pixels (0, 2) and (2, 0) stay uncovered."""
+    app = np.array([[0] * 4, [4] * 4], np.uint8)
+    field = np.array([[0, -1], [7, 1]], np.int32)
+    gt = np.full((3, 3), 4, np.uint8)
+    r = oracle.reconstruct(field, app, 2, 1, 3, 3, gt=gt)
+    np.testing.assert_array_equal(r["count"], [[1, 1, 0], [1, 2, 1], [0, 1, 1]])
+    np.testing.assert_array_equal(r["f_r"][:, :, 0], [[0, 0, 0], [0, 2, 4], [0, 4, 4]])
+    # covered pixels: errors 4, 4, 4, 2, 0, 0, 0 -> 16 * 3 + 4 = 52 over 7 values
+    assert r["sq_err"] == 52.0 and r["sq_gt"] == 112.0 and r["values"] == 7
+
+
 @pytest.mark.parametrize("H,W,p,s", [(9, 13, 3, 1), (20, 17, 4, 2), (16, 16, 8, 3), (5, 5, 5, 1)])
 def test_reconstruct_identity_and_coverage(H, W, p, s):
     """Replacing every patch by itself gives the frame back on every covered
@@ -557,12 +636,14 @@ def _pins_pass():
         test_extract3d_position_code()
         test_knn_riann_equals_brute_force(5)
         test_paper_hand_examples()
+        test_paper_anchor_loop_golden()
+        test_reconstruct_field_entries_outside_the_set()
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_planted_faults(fault):
     assert _pins_pass()
     oracle.set_fault(fault)
