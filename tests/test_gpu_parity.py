@@ -91,6 +91,11 @@ def test_tiny_sequence_exact_and_stats(torch_dev, riann):
     assert st["sum_mstar_ring"] == want["mstar_ring"]
     assert st["no_prior"] == want["noprior"]
     assert st["bound_routed"] == 0
+    ring_phase = want["queries"] - 3249                 # frame 0 is a full search
+    assert st["dense_routed"] == ring_phase - want["ring"]
+    # every query with a prior searches at least one key's ring: two binary
+    # searches, each ending in one line read
+    assert st["bsearch_probes"] >= 2 * (ring_phase - want["noprior"])
     idx.close()
 
 
@@ -367,7 +372,7 @@ def test_hd720_sampled(torch_dev, riann):
         torch.cuda.synchronize()
         P = oracle.extract(f, 8, 1)
         assert len(P) == 907_649
-        sel = np.sort(rng.choice(len(P), 3000, replace=False))
+        sel = np.sort(rng.choice(len(P), 65_536, replace=False))
         sel = np.concatenate([sel, [0, len(P) - 1]])
         bi, bd = oracle.brute_force(P[sel], wl.ref)
         gi, gd = host(out)[sel], host(ssd)[sel].astype(np.uint32)
