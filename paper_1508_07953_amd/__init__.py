@@ -361,8 +361,8 @@ class Index:
         if mode not in (MODE_RING, MODE_FULL):
             raise ValueError(f"mode must be MODE_RING or MODE_FULL, got {mode}")
         out, ssd, prev = it["out"], it.get("ssd"), it.get("prev")
-        if prev is not None and mode != MODE_RING:
-            raise ValueError("prev is only taken in MODE_RING")
+        if mode != MODE_RING:
+            prev = None                     # the full search ignores a previous field
         for name, t in (("out", out), ("ssd", ssd), ("prev", prev)):
             if t is None:
                 continue
@@ -375,8 +375,8 @@ class Index:
                          ssd.data_ptr() if ssd is not None else None, mode, 0)
 
     def match_batch(self, items: List[dict], stream=None) -> None:
-        """items: dicts with frame, out, ssd (optional), prev (optional, ring
-        mode only), mode.  Every item is checked before anything is launched."""
+        """items: dicts with frame, out, ssd (optional), prev (optional; ignored
+        in MODE_FULL), mode.  Every item is checked before anything is launched."""
         descs = [self._batch_desc(it) for it in items]
         arr = (FrameDesc * len(descs))(*descs)
         _check(_lib.riann_match_batch(self._h, arr, len(descs), _stream_ptr(stream)))

@@ -257,13 +257,12 @@ def test_errors(torch_dev, riann):
     with pytest.raises(riann.RiannError):
         riann.Index.build(wl.ref, [5000], patch=8)
     # batch items are checked before any launch: an undersized or mistyped
-    # output, or prev on a full-search item
+    # output or previous field
     good = torch.empty((57, 57), dtype=torch.int32, device=dev)
     sentinel = torch.full((57, 57), -5, dtype=torch.int32, device=dev)
     bad_items = [dict(out=torch.empty((56, 57), dtype=torch.int32, device=dev)),
                  dict(out=torch.empty((57, 57), dtype=torch.int64, device=dev)),
                  dict(out=good, ssd=torch.empty((57, 57, 2), dtype=torch.int32, device=dev)),
-                 dict(out=good, prev=buf, mode=riann.MODE_FULL),
                  dict(out=good, prev=torch.empty((57, 56), dtype=torch.int32, device=dev))]
     for bad in bad_items:
         with pytest.raises(ValueError):
