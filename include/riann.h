@@ -187,6 +187,27 @@ riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev,
                                  uint32_t *ssd_dev, void *hip_stream);
 
 /*
+ * riann_match_frame_noalloc -- riann_match_frame for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same kernels and the
+ * same result as riann_match_frame, but the per-frame scratch (query
+ * patches, ring records, route lists and their counters) lives in one
+ * static device array of 64 MiB per GPU, held from the library's load until
+ * the process ends; this call allocates nothing.  The array holds the
+ * scratch of frames with up to about 470,000 queries at D = 64 (a
+ * 640 x 720 gray frame at stride 1) or 250,000 at D = 192 (640 x 360 RGB);
+ * a larger frame returns RIANN_E_UNSUPPORTED with the bytes it needs.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (other streams, other threads, other indexes) race and must be ordered by
+ * the caller.  The list counters are cleared by the call's own first kernel.
+ * Kernel timing (riann_set_profiling) is not recorded for this call.
+ */
+riann_status_t riann_match_frame_noalloc(riann_index_t h, const uint8_t *frame_dev,
+                                         int32_t H, int32_t W, int64_t pitch,
+                                         const int32_t *prev_dev, int32_t *out_dev,
+                                         uint32_t *ssd_dev, void *hip_stream);
+
+/*
  * riann_full_search -- exact nearest neighbour of every query by exhaustive
  * search (the exact NN the paper uses for its analyses, Sec. 3.1), used for
  * the first frame (Algorithm 1 starts from a random field instead) and at

@@ -39,7 +39,7 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
            "riann_reconstruct", "riann_stack_frames", "riann_match_knn",
-           "riann_build_paper_tables", "riann_match_paper"]
+           "riann_build_paper_tables", "riann_match_paper", "riann_match_frame_noalloc"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -87,6 +87,7 @@ def _load():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.riann_build.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(vp)]
     L.riann_match_frame.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp]
+    L.riann_match_frame_noalloc.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp]
     L.riann_full_search.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp]
     L.riann_match_batch.argtypes = [vp, C.POINTER(FrameDesc), i32, vp]
     L.riann_footprint.argtypes = [C.POINTER(Params), i32, i32, C.POINTER(i64)]
@@ -265,6 +266,28 @@ class Index:
         _check(_lib.riann_match_frame(self._h, frame.data_ptr(), H, W, pitch,
                                       prev.data_ptr() if prev is not None else None,
                                       out.data_ptr(), ssd.data_ptr(), _stream_ptr(stream)))
+        return out, ssd
+
+    def match_frame_noalloc(self, frame, prev, out, ssd, stream=None):
+        """match_frame through the entry point that allocates nothing: the
+        caller supplies out and ssd, and the library's scratch is its static
+        per-GPU array (frames up to its size only; calls that overlap on one
+        GPU race)."""
+        H, W, pitch = _frame_geom(frame, self.params.channels)
+        hq, wq = self.field_shape(H, W)
+        for name, t in (("out", out), ("ssd", ssd), ("prev", prev)):
+            if t is None:
+                if name == "prev":
+                    continue
+                raise ValueError(f"{name} must be given (this call allocates nothing)")
+            if (t.numel() != max(hq, 0) * max(wq, 0) or not t.is_contiguous()
+                    or t.element_size() != 4 or t.device != frame.device):
+                raise ValueError(f"{name} must be a contiguous 4-byte ({hq}, {wq}) tensor on "
+                                 "the frame's device")
+        _check(_lib.riann_match_frame_noalloc(self._h, frame.data_ptr(), H, W, pitch,
+                                              prev.data_ptr() if prev is not None else None,
+                                              out.data_ptr(), ssd.data_ptr(),
+                                              _stream_ptr(stream)))
         return out, ssd
 
     def match_knn(self, frame, k: int, prev=None, full: bool = False, out=None, ssd=None,

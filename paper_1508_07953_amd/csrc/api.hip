@@ -50,9 +50,19 @@ struct riann_index {
     double prof_ms[RIANN_K_COUNT] = {};
 };
 
+// Scratch of riann_match_frame_noalloc: one copy per device, held from the
+// library's load until the process ends.  Host code must never pass the
+// array's name to a kernel (on the host it is only a stand-in): the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;   // device -> address of its `scratch`
 
 riann_status_t fail(riann_status_t st, const std::string &msg) {
     g_err = msg;
@@ -378,6 +388,23 @@ riann_status_t finish_build(riann_index *h, hipStream_t st, riann_index_t *out) 
     return RIANN_OK;
 }
 
+// The per-launch scratch of `cap` queries laid out from `b` (work_bytes(cap,
+// Dp) bytes, 256-byte aligned).
+Work carve_work(char *b, int64_t cap, int Dp) {
+    Work nw;
+    int64_t o = 0;
+    nw.patches = (uint8_t *)(b + o);  o = round_up(o + cap * Dp, 256);
+    nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
+    nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
+    nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
+    nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 48, 256);
+    nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
+    nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
+    nw.counters = (uint32_t *)(b + o);
+    nw.capacity = cap;
+    return nw;
+}
+
 riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     const int Dp = h->Dp;
     std::lock_guard<std::mutex> lk(h->mu);
@@ -396,18 +423,7 @@ riann_status_t get_work(riann_index *h, hipStream_t st, int64_t Q, Work *w) {
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, (size_t)work_bytes(cap, Dp));
     if (e != hipSuccess) return fail(RIANN_E_NOMEM, "hipMalloc of frame scratch failed");
-    char *b = (char *)p;
-    Work nw;
-    int64_t o = 0;
-    nw.patches = (uint8_t *)(b + o);  o = round_up(o + cap * Dp, 256);
-    nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
-    nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
-    nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
-    nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 48, 256);
-    nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
-    nw.dense_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
-    nw.counters = (uint32_t *)(b + o);
-    nw.capacity = cap;
+    const Work nw = carve_work((char *)p, cap, Dp);
     h->work[st] = nw;
     *w = nw;
     return RIANN_OK;
@@ -456,8 +472,9 @@ struct KTimer {
     int kind;
     hipStream_t st;
     hipEvent_t a = nullptr;
-    KTimer(riann_index *h_, int kind_, hipStream_t st_) : h(h_), kind(kind_), st(st_) {
-        const int lv = h->profiling.load();
+    KTimer(riann_index *h_, int kind_, hipStream_t st_, bool on = true)
+        : h(h_), kind(kind_), st(st_) {
+        const int lv = on ? h->profiling.load() : 0;
         if (lv == 0) return;
         if (lv == RIANN_PROFILE_DENSE && kind != RIANN_K_DENSE && kind != RIANN_K_FULL) return;
         a = take();
@@ -490,7 +507,10 @@ struct KTimer {
 };
 
 // One launch sequence over up to kMaxBatch frames (descriptors validated).
-riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn = 1) {
+// `preset`: scratch the caller provides (the no-allocation entry point); then
+// nothing is allocated and no profiling events are taken.
+riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn = 1,
+                         const Work *preset = nullptr) {
     fb.knn = knn;
     int64_t q = 0;
     int32_t t = 0;
@@ -508,26 +528,32 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     fb.ntiles = t;
     fb.all_full = all_full ? 1 : 0;
     Work w;
-    riann_status_t s = get_work(h, st, q, &w);
-    if (s != RIANN_OK) return s;
+    if (preset) {
+        if (preset->capacity < q) return fail(RIANN_E_INVALID, "scratch smaller than the batch");
+        w = *preset;
+    } else {
+        riann_status_t s = get_work(h, st, q, &w);
+        if (s != RIANN_OK) return s;
+    }
     hipError_t e;
     const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
+    const bool timed = preset == nullptr;
     {
         // the extraction kernel also clears the ring and dense list counters
-        KTimer tm(h, RIANN_K_EXTRACT, st);
+        KTimer tm(h, RIANN_K_EXTRACT, st, timed);
         e = launch_extract(h->dix, fb, w, st);
         tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     }
     if (!all_full) {
         {
-            KTimer tm(h, RIANN_K_RING, st);
+            KTimer tm(h, RIANN_K_RING, st, timed);
             e = launch_ring(h->dix, fb, w, h->dstats, h->threshold.load(), st);
             tm.stop();
             if (e != hipSuccess) return hip_fail(e, "k_ring launch");
         }
         {
-            KTimer tm(h, RIANN_K_SCAN, st);
+            KTimer tm(h, RIANN_K_SCAN, st, timed);
             e = knn > 1 ? launch_scan_knn(h->dix, fb, w, h->dstats, st)
                         : launch_scan(h->dix, fb, w, h->dstats, st);
             tm.stop();
@@ -535,7 +561,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
         }
     }
     {
-        KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st);
+        KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st, timed);
         if (knn > 1) {
             e = h->dense_rows && knn_rows_supported(h->dix) ? launch_dense_rows_knn(h->dix, fb, w, st)
                                                             : launch_dense_knn(h->dix, fb, w, st);
@@ -626,6 +652,42 @@ riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev, int3
     if (s != RIANN_OK) return s;
     DeviceGuard g(h->device);
     return run_batch(h, fb, (hipStream_t)hip_stream);
+}
+
+riann_status_t riann_match_frame_noalloc(riann_index_t h, const uint8_t *frame_dev, int32_t H,
+                                         int32_t W, int64_t pitch, const int32_t *prev_dev,
+                                         int32_t *out_dev, uint32_t *ssd_dev, void *hip_stream) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    FrameBatch fb;
+    fb.n = 1;
+    riann_status_t s = frame_desc(h, frame_dev, H, W, pitch, prev_dev, out_dev, ssd_dev,
+                                  RIANN_MODE_RING, &fb.f[0]);
+    if (s != RIANN_OK) return s;
+    const int64_t Q = (int64_t)fb.f[0].Hq * fb.f[0].Wq;
+    const int64_t need = work_bytes(Q, h->Dp);
+    if (need > kNoAllocScratchBytes)
+        return fail(RIANN_E_UNSUPPORTED,
+                    "frame of " + std::to_string(Q) + " queries needs " + std::to_string(need) +
+                        " bytes of scratch, more than the " +
+                        std::to_string(kNoAllocScratchBytes) +
+                        " bytes riann_match_frame_noalloc holds");
+    DeviceGuard g(h->device);
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch_ptr.find(h->device);
+        if (it == g_scratch_ptr.end()) {
+            void *ptr = nullptr;
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) return hip_fail(e, "scratch symbol address");
+            it = g_scratch_ptr.emplace(h->device, (char *)ptr).first;
+        }
+        base = it->second;
+    }
+    // every buffer that must start at zero (the list counters) is cleared by
+    // the extraction kernel of the launch itself
+    const Work w = carve_work(base, Q, h->Dp);
+    return run_batch(h, fb, (hipStream_t)hip_stream, 1, &w);
 }
 
 riann_status_t riann_match_knn(riann_index_t h, const uint8_t *frame_dev, int32_t H, int32_t W,
