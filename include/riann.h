@@ -99,6 +99,16 @@ typedef struct riann_params {
  * then leaves such queries out (they are counted in bound_routed). */
 #define RIANN_FLAG_EXACT_MSTAR 2u
 
+/* riann_params_t.flags: scan rings by gathering each candidate's pivot row
+ * (one K-word row per reference, reached through the sorted list's index)
+ * instead of the default ring-ordered copy, in which entry j of key k's
+ * sorted list carries its reference's whole pivot row (Sec. 3.3 tables laid
+ * out so that scanning a ring is one contiguous read).  The default costs
+ * K * n * 4 * KR more bytes of device memory (KR = 8, 16, 32, 48 or 64 words
+ * for K <= 8, 16, 32, 48, 64: 16 MB at n = 16,384, K = 16; 2.4 GB at
+ * n = 262,144, K = 48); results are identical. */
+#define RIANN_FLAG_GATHER_SCAN 4u
+
 /* One frame of a batch (riann_match_batch). */
 typedef struct riann_frame_desc {
     const uint8_t *frame;      /* device, H x W x C, row pitch `pitch`         */
@@ -360,6 +370,27 @@ riann_status_t riann_get_params(riann_index_t h, riann_params_t *p);
  * a result, only the time it takes (the autotuner picks this value).
  */
 riann_status_t riann_set_dense_threshold(riann_index_t h, int64_t threshold);
+
+/*
+ * riann_set_dense_shape -- block shape of the row-layout dense search (the
+ * default; not RIANN_FLAG_COLUMN_DENSE) for launches issued after the call:
+ * `waves` wavefronts per block and `cols` 32-query column blocks per
+ * wavefront, i.e. 32 * cols queries per wavefront and 32 * cols * waves per
+ * block.  waves = cols = 0 restores the patch width's default.  Only the
+ * shapes riann_get_dense_shapes lists for the index's patch width are built;
+ * any other returns RIANN_E_UNSUPPORTED.  The shape never changes a result,
+ * only the time it takes (the autotuner picks it).
+ */
+riann_status_t riann_set_dense_shape(riann_index_t h, int32_t waves, int32_t cols);
+
+/*
+ * riann_get_dense_shapes -- the shapes built for the index's patch width,
+ * the default first: writes up to `max` (waves, cols) pairs to the host
+ * arrays waves[] and cols[] (either may be NULL), their number to *count and
+ * the index of the shape in use to *current (either may be NULL).
+ */
+riann_status_t riann_get_dense_shapes(riann_index_t h, int32_t *waves, int32_t *cols,
+                                      int32_t max, int32_t *count, int32_t *current);
 
 /*
  * riann_save / riann_load -- write / read the index (reference set, keys and

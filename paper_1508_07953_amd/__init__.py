@@ -31,6 +31,7 @@ RIANN_OK, RIANN_E_INVALID, RIANN_E_NOMEM, RIANN_E_DEVICE, RIANN_E_UNSUPPORTED, R
 MODE_RING, MODE_FULL = 0, 1
 FLAG_COLUMN_DENSE = 1
 FLAG_EXACT_MSTAR = 2
+FLAG_GATHER_SCAN = 4
 PROFILE_ALL, PROFILE_DENSE = 1, 2
 
 # every symbol include/riann.h declares
@@ -39,7 +40,8 @@ EXPORTS = ["riann_build", "riann_match_frame", "riann_full_search", "riann_match
            "riann_save", "riann_load", "riann_destroy", "riann_last_error", "riann_version",
            "riann_set_profiling", "riann_get_profile", "riann_set_dense_threshold",
            "riann_reconstruct", "riann_stack_frames", "riann_match_knn",
-           "riann_build_paper_tables", "riann_match_paper", "riann_match_frame_noalloc"]
+           "riann_build_paper_tables", "riann_match_paper", "riann_match_frame_noalloc",
+           "riann_set_dense_shape", "riann_get_dense_shapes"]
 KERNELS = ["ring", "scan", "dense", "full", "extract"]
 
 
@@ -99,6 +101,8 @@ def _load():
     L.riann_destroy.argtypes = [vp]
     L.riann_set_profiling.argtypes = [vp, C.c_int]
     L.riann_set_dense_threshold.argtypes = [vp, i64]
+    L.riann_set_dense_shape.argtypes = [vp, i32, i32]
+    L.riann_get_dense_shapes.argtypes = [vp, vp, vp, i32, vp, vp]
     L.riann_get_profile.argtypes = [vp, C.POINTER(Profile)]
     L.riann_reconstruct.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, i64, vp, vp]
     L.riann_match_knn.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, i32, vp]
@@ -416,6 +420,19 @@ class Index:
         """Routing threshold for later launches (a performance knob only)."""
         _check(_lib.riann_set_dense_threshold(self._h, int(threshold)))
         self.params.dense_threshold = int(threshold)
+
+    def dense_shapes(self) -> Tuple[List[Tuple[int, int]], int]:
+        """Block shapes (waves, cols) of the row-layout dense search built for
+        this patch width (default first) and the index of the one in use."""
+        wv, cl = (C.c_int32 * 16)(), (C.c_int32 * 16)()
+        cnt, cur = C.c_int32(), C.c_int32()
+        _check(_lib.riann_get_dense_shapes(self._h, wv, cl, 16, C.byref(cnt), C.byref(cur)))
+        return [(int(wv[i]), int(cl[i])) for i in range(min(cnt.value, 16))], int(cur.value)
+
+    def set_dense_shape(self, waves: int, cols: int) -> None:
+        """Block shape of the dense search for later launches (a performance
+        knob only); (0, 0) is the default."""
+        _check(_lib.riann_set_dense_shape(self._h, int(waves), int(cols)))
 
     def set_profiling(self, enable=True) -> None:
         """True: time every kernel; "dense": only the dense search; False: off.

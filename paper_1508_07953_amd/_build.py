@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libriann.so")
 SOURCES = ["api.hip", "k_extract.hip", "k_ring.hip", "k_dense.hip", "k_dense_rows.hip",
-           "k_recon.hip", "k_paper.hip"]
+           "k_dense_rows_shapes.hip", "k_recon.hip", "k_paper.hip"]
 ARCH = os.environ.get("RIANN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -24,7 +24,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # per-source extras: MFMA results go straight to VGPRs in the dense search,
 # whose epilogue reads every accumulator element
 EXTRA = {"k_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
-         "k_dense_rows.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+         "k_dense_rows.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "k_dense_rows_shapes.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:

@@ -22,6 +22,7 @@ struct riann_index {
     int D = 0, Dp = 0, K = 0;
     int64_t n = 0, n_pad = 0;
     std::atomic<int64_t> threshold{0};
+    std::atomic<int32_t> shape{0};   // row-layout dense block shape: waves << 8 | cols, 0 = default
     bool dense_rows = true;   // row-layout dense search where supported
     int device = 0;
     // host copies (kept for riann_save)
@@ -104,7 +105,9 @@ riann_status_t check_params(const riann_params_t *p) {
     if (p->n_keys < 0 || p->n_keys > kMaxKeys)
         return fail(RIANN_E_INVALID, "n_keys must be in [0, 64]");
     if (p->n_keys > p->n_ref) return fail(RIANN_E_INVALID, "n_keys exceeds n_ref");
-    if ((p->flags & ~(RIANN_FLAG_COLUMN_DENSE | RIANN_FLAG_EXACT_MSTAR)) != 0 || p->reserved != 0)
+    if ((p->flags & ~(RIANN_FLAG_COLUMN_DENSE | RIANN_FLAG_EXACT_MSTAR |
+                      RIANN_FLAG_GATHER_SCAN)) != 0 ||
+        p->reserved != 0)
         return fail(RIANN_E_INVALID, "unknown flags or nonzero reserved field");
     return RIANN_OK;
 }
@@ -129,13 +132,15 @@ int64_t row_layout_rows(int64_t n, const std::vector<int32_t> *Rc) {
               : round_up(round_up(n, kTile) + kTile, kRefAlign);
 }
 
-int64_t index_bytes(int64_t n, int D, int K) {
+int64_t index_bytes(int64_t n, int D, int K, uint32_t flags) {
     const int Dp = (int)round_up(D, 32);
     const int64_t n_pad = round_up(n, kRefAlign);
     const int64_t n16 = round_up(n, 16), Kp = round_up(std::max(K, 1), 4);
     const int64_t n_rows = row_layout_rows(n, nullptr);
+    const int64_t pivr = (K > 0 && !(flags & RIANN_FLAG_GATHER_SCAN))
+                             ? (int64_t)K * n16 * pivr_words(K) * 4 + 256 : 0;
     return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
-           n_rows * (Dp + 12) + (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096;
+           n_rows * (Dp + 12) + (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096 + pivr;
 }
 
 int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 64 + 8) + 8192; }
@@ -292,10 +297,12 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
                  szS = ST_COUNT * 8, szTs = Ts.size() * 4, szLb = Lb.size() * 4;
     const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8;
-    size_t off[14], tot = 0;
-    const size_t sz[14] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
-                           szLb};
-    for (int i = 0; i < 14; ++i) {
+    const bool pivr = K > 0 && !(h->prm.flags & RIANN_FLAG_GATHER_SCAN);
+    const size_t szPivR = pivr ? (size_t)K * n16 * pivr_words(K) * 4 : 0;
+    size_t off[15], tot = 0;
+    const size_t sz[15] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
+                           szLb, szPivR};
+    for (int i = 0; i < 15; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -322,6 +329,8 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.lbB = lbB;
     h->dix.lbS = lbS;
     h->dix.exact_mstar = (h->prm.flags & RIANN_FLAG_EXACT_MSTAR) ? 1 : 0;
+    h->dix.PivR = pivr ? (const uint32_t *)(b + off[14]) : nullptr;
+    h->dix.KR = pivr ? pivr_words(K) : 0;
     h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.Rfr = (const int8_t *)(b + off[11]);
     h->dix.Rci = (const int2 *)(b + off[12]);
@@ -357,6 +366,11 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     }
     e = hipMemsetAsync(h->dstats, 0, szS, st);
     if (e != hipSuccess) return hip_fail(e, "stats clear");
+    if (pivr) {
+        // ring-ordered pivot rows, gathered on the device from P and Piv
+        e = launch_build_pivr(h->dix, (uint32_t *)(b + off[14]), st);
+        if (e != hipSuccess) return hip_fail(e, "pivot-row table build");
+    }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "index upload sync");
     return RIANN_OK;
@@ -566,7 +580,11 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
             e = h->dense_rows && knn_rows_supported(h->dix) ? launch_dense_rows_knn(h->dix, fb, w, st)
                                                             : launch_dense_knn(h->dix, fb, w, st);
         } else if (rows) {
-            e = launch_dense_rows(h->dix, fb, w, st);
+            DevIndex dx = h->dix;
+            const int32_t sh = h->shape.load();
+            dx.row_waves = sh >> 8;
+            dx.row_cols = sh & 0xFF;
+            e = launch_dense_rows(dx, fb, w, st);
         } else {
             e = launch_dense(h->dix, fb, w, st);
         }
@@ -593,7 +611,7 @@ riann_status_t riann_footprint(const riann_params_t *p, int32_t H, int32_t W, in
     riann_status_t s = check_params(p);
     if (s != RIANN_OK) return s;
     if (!bytes) return fail(RIANN_E_INVALID, "bytes is NULL");
-    int64_t b = index_bytes(p->n_ref, p->patch * p->patch * p->channels, p->n_keys);
+    int64_t b = index_bytes(p->n_ref, p->patch * p->patch * p->channels, p->n_keys, p->flags);
     if (H > 0 && W > 0) {
         if (H < p->patch || W < p->patch) return fail(RIANN_E_INVALID, "frame smaller than patch");
         const int64_t Q = (int64_t)((H - p->patch) / p->stride + 1) *
@@ -802,6 +820,44 @@ riann_status_t riann_set_dense_threshold(riann_index_t h, int64_t threshold) {
     if (threshold < 0) return fail(RIANN_E_INVALID, "threshold must be >= 0");
     h->threshold.store(threshold);
     h->prm.dense_threshold = threshold;
+    return RIANN_OK;
+}
+
+riann_status_t riann_set_dense_shape(riann_index_t h, int32_t waves, int32_t cols) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (waves == 0 && cols == 0) {
+        h->shape.store(0);
+        return RIANN_OK;
+    }
+    if (!h->dense_rows) return fail(RIANN_E_UNSUPPORTED, "the column-layout dense search has one shape");
+    int32_t wv[16], cl[16];
+    const int n = dense_rows_shapes(h->Dp, wv, cl, 16);
+    for (int i = 0; i < n && i < 16; ++i)
+        if (wv[i] == waves && cl[i] == cols) {
+            h->shape.store(i == 0 ? 0 : (waves << 8 | cols));
+            return RIANN_OK;
+        }
+    return fail(RIANN_E_UNSUPPORTED, "block shape " + std::to_string(waves) + " x " +
+                                         std::to_string(cols) + " is not built for this patch width");
+}
+
+riann_status_t riann_get_dense_shapes(riann_index_t h, int32_t *waves, int32_t *cols, int32_t max,
+                                      int32_t *count, int32_t *current) {
+    if (!h) return fail(RIANN_E_INVALID, "index is NULL");
+    if (max < 0) return fail(RIANN_E_INVALID, "max must be >= 0");
+    int32_t wv[16], cl[16];
+    const int n = h->dense_rows ? std::min(dense_rows_shapes(h->Dp, wv, cl, 16), 16) : 0;
+    const int32_t sh = h->shape.load();
+    int cur = 0;
+    for (int i = 0; i < n; ++i) {
+        if (i < max) {
+            if (waves) waves[i] = wv[i];
+            if (cols) cols[i] = cl[i];
+        }
+        if (sh != 0 && (wv[i] << 8 | cl[i]) == sh) cur = i;
+    }
+    if (count) *count = n;
+    if (current) *current = cur;
     return RIANN_OK;
 }
 

@@ -1,497 +1,11 @@
-// k_dense_rows.hip -- exact exhaustive search with references as the MFMA
-// rows and queries as the columns (v_mfma_i32_32x32x32_i8), the default dense
-// search at every patch width.
-//
-// With a = 127 - q, v = r - 128 and p = Rc & 1, the per-reference value
-// Hf = (Rc + bias - p) / 2 enters as the MFMA's C operand, read straight from
-// LDS, so the accumulator is Y = Hf + <a, v> and SSD - Qc + bias = 2Y + p
-// exactly.  The references run in the index's class order -- every one with
-// even Rc, then every one with odd Rc, index order within each class, each
-// class padded to whole tiles -- so p is constant over a tile.  Per (query,
-// tile) a lane holds 16 rows of one query column: a v_min3 tree gives the
-// tile minimum of Y (about 0.5 VALU op per pair) and one v_lshl_or plus one
-// v_min keep the key (Y << b) | tile over a segment of 2^b tiles (b = 11 to 8
-// as the widest Y grows with the patch); at each segment's end the key folds
-// into the query's (Y, tile) minimum, an earlier segment keeping a tie.  Over
-// both lane groups the lexicographic (Y, tile) minimum is in the tile holding
-// the (SSD, index) minimum: a row with smaller SSD would have a smaller Y, or
-// the same Y and p = 0 (an even-class tile, hence an earlier one); a row with
-// the same SSD and a lower index sits in the same class, in the same or an
-// earlier tile.  The wavefront then recomputes the exact SSDs of that tile's
-// rows in the lane group(s) that reached the minimum and takes their (SSD,
-// index) minimum; these gathers overlap the matrix work of the other
-// wavefronts on the SIMD.  Query chunks that fill whole rounds of the resident
-// block slots run whole; the chunks of a last, partial round (or all of them
-// when there are fewer chunks than slots) split the reference range over up
-// to four blocks each, so the last round runs full and short.  The parts
-// leave records that a resolve kernel merges before the same check.
-#include "riann_internal.h"
-
-#include <algorithm>
+// k_dense_rows.hip -- the row-layout dense search at the default block shape
+// of every patch width (kernels in k_dense_rows.h), its k-NN variant, and the
+// launch dispatch (other block shapes: k_dense_rows_shapes.hip).
+#include "k_dense_rows.h"
 
 namespace riann {
 
 namespace {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) void glb_void;
-
-#ifndef RIANN_ROWS_WAVES
-#define RIANN_ROWS_WAVES 0                     // 0: four
-#endif
-#ifndef RIANN_ROWS_QB
-#define RIANN_ROWS_QB 0                        // 0: four
-#endif
-#ifndef RIANN_ROWS_INFLIGHT
-#define RIANN_ROWS_INFLIGHT 0                  // 0: by patch width
-#endif
-
-// Block shape: wavefronts per block and 32-query column blocks per
-// wavefront.  Measured on the 720p workload (D = 64, dense step): four column
-// blocks and four wavefronts 0.73-0.75 ms; three or five column blocks
-// 0.78-0.80 ms; six 0.73-0.76 ms; two 0.84 ms; eight wavefronts per block
-// 0.75-0.83 ms.  Every variant passed the row-layout parity tests first.
-template <int DP>
-struct RowCfg {
-    static constexpr int waves = RIANN_ROWS_WAVES > 0 ? RIANN_ROWS_WAVES : 4;
-    static constexpr int qb = RIANN_ROWS_QB > 0 ? RIANN_ROWS_QB : (DP <= 192 ? 4 : 2);
-    // check passes in flight: the wide patches' rows need the registers
-    static constexpr int inflight =
-        RIANN_ROWS_INFLIGHT > 0 ? RIANN_ROWS_INFLIGHT : (DP <= 96 ? 2 : 1);
-    static constexpr int block = 64 * waves;
-    static constexpr int wave_q = 32 * qb;
-    static constexpr int block_q = wave_q * waves;
-    static_assert(qb >= 2, "the LDS prefetch runs one query block ahead");
-};
-#ifndef RIANN_ROWS_SCHED
-// MFMA/VALU interleave: 2 = each MFMA of a chain followed by a share of the
-// minimum tree (1: one MFMA, half the tree, the rest; 0: the compiler's
-// order).  Measured: 2 and 1 equal at D = 64, 2 faster by 1.8 % at D = 192;
-// 0 slower by 3 % at D = 64.  Raising the wave priority around the MFMA
-// issue (RIANN_ROWS_SETPRIO) gained nothing.
-#define RIANN_ROWS_SCHED 2
-#endif
-#ifndef RIANN_ROWS_SETPRIO
-#define RIANN_ROWS_SETPRIO 0                   // 1: raise wave priority while issuing MFMAs
-#endif
-#ifndef RIANN_ROWS_LOOKAHEAD
-#define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
-#endif                                         // (2: within 1 %, 25 more registers)
-constexpr int kLookahead = RIANN_ROWS_LOOKAHEAD;
-
-template <int KB, int ST, int WAVES>
-__device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
-                                          const int32_t *__restrict__ gh, int sg, int8_t *lf,
-                                          int32_t *lh, int wv, int lane) {
-    constexpr int CH = ST * KB;
-    const int8_t *src = gf + (int64_t)sg * CH * 1024;
-#pragma unroll
-    for (int i = 0; i < (CH + WAVES - 1) / WAVES; ++i) {
-        const int c = wv + WAVES * i;
-        if (c < CH)
-            __builtin_amdgcn_global_load_lds((glb_void *)(src + c * 1024 + lane * 16),
-                                             (lds_void *)(lf + c * 1024), 16, 0, 0);
-    }
-    if (wv == WAVES - 1 && lane < ST * 8)
-        __builtin_amdgcn_global_load_lds((glb_void *)(gh + (int64_t)sg * ST * kTile + lane * 4),
-                                         (lds_void *)lh, 16, 0, 0);
-}
-
-__device__ __forceinline__ uint32_t min16(const v16i &a) {
-    uint32_t m0 = min(min((uint32_t)a[0], (uint32_t)a[1]), (uint32_t)a[2]);
-    uint32_t m1 = min(min((uint32_t)a[3], (uint32_t)a[4]), (uint32_t)a[5]);
-    uint32_t m2 = min(min((uint32_t)a[6], (uint32_t)a[7]), (uint32_t)a[8]);
-    uint32_t m3 = min(min((uint32_t)a[9], (uint32_t)a[10]), (uint32_t)a[11]);
-    uint32_t m4 = min(min((uint32_t)a[12], (uint32_t)a[13]), (uint32_t)a[14]);
-    m0 = min(min(m0, m1), m2);
-    m3 = min(min(m3, m4), (uint32_t)a[15]);
-    return min(m0, m3);
-}
-
-template <int DP, int ST, int QB, int KN = 1>
-struct RowState {
-    static constexpr int KB = DP / 32, TB = row_tile_bits(DP);
-    v4i Bq[QB][KB];         // query fragments (MFMA B operand)
-    uint32_t key[QB];       // min over the current segment of (Y << TB) | tile
-    uint32_t bY[QB], bT[QB];// (Y, tile) minimum of the earlier segments
-    uint32_t kl[QB][KN];    // k-NN (KN > 1): the KN smallest keys, ascending
-
-    // fold the segment starting at tile t0 into (bY, bT); an earlier segment
-    // keeps a tie (its tiles come first)
-    __device__ __forceinline__ void fold(uint32_t t0) {
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-            const uint32_t y = key[qb] >> TB, t = t0 + (key[qb] & ((1u << TB) - 1u));
-            const bool lt = y < bY[qb];
-            bY[qb] = lt ? y : bY[qb];
-            bT[qb] = lt ? t : bT[qb];
-            key[qb] = ~0u;
-        }
-    }
-
-    // A fragments and accumulator initial values (Hf) of tile u of a stage
-    __device__ __forceinline__ void load_tile(const int8_t *lf, const int32_t *lh, int u,
-                                              int lane, int grp, v4i (&Af)[KB], v16i &H) {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-            Af[kb] = *reinterpret_cast<const v4i *>(lf + (u * KB + kb) * 1024 + lane * 16);
-        const v4i *hp = reinterpret_cast<const v4i *>(lh + u * kTile + grp * 16);
-        const v4i h0 = hp[0], h1 = hp[1], h2 = hp[2], h3 = hp[3];
-        H = v16i{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3],
-                 h2[0], h2[1], h2[2], h2[3], h3[0], h3[1], h3[2], h3[3]};
-    }
-
-    __device__ __forceinline__ void mma(int qb, const v4i (&Af)[KB], const v16i &H, v16i &acc) {
-        acc = H;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(Af[kb], Bq[qb][kb], acc, 0, 0, 0);
-    }
-
-    __device__ __forceinline__ void track(int qb, const v16i &acc, uint32_t t) {
-        const uint32_t x0 = (min16(acc) << TB) | t;
-        if constexpr (KN == 1) {
-            key[qb] = min(key[qb], x0);
-        } else {
-            uint32_t x = x0;                      // sorted insertion
-#pragma unroll
-            for (int i = 0; i < KN; ++i) {
-                const uint32_t o = kl[qb][i];
-                kl[qb][i] = min(o, x);
-                x = max(o, x);
-            }
-        }
-    }
-
-    // all tiles of one LDS stage, as a sequence of (tile, query block) items:
-    // the MFMA chain of item i + LA is issued before the minimum tree of
-    // item i, so the tree reads an accumulator whose chain has finished while
-    // the later chains run (LA + 1 accumulators, used in turn).  The next
-    // tile's LDS operands are read one item before its first chain.
-    __device__ __forceinline__ void stage(const int8_t *lf, const int32_t *lh, uint32_t t0s,
-                                          int lane, int grp) {
-        constexpr int LA = kLookahead;
-        static_assert(QB >= LA + 1, "the next tile's operands load inside the current tile");
-        v4i Af[2][KB];
-        v16i H[2];
-        v16i acc[LA + 1];
-        load_tile(lf, lh, 0, lane, grp, Af[0], H[0]);
-#pragma unroll
-        for (int j = 0; j < LA; ++j) mma(j, Af[0], H[0], acc[j]);
-#pragma unroll
-        for (int u = 0; u < ST; ++u) {
-            const int cur = u & 1;
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                const int it = u * QB + qb, nx = it + LA;
-                if (qb == QB - 1 - LA && u + 1 < ST)
-                    load_tile(lf, lh, u + 1, lane, grp, Af[cur ^ 1], H[cur ^ 1]);
-                if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(1);
-                if (nx < ST * QB)
-                    mma(nx % QB, Af[(nx / QB) & 1], H[(nx / QB) & 1], acc[nx % (LA + 1)]);
-                if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(0);
-                track(qb, acc[it % (LA + 1)], t0s + (uint32_t)u);
-                if constexpr (RIANN_ROWS_SCHED == 1) {
-                    // one MFMA, then half of the tree, then the chain's other
-                    // MFMAs and the rest: the wave keeps issuing VALU work
-                    // while each MFMA of the chain executes
-                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x008, KB - 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
-                    __builtin_amdgcn_sched_barrier(0);
-                } else if constexpr (RIANN_ROWS_SCHED == 2) {
-                    // each MFMA of the chain followed by a share of the tree
-                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x002, (10 + KB - 1) / KB, 0);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-    }
-};
-
-// Candidate check of one dense query by a 16-lane group.  rec = {Y,
-// tile << 2 | group mask}: lane r takes accumulator row r of the tile in each
-// masked lane group -- class-order row 32 tile + 8(r/4) + 4g + r%4 -- forms
-// its exact SSD with v_dot4 from the row's fragment bytes, and a 16-lane
-// reduction keeps the (SSD, reference index) minimum.  issue() starts the
-// loads that need only the record (Qc and the first masked group's row with
-// its {Rc, index}); finish() takes the query patch (global memory or LDS) and
-// does the rest, so a caller can have the loads of several queries in flight
-// before any waits.
-template <int DP>
-struct RowCheck {
-    static constexpr int KB = DP / 32;
-    uint4 v[DP / 16];       // first candidate row of this lane (patch byte order)
-    int2 ri;                // its {Rc, reference index}; index < 0: none
-    int qc;
-
-    __device__ __forceinline__ static void row_bytes(const DevIndex &ix, int64_t tile, int m,
-                                                     uint4 (&v)[DP / 16]) {
-        // fragment order: tile, k-block kb, lane m + 32h -> bytes 32kb + 16h of row m
-        const uint4 *f = reinterpret_cast<const uint4 *>(ix.Rfr) + tile * KB * 64 + m;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            v[2 * kb] = f[kb * 64];
-            v[2 * kb + 1] = f[kb * 64 + 32];
-        }
-    }
-
-    __device__ __forceinline__ void issue(const DevIndex &ix, const Work &w, uint32_t q,
-                                          const uint2 &rec, bool live, int r) {
-        ri = make_int2(0, -1);
-        if (!live) return;
-        qc = w.qc[q];
-        const int g = (rec.y & 1u) ? 0 : 1;
-        const int64_t tile = rec.y >> 2;
-        const int m = 8 * (r >> 2) + 4 * g + (r & 3);
-        ri = ix.Rci[tile * kTile + m];
-        row_bytes(ix, tile, m, v);
-    }
-
-    __device__ __forceinline__ static int dot(const uint4 (&a)[DP / 16], const uint4 (&v)[DP / 16]) {
-        int d = 0;
-#pragma unroll
-        for (int k = 0; k < DP / 16; ++k) {
-            d = __builtin_amdgcn_sdot4((int)a[k].x, (int)v[k].x, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[k].y, (int)v[k].y, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[k].z, (int)v[k].z, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[k].w, (int)v[k].w, d, false);
-        }
-        return d;
-    }
-
-    __device__ __forceinline__ void finish(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                                           uint32_t q, const uint2 &rec, bool live, int lane,
-                                           const uint4 *patch) {
-        const int r = lane & 15;
-        unsigned long long best = ~0ull;
-        if (live) {
-            uint4 a[DP / 16];
-#pragma unroll
-            for (int k = 0; k < DP / 16; ++k) a[k] = patch[k];
-            if (ri.y >= 0) {
-                const uint32_t ssd = (uint32_t)(qc + ri.x + 2 * dot(a, v));
-                best = ((unsigned long long)ssd << 32) | (uint32_t)ri.y;
-            }
-            if ((rec.y & 3u) == 3u) {           // both lane groups reached the minimum
-                const int64_t tile = rec.y >> 2;
-                const int m = 8 * (r >> 2) + 4 + (r & 3);
-                const int2 rj = ix.Rci[tile * kTile + m];
-                if (rj.y >= 0) {
-                    uint4 u[DP / 16];
-                    row_bytes(ix, tile, m, u);
-                    const uint32_t ssd = (uint32_t)(qc + rj.x + 2 * dot(a, u));
-                    const unsigned long long k2 = ((unsigned long long)ssd << 32) | (uint32_t)rj.y;
-                    best = k2 < best ? k2 : best;
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) {
-            const unsigned lo = __shfl_xor((unsigned)best, m, 64);
-            const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
-            const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-            best = o < best ? o : best;
-        }
-        if (live && r == 0) {
-            const FrameDesc *fdp = &fb.f[w.fid[q]];
-            const int64_t ql = (int64_t)q - fdp->qbase;
-            fdp->out[ql] = (int32_t)(uint32_t)best;
-            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
-        }
-    }
-};
-
-// How a launch covers `chunks` query chunks with `slots` resident blocks:
-// the first `whole` chunks run as one block each over every reference; each
-// later chunk is split over `parts` blocks (consecutive blocks, consecutive
-// parts).  With more chunks than slots, only the remainder past whole rounds
-// is split, into as many parts as still fit one round (at most
-// kRowMaxParts); with fewer, every chunk is split so the chunks' parts cover
-// the slots.  Blocks used: whole + (chunks - whole) * parts
-// <= chunks + min(3 * chunks, slots).
-struct RowPlan {
-    uint32_t whole, parts;
-};
-__host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots) {
-    const uint32_t cap = (uint32_t)kRowMaxParts;
-    uint32_t p = 1;
-    if (chunks == 0 || slots == 0) return RowPlan{chunks, 1u};
-    if (chunks <= slots) {
-        p = (slots + chunks - 1) / chunks;
-        p = p < cap ? p : cap;
-        return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
-    }
-    const uint32_t rem = chunks % slots;
-    if (rem) {
-        p = slots / rem;
-        p = p < cap ? p : cap;
-    }
-    return p > 1 ? RowPlan{chunks - rem, p} : RowPlan{chunks, 1u};
-}
-
-template <int DP, int ST>
-__global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows(DevIndex ix, FrameBatch fb, Work w,
-                                                       uint32_t slots) {
-    constexpr int KB = DP / 32;
-    constexpr int kWaves = RowCfg<DP>::waves, kQB = RowCfg<DP>::qb;
-    constexpr int kWaveQ = RowCfg<DP>::wave_q, kBlockQ = RowCfg<DP>::block_q;
-    constexpr int STAGE = ST * KB * 1024;
-    // the two reference stages; after the last tile, the query patches of
-    // narrow patches (wide ones are read from global memory by the check)
-    constexpr bool kStagePatches = DP <= 96;
-    constexpr int PATCHES = kStagePatches ? kBlockQ * DP : 0;
-    constexpr int BUF = 2 * STAGE > PATCHES ? 2 * STAGE : PATCHES;
-    constexpr int SPS = (1 << row_tile_bits(DP)) / ST;  // stages per key segment
-    static_assert(SPS % 2 == 0, "stage pairs never straddle a segment");
-    __shared__ __attribute__((aligned(16))) int8_t s_buf[BUF];
-    int8_t *const s_f0 = s_buf;
-    int8_t *const s_f1 = s_buf + STAGE;
-    __shared__ __attribute__((aligned(16))) int32_t s_h0[ST * kTile];
-    __shared__ __attribute__((aligned(16))) int32_t s_h1[ST * kTile];
-
-    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
-    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    // whole chunks first, then the split ones, nsplit blocks per chunk, each
-    // over one part of the reference stages (consecutive blocks take
-    // consecutive parts and land on different XCDs, so each XCD's L2 holds
-    // fewer parts)
-    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
-    const uint32_t bx = blockIdx.x;
-    const bool whole = bx < plan.whole;
-    const int nsplit = whole ? 1 : (int)plan.parts;
-    const uint32_t split = whole ? 0u : (bx - plan.whole) % plan.parts;
-    const uint32_t chunk = whole ? bx : plan.whole + (bx - plan.whole) / plan.parts;
-    const uint32_t qbase = chunk * kBlockQ;
-    if (qbase >= count) return;                   // whole block exits together
-
-    // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
-    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int col = lane & 31, grp = lane >> 5;
-    const int ns_all = (int)(ix.n_rows / (kTile * ST));
-    const int s_begin = (int)((int64_t)split * ns_all / nsplit);
-    const int s_end = (int)((int64_t)(split + 1) * ns_all / nsplit);
-
-    if (s_begin < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, s_begin, s_f0, s_h0, wv, lane);
-
-    RowState<DP, ST, kQB> S;
-    uint32_t qid[kQB];
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
-        qid[qb] = list ? list[slot] : slot;
-        const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) + (int64_t)qid[qb] * DP +
-                            grp * 16;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) S.Bq[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
-        S.key[qb] = ~0u;
-        S.bY[qb] = ~0u;
-        S.bT[qb] = 0u;
-    }
-    __syncthreads();
-
-    int seg0 = s_begin;                           // first stage of the key segment
-    for (int sg = s_begin; sg < s_end; sg += 2) {
-        if (sg - seg0 == SPS) {
-            S.fold((uint32_t)(seg0 * ST));
-            seg0 = sg;
-        }
-        if (sg + 1 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
-        S.stage(s_f0, s_h0, (uint32_t)((sg - seg0) * ST), lane, grp);
-        __syncthreads();
-        if (sg + 1 < s_end) {
-            if (sg + 2 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
-            S.stage(s_f1, s_h1, (uint32_t)((sg + 1 - seg0) * ST), lane, grp);
-            __syncthreads();
-        }
-    }
-    S.fold((uint32_t)(seg0 * ST));
-
-    // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
-    // accumulator order): the lexicographically smaller (Y, tile) wins; equal
-    // pairs mean the same Y in the same tile, checked in both groups.
-    // rec = {Y, tile << 2 | group mask}, the tile counted over the whole class
-    // order, the same in both groups.
-    uint2 rc[kQB];
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t y = S.bY[qb], t = S.bT[qb];
-        const uint32_t oy = (uint32_t)__shfl_xor((int)y, 32, 64);
-        const uint32_t ot = (uint32_t)__shfl_xor((int)t, 32, 64);
-        const bool same = y == oy && t == ot;
-        const bool mine = y < oy || (y == oy && t < ot);
-        const uint32_t gm = same ? 3u : (mine ? (1u << grp) : (2u >> grp));
-        rc[qb] = make_uint2(mine || same ? y : oy, ((mine || same ? t : ot) << 2) | gm);
-    }
-
-    const uint32_t wbase = qbase + (uint32_t)(wv * kWaveQ);
-    if (nsplit > 1) {
-        // one part of the reference range: the record goes to the resolve
-        // kernel at the query's dense-list position (the records are free
-        // once the ring scan has run)
-        uint4 *dst = split ? w.rec2 + (int64_t)(split - 1) * w.capacity : w.rec;
-#pragma unroll
-        for (int qb = 0; qb < kQB; ++qb) {
-            const uint32_t slot = wbase + (uint32_t)(qb * 32 + col);
-            if (slot < count && grp == 0) dst[slot] = make_uint4(rc[qb].x, rc[qb].y, 0u, 0u);
-        }
-        return;
-    }
-    // the whole reference range: the wavefront checks its own queries, four
-    // at a time (one per 16-lane group), with the gathers of kInFlight such
-    // passes issued before any waits.  The records and query ids come from
-    // the owning lanes by shuffles, the query patches from the MFMA operand
-    // registers through the (now free) stage buffers.
-    int8_t *const sp = s_buf + wv * (kWaveQ * DP);
-    if constexpr (kStagePatches) {
-        __syncthreads();                          // every wavefront is past its last tile
-#pragma unroll
-        for (int qb = 0; qb < kQB; ++qb)
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-                *reinterpret_cast<v4i *>(sp + (qb * 32 + col) * DP + kb * 32 + grp * 16) =
-                    S.Bq[qb][kb];
-        __syncthreads();
-    }
-    constexpr int kInFlight = RowCfg<DP>::inflight;
-    const int sub = lane >> 4, r = lane & 15;
-#pragma unroll
-    for (int qb = 0; qb < kQB; ++qb) {
-#pragma unroll
-        for (int h = 0; h < 32; h += 4 * kInFlight) {
-            RowCheck<DP> C[kInFlight];
-            uint2 rr[kInFlight];
-            uint32_t qq[kInFlight];
-            bool ll[kInFlight];
-#pragma unroll
-            for (int p = 0; p < kInFlight; ++p) {
-                const int c = h + 4 * p + sub;
-                rr[p] = make_uint2(__shfl(rc[qb].x, c, 64), __shfl(rc[qb].y, c, 64));
-                qq[p] = (uint32_t)__shfl((int)qid[qb], c, 64);
-                ll[p] = wbase + (uint32_t)(qb * 32 + c) < count;
-                C[p].issue(ix, w, qq[p], rr[p], ll[p], r);
-            }
-#pragma unroll
-            for (int p = 0; p < kInFlight; ++p) {
-                const int c = h + 4 * p + sub;
-                const int8_t *patch = kStagePatches ? sp + (qb * 32 + c) * DP
-                                                    : reinterpret_cast<const int8_t *>(w.patches) +
-                                                          (int64_t)qq[p] * DP;
-                C[p].finish(ix, fb, w, qq[p], rr[p], ll[p], lane,
-                            reinterpret_cast<const uint4 *>(patch));
-            }
-        }
-    }
-}
 
 // ---- k-NN over the class order (exact k nearest (SSD, index) pairs).
 // The k nearest lie in the k tiles with the smallest (per-tile minimum Y,
@@ -678,73 +192,6 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows_knn(DevIndex i
 // candidate check.  The records sit at the list position, so they load
 // alongside the list.  A grid-stride loop whose trip count is uniform over
 // the block; with no split chunk every block returns at once.
-template <int DP>
-__global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w, uint32_t slots) {
-    constexpr uint32_t kBlockQ = RowCfg<DP>::block_q;
-    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
-    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
-    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
-    const int nsplit = (int)plan.parts;
-    const int lane = threadIdx.x & 63, r = lane & 15;
-    for (uint32_t base = plan.whole * kBlockQ + blockIdx.x * 16u; base < count;
-         base += gridDim.x * 16u) {
-        const uint32_t i = base + (threadIdx.x >> 4);
-        const bool live = i < count;
-        const uint32_t q = live ? (list ? list[i] : i) : 0u;
-        uint2 rec = make_uint2(0u, 0u);
-        if (live) {
-            unsigned long long best = ~0ull;
-#pragma unroll
-            for (int s = 0; s < kRowMaxParts; ++s) {
-                if (s < nsplit) {
-                    const uint4 p = s ? w.rec2[(int64_t)(s - 1) * w.capacity + i] : w.rec[i];
-                    const unsigned long long k = ((unsigned long long)p.x << 32) | p.y;
-                    best = k < best ? k : best;
-                }
-            }
-            rec = make_uint2((uint32_t)(best >> 32), (uint32_t)best);
-        }
-        RowCheck<DP> C;
-        C.issue(ix, w, q, rec, live, r);
-        C.finish(ix, fb, w, q, rec, live, lane,
-                 reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP));
-    }
-}
-
-template <int DP>
-hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
-    constexpr int ST = DP <= 64 ? 8 : 4;
-    static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
-    // The dense query count is known on the device only: the grid covers the
-    // largest plan any count up to fb.Q can take, and surplus blocks return
-    // at once.  (Splitting every chunk of a 720p frame -- 1,773 chunks on
-    // 768 slots -- costs more than it gains: the query patches are read once
-    // per part and every query goes through the resolve kernel.)
-    static int resident = 0;
-    if (resident == 0) {
-        int dev = 0, cus = 0, per = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&k_dense_rows<DP, ST>), RowCfg<DP>::block, 0);
-        resident = std::max(1, cus) * std::max(1, per);
-    }
-    constexpr int kBlockQ = RowCfg<DP>::block_q;
-    const int64_t chunks = std::max<int64_t>(1, (fb.Q + kBlockQ - 1) / kBlockQ);
-    const uint32_t slots = (uint32_t)resident;
-    const int64_t blocks = chunks + std::min<int64_t>(3 * chunks, resident);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dense_rows<DP, ST>), dim3((unsigned)blocks),
-                       dim3(RowCfg<DP>::block),
-                       0, st, ix, fb, w, slots);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // split queries: fewer than min(chunks, slots) chunks' worth
-    const int64_t sq = std::min<int64_t>(chunks, resident) * kBlockQ;
-    const int64_t rb = std::min<int64_t>((sq + 15) / 16, 4096);   // 16 queries per 256-thread block
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP>), dim3((unsigned)rb), dim3(256),
-                       0, st, ix, fb, w, slots);
-    return hipGetLastError();
-}
 
 template <int DP, int KN>
 hipError_t launch_rows_knn_kn(const DevIndex &ix, const FrameBatch &fb, const Work &w,
@@ -792,6 +239,7 @@ hipError_t launch_dense_rows_knn(const DevIndex &ix, const FrameBatch &fb, const
 
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              hipStream_t st) {
+    if (ix.row_waves != 0 || ix.row_cols != 0) return launch_dense_rows_shape(ix, fb, w, st);
     switch (ix.Dp) {
     case 32: return launch_rows_t<32>(ix, fb, w, st);
     case 64: return launch_rows_t<64>(ix, fb, w, st);

@@ -14,6 +14,8 @@
 //   of the exact SSD over S with a wavefront reduction (lowest index on ties).
 #include "riann_internal.h"
 
+#include <algorithm>
+
 namespace riann {
 
 namespace {
@@ -511,6 +513,122 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameBatch fb, Wor
     }
 }
 
+// ---------------------------------------------------------------- k_scan_rows
+// k_scan over the ring-ordered pivot rows (the default layout): entry j of
+// key k's sorted list carries its reference's whole pivot row,
+// PivR[k][j] = Piv[P[k][j]] (KQ 16-byte words per row, padding keys 0), so
+// the smallest ring [st, en) of key k* is one contiguous stream of rows that
+// consecutive lanes read from consecutive addresses.  Each lane keeps U rows
+// in flight.  Ring k's test lo_k <= x <= hi_k is the unsigned
+// x - lo_k <= hi_k - lo_k; padding keys get [0, 2^32 - 1], which every
+// value meets.  The reference index (P) is read only for candidates inside
+// every ring, before their exact SSD.
+template <int DP, int KQ>
+__global__ __launch_bounds__(kBlock) void k_scan_rows(DevIndex ix, FrameBatch fb, Work w,
+                                                       unsigned long long *__restrict__ stats) {
+    constexpr int U = KQ <= 4 ? 4 : (KQ <= 8 ? 2 : 1);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t count = w.counters[0];
+    const uint32_t n = (uint32_t)ix.n;
+    const int K = ix.K;
+    unsigned long long surv_tot = 0, mstar_tot = 0;
+    for (uint32_t item = blockIdx.x * (kBlock / 64) + wv; item < count;
+         item += gridDim.x * (kBlock / 64)) {
+        const uint32_t qid = w.ring_list[item];
+        const uint4 rec = w.rec[qid];
+        const uint32_t c = rec.x, ks = rec.y, st = rec.z, en = rec.w;
+        const uint32_t mine = lane < DP / 4
+            ? reinterpret_cast<const uint32_t *>(w.patches + (int64_t)qid * DP)[lane] : 0u;
+        uint32_t a[DP / 4];
+#pragma unroll
+        for (int i = 0; i < DP / 4; ++i) a[i] = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+        const int Qc = w.qc[qid];
+        uint32_t lo = 0, wd = 0xFFFFFFFFu;
+        if (lane < K) {
+            const int key = ix.keys[lane];
+            const int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
+            const uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
+            uint32_t hi;
+            ring_bounds(b, c, lo, hi);
+            wd = hi - lo;
+        }
+        unsigned long long best = ~0ull;
+        uint32_t cnt = 0;
+        const int32_t *Pk = ix.P + (int64_t)ks * n;
+        const uint4 *rows = reinterpret_cast<const uint4 *>(ix.PivR) + (int64_t)ks * ix.n16 * KQ;
+        for (uint32_t j0 = st; j0 < en; j0 += 64 * U) {
+            uint4 pv[U][KQ];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = j0 + 64 * u + lane;
+                const uint4 *row = rows + (int64_t)(j < en ? j : st) * KQ;
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) pv[u][q] = row[q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = j0 + 64 * u + lane;
+                bool in = j < en;
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) {
+                    const uint32_t x[4] = {pv[u][q].x, pv[u][q].y, pv[u][q].z, pv[u][q].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, 4 * q + e);
+                        const uint32_t wk = (uint32_t)__builtin_amdgcn_readlane((int)wd, 4 * q + e);
+                        in = in && x[e] - lk <= wk;
+                    }
+                }
+                if (in) {
+                    ++cnt;
+                    const int32_t r = Pk[j];
+                    const int d = dot_row<DP>(a, ix.Rv + (int64_t)r * ix.Dp);
+                    const uint32_t s = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
+                    const unsigned long long key = ((unsigned long long)s << 32) | (uint32_t)r;
+                    best = key < best ? key : best;
+                }
+            }
+        }
+        best = wave_min_u64(best);
+        const unsigned long long tot = wave_sum_u64(cnt);
+        if (lane == 0) {
+            const FrameDesc *fdp = &fb.f[w.fid[qid]];
+            const int64_t ql = (int64_t)qid - fdp->qbase;
+            fdp->out[ql] = (int32_t)(uint32_t)best;
+            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
+            surv_tot += tot;
+            mstar_tot += en - st;
+        }
+    }
+    __shared__ unsigned long long s_acc[kBlock / 64][2];
+    if (lane == 0) { s_acc[wv][0] = surv_tot; s_acc[wv][1] = mstar_tot; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
+        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
+    }
+}
+
+// PivR[k][j] = Piv[P[k][j]], each row widened from Kp to KR words with zeros;
+// entries j >= n (the list's padding to whole lines) are zero rows.
+__global__ __launch_bounds__(256) void k_build_pivr(const uint32_t *__restrict__ Piv,
+                                                     const int32_t *__restrict__ P, int64_t n,
+                                                     int32_t n16, int32_t K, int32_t Kp,
+                                                     int32_t KR, uint32_t *__restrict__ PivR) {
+    const int64_t total = (int64_t)K * n16 * KR;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / KR;
+        const int col = (int)(i - e * KR);
+        const int k = (int)(e / n16);
+        const int64_t j = e - (int64_t)k * n16;
+        uint32_t v = 0;
+        if (j < n && col < Kp) v = Piv[(int64_t)P[(int64_t)k * n + j] * Kp + col];
+        PivR[i] = v;
+    }
+}
+
 // ---------------------------------------------------------------- k_scan_knn
 // k-NN variant of k_scan: each lane keeps the KN smallest (SSD, index) keys of
 // its candidates in a sorted register list (KN = 2, 4 or 8 >= k); the
@@ -648,9 +766,27 @@ hipError_t launch_scan_knn_t(const DevIndex &ix, const FrameBatch &fb, const Wor
     return hipGetLastError();
 }
 
+template <int DP, int KQ>
+hipError_t launch_scan_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                              unsigned long long *stats, hipStream_t st) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_rows<DP, KQ>), dim3(1024), dim3(kBlock), 0, st, ix,
+                       fb, w, stats);
+    return hipGetLastError();
+}
+
 template <int DP>
 hipError_t launch_scan_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                          unsigned long long *stats, hipStream_t st) {
+    if (ix.PivR) {
+        switch (ix.KR) {
+        case 8: return launch_scan_rows_t<DP, 2>(ix, fb, w, stats, st);
+        case 16: return launch_scan_rows_t<DP, 4>(ix, fb, w, stats, st);
+        case 32: return launch_scan_rows_t<DP, 8>(ix, fb, w, stats, st);
+        case 48: return launch_scan_rows_t<DP, 12>(ix, fb, w, stats, st);
+        case 64: return launch_scan_rows_t<DP, 16>(ix, fb, w, stats, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan<DP>), dim3(1024), dim3(kBlock), 0, st, ix, fb, w,
                        stats);
     return hipGetLastError();
@@ -683,6 +819,16 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 #define CALL_SCAN(D) launch_scan_t<D>(ix, fb, w, stats, st)
     RIANN_DP_SWITCH(ix.Dp, CALL_SCAN)
 #undef CALL_SCAN
+}
+
+int pivr_words(int K) { return K <= 8 ? 8 : (K + 15) / 16 * 16; }
+
+hipError_t launch_build_pivr(const DevIndex &ix, uint32_t *PivR, hipStream_t st) {
+    const int64_t total = (int64_t)ix.K * ix.n16 * pivr_words(ix.K);
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_build_pivr, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                       ix.Piv, ix.P, ix.n, ix.n16, ix.K, ix.Kp, pivr_words(ix.K), PivR);
+    return hipGetLastError();
 }
 
 hipError_t launch_scan_knn(const DevIndex &ix, const FrameBatch &fb, const Work &w,

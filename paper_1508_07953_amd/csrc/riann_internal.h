@@ -78,6 +78,11 @@ struct DevIndex {
     const int32_t *P;     // K x n, reference index of each T entry
     const uint32_t *Piv;  // n x Kp, SSD(r, key_k); rows padded to Kp = 4*ceil(K/4)
                           // with zeros (padding keys get the bounds [0, 2^32-1])
+    const uint32_t *PivR; // K x n16 x KR, ring-ordered pivot rows: PivR[k][j] =
+                          // Piv[P[k][j]] widened to KR words with zeros
+                          // (entries j >= n are zero rows); nullptr with
+                          // RIANN_FLAG_GATHER_SCAN (the scan then gathers Piv)
+    int32_t KR;           // PivR row length in words: 8, 16, 32, 48 or 64
     const uint32_t *Ts;   // K x ns binary-search samples Ts[k][i] = T[k][i * 16 * s0l],
                           // copied to LDS by the ring phase
     const uint32_t *Lb;   // K x lbS ring-size lower-bound rows {vmin, shift,
@@ -94,6 +99,9 @@ struct DevIndex {
     int32_t Kp;           // Piv row stride
     int32_t lbB, lbS;     // lower-bound buckets per key, row stride in words
     int32_t exact_mstar;  // 1: every ring-phase query's smallest ring is evaluated
+    int32_t row_waves;    // block shape of the row-layout dense search: wavefronts
+    int32_t row_cols;     // per block, 32-query column blocks per wavefront (0, 0:
+                          // the patch width's default); read on the host only
 };
 
 // One frame of a launch.  A launch takes up to kMaxBatch frames of any sizes;
@@ -156,6 +164,10 @@ hipError_t launch_ring(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                        unsigned long long *stats, int64_t threshold, hipStream_t st);
 hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                        unsigned long long *stats, hipStream_t st);
+// Ring-ordered pivot rows (k_ring.hip): the row length for K keys, and the
+// device build of ix.PivR from ix.P and ix.Piv.
+int pivr_words(int K);
+hipError_t launch_build_pivr(const DevIndex &ix, uint32_t *PivR, hipStream_t st);
 // all_full batches: every query (no list); otherwise the dense list and its
 // device-side count.  Reads the query patches written by launch_extract.
 hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
@@ -166,6 +178,12 @@ hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 bool dense_rows_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              hipStream_t st);
+// The block shapes built for patch width Dp as (waves, cols) pairs, the
+// default first; returns their number and writes at most `max` of them.
+int dense_rows_shapes(int Dp, int *waves, int *cols, int max);
+// The row kernel at the non-default shape ix.row_waves x ix.row_cols.
+hipError_t launch_dense_rows_shape(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                                   hipStream_t st);
 // T planar frames (each H x W x C, common row pitch) -> one H x W x (T*C)
 // frame whose channel t*C + c is channel c of frame t (k_extract.hip).
 constexpr int kMaxStack = 16;

@@ -1,12 +1,16 @@
-"""Autotuner for the ring/dense routing threshold.
+"""Autotuner for the dense search's block shape and the ring/dense routing
+threshold.
 
 Which path answers a query never changes its result (both are exact); it
 only changes the time.  The break-even ring size depends on the reference-set
 size, the patch dimension, the number of key points and how wide the rings of
 the actual video are (Sec. 3.3: more temporal change, more candidates), so it
 is measured rather than modelled: each candidate threshold is timed on real
-frames with HIP events and the fastest is kept.  Results are cached in a JSON
-file keyed by (device architecture, patch, channels, stride, n, K).
+frames with HIP events and the fastest is kept.  The same holds for the
+dense search's block shape (wavefronts per block, 32-query column blocks per
+wavefront, i.e. queries per wavefront): the shapes built for the patch width
+are timed on the exhaustive search of real frames.  Results are cached in a
+JSON file keyed by (device architecture, patch, channels, stride, n, K).
 """
 from __future__ import annotations
 
@@ -86,6 +90,45 @@ def tune_threshold(index, frames: Sequence, prevs: Sequence,
     best = min(ms, key=lambda t: (ms[t], t))
     index.set_dense_threshold(best)
     rec = {"threshold": best, "ms": {str(k): v for k, v in ms.items()}}
+    if write_cache:
+        _store(key, rec)
+    return dict(rec, cached=False)
+
+
+def tune_shape(index, frames: Sequence, repeats: int = 2, use_cache: bool = True,
+               write_cache: bool = True, arch: Optional[str] = None) -> Dict:
+    """Times `index.full_search(frames[i])` (every query through the dense
+    search) at each block shape the library built for the index's patch
+    width and sets the fastest.  Returns {"shape": (waves, cols), "ms":
+    {"WxC": mean ms per frame}, "cached": bool}."""
+    import torch
+    if arch is None:
+        arch = torch.cuda.get_device_properties(frames[0].device).gcnArchName.split(":")[0]
+    key = cache_key(index, arch) + ":shape"
+    if use_cache:
+        rec = _load_cache().get(key)
+        if rec is not None:
+            index.set_dense_shape(*rec["shape"])
+            return dict(rec, cached=True)
+    shapes, _ = index.dense_shapes()
+    outs = [index.full_search(f) for f in frames]
+    ms: Dict[str, float] = {}
+    stream = torch.cuda.current_stream()
+    for wv, cl in shapes:
+        index.set_dense_shape(wv, cl)
+        for f, (o, d) in zip(frames, outs):               # warm-up
+            index.full_search(f, out=o, ssd=d)
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(repeats):
+            for f, (o, d) in zip(frames, outs):
+                index.full_search(f, out=o, ssd=d)
+        end.record(stream)
+        end.synchronize()
+        ms[f"{wv}x{cl}"] = start.elapsed_time(end) / (repeats * len(frames))
+    best = min(shapes, key=lambda sh: (ms[f"{sh[0]}x{sh[1]}"], shapes.index(sh)))
+    index.set_dense_shape(*best)
+    rec = {"shape": list(best), "ms": ms}
     if write_cache:
         _store(key, rec)
     return dict(rec, cached=False)

@@ -139,7 +139,7 @@ SHAPES = [
 ]
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 4])      # default, column dense, gather scan
 @pytest.mark.parametrize("p,C,s,n,K,H,W", SHAPES)
 def test_shapes_exact(torch_dev, riann, p, C, s, n, K, H, W, flags):
     torch, dev = torch_dev
@@ -704,14 +704,17 @@ RING_CASES = [  # p, C, K, n: the ring phase's register-bound (K <= 16, Dp <= 64
 ]
 
 
+@pytest.mark.parametrize("scan", ["rows", "gather"])
 @pytest.mark.parametrize("p,C,K,n", RING_CASES)
-def test_ring_stats_both_paths(torch_dev, riann, p, C, K, n):
+def test_ring_stats_both_paths(torch_dev, riann, p, C, K, n, scan):
     """Per-key bucket bounds must leave m* and the survivor counts exactly
     the oracle's (all K rings evaluated), whichever key-selection path runs;
     every query with a prior is sent to the ring scan, so a wrong k* or range
-    would also break the exact field."""
+    would also break the exact field.  Both scan layouts: the ring-ordered
+    pivot rows (default, row lengths 8/16/32/48 words here) and the gather
+    through the sorted list's index."""
     torch, dev = torch_dev
-    print_case(f"ring stats p={p} C={C} K={K} n={n}")
+    print_case(f"ring stats p={p} C={C} K={K} n={n} scan={scan}")
     rng = np.random.default_rng(1000 * p + K)
     H, W = 30, 41
     base = rng.integers(0, 256, (H + 40, W + 40, C), dtype=np.uint8)
@@ -721,7 +724,8 @@ def test_ring_stats_both_paths(torch_dev, riann, p, C, K, n):
     ref = R[np.sort(rng.choice(len(R), n, replace=False))]
     ref[11] = ref[3]
     keys = np.sort(rng.choice(n, K, replace=False))
-    idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=1, dense_threshold=n)
+    idx = riann.Index.build(ref, keys, patch=p, channels=C, stride=1, dense_threshold=n,
+                            flags=riann.FLAG_GATHER_SCAN if scan == "gather" else 0)
     P = oracle.extract(f, p, 1)
     hq, wq = oracle.field_shape(H, W, p, 1)
     prev = rng.integers(-1, n, (hq, wq)).astype(np.int32)

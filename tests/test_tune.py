@@ -36,3 +36,26 @@ def test_unreadable_cache_is_empty(tmp_path, monkeypatch):
     path.write_text("{not json")
     monkeypatch.setenv("RIANN_TUNE_CACHE", str(path))
     assert tune._load_cache() == {}
+
+
+class FakeShapeIndex(FakeIndex):
+    def __init__(self):
+        super().__init__()
+        self.shapes_set = []
+
+    def set_dense_shape(self, waves, cols):
+        self.shapes_set.append((waves, cols))
+
+
+def test_cached_shape_is_applied(tmp_path, monkeypatch):
+    """A cached block shape is set without timing anything, under its own
+    key beside the threshold's."""
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("RIANN_TUNE_CACHE", str(path))
+    idx = FakeShapeIndex()
+    key = tune.cache_key(idx, "gfx950") + ":shape"
+    tune._store(key, {"shape": [8, 4], "ms": {"4x4": 1.0, "8x4": 0.9}})
+    tune._store(tune.cache_key(idx, "gfx950"), {"threshold": 64, "ms": {"64": 1.0}})
+    r = tune.tune_shape(idx, [None], arch="gfx950")
+    assert r["cached"] and tuple(r["shape"]) == (8, 4) and idx.shapes_set == [(8, 4)]
+    assert json.loads(path.read_text())["gfx950:p8c1s1:n16384:K16"]["threshold"] == 64
