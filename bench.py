@@ -163,22 +163,6 @@ def extras(args, result, idx, wl, frames, field, H, Wd, hq, wq, Q, K, W, dev, st
                              "GBps": rbytes / (ms_r * 1e-3) / 1e9,
                              "note": "field 4 B/query + frame 1 B and output 4 B per value + "
                                      "appearance set once; gathers served by L2"}
-    # the same frames by the exhaustive search alone (no ring phase): exact
-    # as well, so this is what the ring intersection buys on this workload
-    nf = min(10, K)
-    fo = torch.empty((hq, wq), dtype=torch.int32, device=dev)
-    fs = torch.empty((hq, wq), dtype=torch.int32, device=dev)
-    idx.full_search(frames[W + 1], out=fo, ssd=fs)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(nf):
-        idx.full_search(frames[W + 1 + i], out=fo, ssd=fs)
-    e1.record(stream)
-    e1.synchronize()
-    result["full_search_every_frame"] = {
-        "ms_per_frame": e0.elapsed_time(e1) / nf, "frames": nf,
-        "note": "riann_full_search on the timed frames: the same exact field without the "
-                "ring phase (HIP events on the launch stream)"}
     # exact k-NN fields (k = 4) on the same frames, where the key range allows
     try:
         kk = 4
@@ -205,6 +189,173 @@ def extras(args, result, idx, wl, frames, field, H, Wd, hq, wq, Q, K, W, dev, st
         result["knn"] = {"k": 4, "unsupported": str(ex)}
     if not args.no_paper_mode:
         result["paper_mode"] = paper_mode(idx, frames, hq, wq, dev, log)
+
+
+def ring_path_forced(idx, wl, frames, field, t0, nframes, hq, wq, log_fn):
+    """The ring path carrying every query: routing threshold n, so each query
+    with a prior goes through the smallest-ring search (k_ring), the ring
+    scan and the survivor check (k_scan) -- nothing is routed to the dense
+    search.  Every kernel is bracketed by HIP events on the launch stream;
+    algorithmic bytes come from the device counters (sum of m*, sum of |S|)."""
+    import torch
+    n, D = int(idx.params.n_ref), wl.D
+    Dp = (D + 31) // 32 * 32
+    Kn = len(wl.keys)
+    kr = 0 if Kn == 0 else (8 if Kn <= 8 else (Kn + 15) // 16 * 16)
+    thr0 = int(idx.params.dense_threshold)
+    idx.set_dense_threshold(n)
+    outs = [torch.empty_like(field), torch.empty_like(field)]
+    ssd = torch.empty_like(field)
+    # frame t0's field by the full search; a warm-up ring frame; then the
+    # timed frames, each with the field before it as prev
+    idx.full_search(frames[t0], out=outs[0], ssd=ssd)
+    idx.match_frame(frames[t0 + 1], prev=outs[0], out=outs[1], ssd=ssd)
+    torch.cuda.synchronize()
+    idx.reset_stats()
+    idx.set_profiling(True)
+    cur = 0
+    w0 = time.perf_counter()
+    for i in range(nframes):
+        idx.match_frame(frames[t0 + 1 + i], prev=outs[cur], out=outs[1 - cur], ssd=ssd)
+        cur = 1 - cur
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    prof = idx.profile()
+    idx.set_profiling(False)
+    st = idx.stats()
+    idx.set_dense_threshold(thr0)
+    Q = hq * wq
+    rq = st["ring_queries"]
+    per = {}
+    # k_scan: per ring query its record, list entry, patch, Qc and the match
+    # written; per candidate of the smallest ring its pivot row (contiguous in
+    # the ring-ordered layout); per survivor its index and reference row
+    sb = (rq * (16 + 4 + Dp + 4 + 8) + st["sum_mstar_ring"] * 4 * kr +
+          st["sum_survivors"] * (4 + Dp)) / nframes
+    for k in ("extract", "ring", "scan", "dense"):
+        if prof[k]["launches"]:
+            per[k] = prof[k]["ms"] / prof[k]["launches"]
+    # the ring phase: patch + Qc + prev + the previous match's row + record
+    # per query; the binary searches' line reads counted apart (probes)
+    rb = Q * (Dp + 4 + 4 + Dp + 16)
+    inline = "scan" not in per            # the ring kernel scanned its own ring queries
+    scan_kernel = "k_ring (ring phase, then the ring scan of its own queries)" if inline \
+        else "k_scan"
+    scan_ms = per["ring"] if inline else per["scan"]
+    scan_bytes = sb + (rb if inline else 0)
+    res = {"threshold": n, "frames": nframes, "ms_per_frame": 1e3 * wall / nframes,
+           "kernels_ms_per_frame": per,
+           "ring_queries_per_frame": rq / nframes, "no_prior_per_frame": st["no_prior"] / nframes,
+           "mean_mstar": st["sum_mstar_ring"] / max(1, rq),
+           "mean_survivors": st["sum_survivors"] / max(1, rq),
+           "probes_per_query": st["bsearch_probes"] / max(1, rq),
+           "ring_scan": {"kernel": scan_kernel, "algorithmic_bytes": scan_bytes, "ms": scan_ms,
+                         "GBps": scan_bytes / (scan_ms * 1e-3) / 1e9,
+                         "hbm_frac": scan_bytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "layout": "ring-ordered pivot rows, %d words per entry" % kr,
+                         "note": "per ring query 32 B + patch; per candidate of the smallest "
+                                 "ring its pivot row; per survivor its index and row"
+                                 + ("; plus the ring phase's bytes per query" if inline else "")}}
+    log_fn(f"ring path forced: {res['ms_per_frame']:.2f} ms/frame, ring scan "
+           f"{res['ring_scan']['GBps']:.0f} GB/s, mean m* {res['mean_mstar']:.0f}")
+    return res
+
+
+def uhd_batch_graph(dev, steps, log_fn):
+    """The uneven batch: one 3840x2160 gray frame and four 640x360 gray
+    frames per step (12x12 patches at stride 2, n = 262,144, K = 48), all
+    five in one riann_match_batch, captured once as a HIP graph and replayed
+    with each step's frames copied into the captured input buffers.  Beside
+    it the same steps eagerly as one batch, and as five separate per-frame
+    calls.  Frame 0 of every video is a full search; the 4K video's scene
+    cuts (every 50 frames) fall outside the timed steps."""
+    import torch
+    import gen
+    import paper_1508_07953_amd as riann
+    t0 = time.time()
+    nfr = steps + 2
+    wl = gen.make_workload("uhd_mix", frames=nfr)
+    vids = [wl.video] + [gen.make_video("uhd_mix", stream=1 + i, H=360, W=640, frames=nfr)
+                         for i in range(4)]
+    frames = [[torch.from_numpy(v.frame(t)).to(dev) for t in range(nfr)] for v in vids]
+    idx = riann.Index.build(wl.ref, wl.keys, patch=12, channels=1, stride=2)
+    log_fn(f"uhd batch: frames and index in {time.time() - t0:.1f}s")
+    shapes = [idx.field_shape(int(f[0].shape[0]), int(f[0].shape[1])) for f in frames]
+    Q = sum(h * w for h, w in shapes)
+    outs = [[torch.empty(s, dtype=torch.int32, device=dev) for _ in range(2)] for s in shapes]
+    ssds = [torch.empty(s, dtype=torch.int32, device=dev) for s in shapes]
+    f_in = [torch.empty_like(frames[v][0]) for v in range(len(vids))]
+
+    def items(src, par, mode=riann.MODE_RING):
+        it = []
+        for v in range(len(vids)):
+            d = dict(frame=src[v], out=outs[v][1 - par], ssd=ssds[v], mode=mode)
+            if mode == riann.MODE_RING:
+                d["prev"] = outs[v][par]
+            it.append(d)
+        return it
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for v in range(len(vids)):
+            f_in[v].copy_(frames[v][0])
+        idx.match_batch(items(f_in, 1, riann.MODE_FULL), stream=s)     # fields in outs[.][0]
+        idx.match_batch(items(f_in, 0), stream=s)                      # warm-up, both parities
+        idx.match_batch(items(f_in, 1), stream=s)
+    s.synchronize()
+    graphs = []
+    for par in (0, 1):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            idx.match_batch(items(f_in, par), stream=s)
+        graphs.append(g)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(run_step):
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for i in range(steps):
+                run_step(1 + i, i % 2)
+            e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def graph_step(t, par):
+        for v in range(len(vids)):
+            f_in[v].copy_(frames[v][t])
+        graphs[par].replay()
+
+    def batch_step(t, par):
+        idx.match_batch(items([frames[v][t] for v in range(len(vids))], par), stream=s)
+
+    def single_step(t, par):
+        for v in range(len(vids)):
+            idx.match_frame(frames[v][t], prev=outs[v][par], out=outs[v][1 - par], ssd=ssds[v],
+                            stream=s)
+
+    res = {"workload": "one 3840x2160 + four 640x360 gray frames per step, 12x12 patches, "
+                       "stride 2, n=262144, K=48, %d queries per step" % Q,
+           "steps": steps}
+    # two rounds in turn, the better of each kept (the first steps of a run
+    # can meet lower clocks)
+    for _ in range(2):
+        for name, fn in (("separate_frames", single_step), ("batch_eager", batch_step),
+                         ("graph", graph_step)):
+            ms = timed(fn)
+            if name not in res or ms < res[name]["ms_per_step"]:
+                res[name] = {"ms_per_step": ms, "patches_per_s": Q / (ms * 1e-3)}
+    # the graph's fields of the last step equal the eager per-frame search's
+    last = steps % 2
+    g_out = [outs[v][last].clone() for v in range(len(vids))]
+    timed(single_step)
+    res["graph_equals_eager"] = all(torch.equal(g_out[v], outs[v][last])
+                                    for v in range(len(vids)))
+    idx.close()
+    log_fn(f"uhd batch: graph {res['graph']['ms_per_step']:.2f} ms/step, eager batch "
+           f"{res['batch_eager']['ms_per_step']:.2f}, separate "
+           f"{res['separate_frames']['ms_per_step']:.2f}")
+    return res
 
 
 def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=None,
@@ -303,6 +454,12 @@ def main():
                     help="skip the serving-vs-plain comparison")
     ap.add_argument("--serving-streams", type=int, default=64)
     ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--ring-forced-frames", type=int, default=3,
+                    help="frames matched with every query on the ring path (threshold n) "
+                         "after the timed region; 0 skips")
+    ap.add_argument("--uhd-batch-steps", type=int, default=6,
+                    help="steps of the 4K + 4 x 640x360 batch as one captured HIP graph; "
+                         "0 skips")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="after the timed region, run one plain device copy of this many "
                          "MiB (reference point for hardware byte counters)")
@@ -361,7 +518,10 @@ def main():
             fr.append(frames[t])
             pv.append(f_prev)
             f_prev = o
+        shape = tune.tune_shape(idx, fr, use_cache=False, write_cache=False)
+        log(f"tuned dense block shape {shape['shape']}: {shape['ms']}")
         tuned = tune.tune_threshold(idx, fr, pv, use_cache=False, write_cache=False)
+        tuned["shape"] = shape
         log(f"tuned dense threshold {tuned['threshold']}: {tuned['ms']}")
         torch.cuda.synchronize()
     idx.reset_stats()
@@ -385,6 +545,30 @@ def main():
     prof = idx.profile() if not args.no_profile else None
     idx.set_profiling(False)
     st = idx.stats()
+    # the same frames by the exhaustive search alone (no ring phase), right
+    # after the timed region and timed the same way (a step's events, the
+    # dense step's events): the same exact field, so this is what the ring
+    # phase costs or buys on this workload
+    fo = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    fs = torch.empty((hq, wq), dtype=torch.int32, device=dev)
+    if not args.no_profile:
+        idx.set_profiling("dense")
+    fevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(K)]
+    torch.cuda.synchronize()
+    f_start = time.perf_counter()
+    for i in range(K):
+        fevs[i][0].record(stream)
+        idx.full_search(frames[W + 1 + i], out=fo, ssd=fs)
+        fevs[i][1].record(stream)
+    torch.cuda.synchronize()
+    f_wall = time.perf_counter() - f_start
+    idx.set_profiling(False)
+    flat = np.array([a.elapsed_time(b) for a, b in fevs])
+    full_every = {"ms_per_frame": 1000.0 * f_wall / K, "frames": K,
+                  "p50_frame_ms": float(np.percentile(flat, 50)),
+                  "note": "riann_full_search on the timed frames right after the timed region, "
+                          "timed the same way: the same exact field without the ring phase"}
     prof_all = None
     if not args.no_profile:
         # per-kernel breakdown: an untimed pass over the first timed frames
@@ -415,13 +599,17 @@ def main():
                    "frames_timed": K, "mode": "plain (one frame at a time)",
                    "dense_layout": args.dense_layout},
         "frames_per_s": K / wall,
+        "full_search_every_frame": full_every,
         "p50_frame_ms": float(np.percentile(lat, 50)),
         "p99_frame_ms": float(np.percentile(lat, 99)),
         "routing": {"ring_queries": st["ring_queries"], "dense_queries": st["dense_queries"],
                     "bound_routed": st["bound_routed"],
                     "mean_mstar_evaluated": st["sum_mstar"] / max(1, st["queries"] - st["bound_routed"]),
                     "dense_threshold": int(idx.params.dense_threshold),
-                    "autotune_ms_per_frame": tuned["ms"] if tuned else None},
+                    "autotune_ms_per_frame": tuned["ms"] if tuned else None,
+                    "dense_shape": (tuned["shape"]["shape"] if tuned else
+                                    list(idx.dense_shapes()[0][idx.dense_shapes()[1]])),
+                    "dense_shape_ms_per_full_frame": tuned["shape"]["ms"] if tuned else None},
     }
     if prof is not None:
         n, D = int(idx.params.n_ref), wl.D
@@ -479,8 +667,14 @@ def main():
                                      "smallest ring 4 B index + the Kp-word pivot row; per "
                                      "survivor its row"}
         result["secondary_kernels"] = sec
+    if args.ring_forced_frames > 0 and W + 1 + args.ring_forced_frames < nframes + 1:
+        result["ring_path_forced"] = ring_path_forced(
+            idx, wl, frames, bufs[cur], W, min(args.ring_forced_frames, nframes - W - 1),
+            hq, wq, log)
     if not args.no_extras:
         extras(args, result, idx, wl, frames, bufs[cur], H, Wd, hq, wq, Q, K, W, dev, stream, log)
+    if args.uhd_batch_steps > 0:
+        result["uhd_batch_graph"] = uhd_batch_graph(dev, args.uhd_batch_steps, log)
     if not args.no_serving:
         result["serving_vs_plain"] = serving_compare(dev, args.serving_streams, 3,
                                                      args.serving_seconds, log)

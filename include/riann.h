@@ -414,10 +414,13 @@ riann_status_t riann_destroy(riann_index_t h);
  * totals; other levels return RIANN_E_INVALID.  riann_get_profile synchronises, converts the pending event
  * pairs into milliseconds and returns the totals per kernel since profiling
  * was turned on.  Events are reused across calls.
- * Kernels: RIANN_K_RING (ring phase), RIANN_K_SCAN (ring scan and
- * verification), RIANN_K_DENSE (dense search of routed queries),
- * RIANN_K_FULL (dense search of whole frames), RIANN_K_EXTRACT (patch
- * extraction, run first for every frame).
+ * Kernels: RIANN_K_RING (ring phase; with the default ring-ordered pivot
+ * rows and the row-layout dense search it also runs the ring scan of its
+ * ring-routed queries), RIANN_K_SCAN (ring scan and verification as a launch
+ * of its own: RIANN_FLAG_GATHER_SCAN, RIANN_FLAG_COLUMN_DENSE or k-NN
+ * fields), RIANN_K_DENSE (dense search of routed queries), RIANN_K_FULL
+ * (dense search of whole frames), RIANN_K_EXTRACT (patch extraction, run
+ * first for every frame; in a ring launch it also routes queries).
  */
 #define RIANN_K_RING 0
 #define RIANN_K_SCAN 1

@@ -5,6 +5,7 @@
 #include "riann_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -140,10 +141,11 @@ int64_t index_bytes(int64_t n, int D, int K, uint32_t flags) {
     const int64_t pivr = (K > 0 && !(flags & RIANN_FLAG_GATHER_SCAN))
                              ? (int64_t)K * n16 * pivr_words(K) * 4 + 256 : 0;
     return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
-           n_rows * (Dp + 12) + (int64_t)K * 4 + ST_COUNT * 8 + 65536 + 4096 + pivr;
+           n_rows * (Dp + 12) + (int64_t)K * 4 + (int64_t)kStatWords * 8 + 65536 + 4096 + pivr +
+           (int64_t)std::max(K, 1) * kRouteStride * 4 + 256;
 }
 
-int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 64 + 8) + 8192; }
+int64_t work_bytes(int64_t Q, int Dp) { return Q * ((int64_t)Dp + 4 + 1 + 1 + 64 + 8) + 8192; }
 
 // host pre-processing: pivot table and sorted per-key lists
 void build_tables(riann_index *h) {
@@ -276,6 +278,46 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                                                      [](uint32_t x, uint64_t e) { return x < e; }) - t);
         }
     }
+    // routing rows in square-root space (the extraction kernel's test): per
+    // key, origin o = floor(sqrt(vmin)) and bucket width 2^e, the smallest
+    // with o + B 2^e > sqrt(vmax) (e >= -16); F[j] = #{entries a :
+    // sqrt(a) < x_j}, x_j = o + j 2^e, i.e. entries below ceil(x_j^2), which
+    // integer arithmetic gives exactly
+    std::vector<uint32_t> Rt((size_t)std::max(K, 1) * kRouteStride, 0u);
+    for (int k = 0; k < K; ++k) {
+        const uint32_t *t = &h->T[(size_t)k * n];
+        const uint64_t vmin = t[0], vmax = t[n - 1];
+        uint64_t o = (uint64_t)std::sqrt((double)vmin);
+        while (o * o > vmin) --o;
+        while ((o + 1) * (o + 1) <= vmin) ++o;
+        // x_j^2 > a for every entry once x_j^2 > vmax
+        auto above_max = [&](int e, uint64_t j) {
+            if (e >= 0) {
+                const uint64_t x = o + (j << e);
+                return x * x > vmax;
+            }
+            const uint64_t m = 1ull << (-e), x = o * m + j;   // x_j = x / m
+            return x * x > vmax * m * m;
+        };
+        int e = -16;
+        while (!above_max(e, kRouteBuckets)) ++e;
+        uint32_t *row = &Rt[(size_t)k * kRouteStride];
+        const float of = (float)o, inv = std::ldexp(1.0f, -e);
+        std::memcpy(&row[0], &of, 4);
+        std::memcpy(&row[1], &inv, 4);
+        for (int j = 0; j <= kRouteBuckets; ++j) {
+            uint64_t c2;   // ceil(x_j^2)
+            if (e >= 0) {
+                const uint64_t x = o + ((uint64_t)j << e);
+                c2 = x * x;
+            } else {
+                const uint64_t m = 1ull << (-e), x = o * m + (uint64_t)j, d = m * m;
+                c2 = (x * x + d - 1) / d;
+            }
+            row[2 + j] = (uint32_t)(std::lower_bound(t, t + n, c2,
+                                                     [](uint32_t a, uint64_t v) { return a < v; }) - t);
+        }
+    }
     int64_t s0l = 1;   // sample stride in lines: samples, bound rows, key rows and
                        // key Rc of all keys fit 64 KB of LDS
     while ((int64_t)K * (((n + 16 * s0l - 1) / (16 * s0l) + 3) / 4 * 4 + lbS + Dp / 4 + 1) * 4 >
@@ -295,14 +337,15 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szT = (size_t)std::max<int64_t>(K * n16, 1) * 4,
                  szP = (size_t)std::max<int64_t>(K * n, 1) * 4,
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
-                 szS = ST_COUNT * 8, szTs = Ts.size() * 4, szLb = Lb.size() * 4;
+                 szS = (size_t)kStatWords * 8, szTs = Ts.size() * 4, szLb = Lb.size() * 4;
     const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8;
     const bool pivr = K > 0 && !(h->prm.flags & RIANN_FLAG_GATHER_SCAN);
     const size_t szPivR = pivr ? (size_t)K * n16 * pivr_words(K) * 4 : 0;
-    size_t off[15], tot = 0;
-    const size_t sz[15] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
-                           szLb, szPivR};
-    for (int i = 0; i < 15; ++i) {
+    const size_t szRt = Rt.size() * 4;
+    size_t off[16], tot = 0;
+    const size_t sz[16] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
+                           szLb, szPivR, szRt};
+    for (int i = 0; i < 16; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -330,6 +373,8 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.lbS = lbS;
     h->dix.exact_mstar = (h->prm.flags & RIANN_FLAG_EXACT_MSTAR) ? 1 : 0;
     h->dix.PivR = pivr ? (const uint32_t *)(b + off[14]) : nullptr;
+    h->dix.Rt = (const uint32_t *)(b + off[15]);
+    h->dix.rtS = kRouteStride;
     h->dix.KR = pivr ? pivr_words(K) : 0;
     h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.Rfr = (const int8_t *)(b + off[11]);
@@ -355,6 +400,7 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         {b + off[7], Rf.data(), szRv},          {b + off[8], Rk.data(), szRc},
         {b + off[9], Ts.data(), (size_t)K * ns * 4},
         {b + off[13], Lb.data(), szLb},
+        {b + off[15], Rt.data(), szRt},
         {b + off[10], Hf.data(), szHf},
         {b + off[11], Rfr.data(), szRfr},
         {b + off[12], Rci.data(), szRci},
@@ -410,6 +456,7 @@ Work carve_work(char *b, int64_t cap, int Dp) {
     nw.patches = (uint8_t *)(b + o);  o = round_up(o + cap * Dp, 256);
     nw.qc = (int32_t *)(b + o);       o = round_up(o + cap * 4, 256);
     nw.fid = (uint8_t *)(b + o);      o = round_up(o + cap, 256);
+    nw.route = (uint8_t *)(b + o);    o = round_up(o + cap, 256);
     nw.rec = (uint4 *)(b + o);        o = round_up(o + cap * 16, 256);
     nw.rec2 = (uint4 *)(b + o);       o = round_up(o + cap * 48, 256);
     nw.ring_list = (uint32_t *)(b + o); o = round_up(o + cap * 4, 256);
@@ -526,6 +573,7 @@ struct KTimer {
 riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn = 1,
                          const Work *preset = nullptr) {
     fb.knn = knn;
+    fb.dense_masked = 0;
     int64_t q = 0;
     int32_t t = 0;
     bool all_full = true;
@@ -551,22 +599,28 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     }
     hipError_t e;
     const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
+    // the row-layout search takes the queries in order and skips the
+    // ring-scanned ones by their route codes: no dense list is built
+    fb.dense_masked = rows && !all_full ? 1 : 0;
     const bool timed = preset == nullptr;
+    // one threshold for the whole launch: the extraction kernel routes on it
+    // and the ring kernel decides the rest with it
+    const int64_t threshold = h->threshold.load();
     {
         // the extraction kernel also clears the ring and dense list counters
         KTimer tm(h, RIANN_K_EXTRACT, st, timed);
-        e = launch_extract(h->dix, fb, w, st);
+        e = launch_extract(h->dix, fb, w, threshold, h->dstats, st);
         tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     }
     if (!all_full) {
         {
             KTimer tm(h, RIANN_K_RING, st, timed);
-            e = launch_ring(h->dix, fb, w, h->dstats, h->threshold.load(), st);
+            e = launch_ring(h->dix, fb, w, h->dstats, threshold, st);
             tm.stop();
             if (e != hipSuccess) return hip_fail(e, "k_ring launch");
         }
-        {
+        if (!ring_scans_inline(h->dix, fb)) {
             KTimer tm(h, RIANN_K_SCAN, st, timed);
             e = knn > 1 ? launch_scan_knn(h->dix, fb, w, h->dstats, st)
                         : launch_scan(h->dix, fb, w, h->dstats, st);
@@ -777,9 +831,13 @@ riann_status_t riann_get_stats(riann_index_t h, riann_stats_t *s) {
     DeviceGuard g(h->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "device sync");
-    unsigned long long v[ST_COUNT];
-    e = hipMemcpy(v, h->dstats, sizeof(v), hipMemcpyDeviceToHost);
+    std::vector<unsigned long long> rep((size_t)kStatWords);
+    e = hipMemcpy(rep.data(), h->dstats, rep.size() * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "stats copy");
+    unsigned long long v[ST_COUNT] = {};
+    for (int slot = 0; slot < ST_COUNT; ++slot)
+        for (int r = 0; r < kStatReplicas; ++r)
+            v[slot] += rep[((size_t)slot * kStatReplicas + r) * kStatStride];
     const uint64_t fq = h->full_queries.load();
     s->frames = h->frames.load();
     s->queries = v[ST_QUERIES] + fq;
@@ -800,7 +858,7 @@ riann_status_t riann_reset_stats(riann_index_t h) {
     DeviceGuard g(h->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "device sync");
-    e = hipMemset(h->dstats, 0, ST_COUNT * 8);
+    e = hipMemset(h->dstats, 0, (size_t)kStatWords * 8);
     if (e != hipSuccess) return hip_fail(e, "stats clear");
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "device sync");
@@ -1096,10 +1154,11 @@ riann_status_t riann_match_paper(riann_index_t h, const uint8_t *frame_dev, int3
     fb.ntiles = ((fd.Wq + kExtTX - 1) / kExtTX) * ((fd.Hq + kExtTY - 1) / kExtTY);
     fb.all_full = 0;
     fb.knn = 1;
+    fb.dense_masked = 0;
     Work w;
     s = get_work(h, st, Q, &w);
     if (s != RIANN_OK) return s;
-    hipError_t e = launch_extract(h->dix, fb, w, st);
+    hipError_t e = launch_extract(h->dix, fb, w, -1, nullptr, st);   // no ring phase: no routing
     if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     const size_t nn = (size_t)h->n * (size_t)h->n;
     const char *b = (const char *)pmem;

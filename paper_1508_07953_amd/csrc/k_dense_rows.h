@@ -369,8 +369,11 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     __shared__ __attribute__((aligned(16))) int32_t s_h0[ST * kTile];
     __shared__ __attribute__((aligned(16))) int32_t s_h1[ST * kTile];
 
-    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
-    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
+    // the queries in order (a full search, or a ring launch whose route codes
+    // mark the ring-scanned ones), or the dense list
+    const bool natural = fb.all_full || fb.dense_masked;
+    const uint32_t *list = natural ? nullptr : w.dense_list;
+    const uint32_t count = natural ? (uint32_t)fb.Q : w.counters[1];
     // whole chunks first, then the split ones, nsplit blocks per chunk, each
     // over one part of the reference stages (consecutive blocks take
     // consecutive parts and land on different XCDs, so each XCD's L2 holds
@@ -383,6 +386,13 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     const uint32_t chunk = whole ? bx : plan.whole + (bx - plan.whole) / plan.parts;
     const uint32_t qbase = chunk * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
+    if (!fb.all_full && fb.dense_masked) {
+        // a chunk whose queries the ring scan answers, all of them, has no work
+        bool any = false;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)kBlockQ; i += Cfg::block)
+            any = any || (qbase + i < count && w.route[qbase + i] != kRouteScan);
+        if (!__syncthreads_or(any)) return;
+    }
 
     // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -487,7 +497,8 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
                 const int c = h + 4 * p + sub;
                 rr[p] = make_uint2(__shfl(rc[qb].x, c, 64), __shfl(rc[qb].y, c, 64));
                 qq[p] = (uint32_t)__shfl((int)qid[qb], c, 64);
-                ll[p] = wbase + (uint32_t)(qb * 32 + c) < count;
+                ll[p] = wbase + (uint32_t)(qb * 32 + c) < count &&
+                        (fb.all_full || !fb.dense_masked || w.route[qq[p]] != kRouteScan);
                 C[p].issue(ix, w, qq[p], rr[p], ll[p], r);
             }
 #pragma unroll
@@ -506,15 +517,17 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
 template <int DP, int BQ>
 __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Work w, uint32_t slots) {
     constexpr uint32_t kBlockQ = BQ;                 // queries per chunk of the row kernel
-    const uint32_t *list = fb.all_full ? nullptr : w.dense_list;
-    const uint32_t count = fb.all_full ? (uint32_t)fb.Q : w.counters[1];
+    const bool natural = fb.all_full || fb.dense_masked;
+    const uint32_t *list = natural ? nullptr : w.dense_list;
+    const uint32_t count = natural ? (uint32_t)fb.Q : w.counters[1];
     const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
     const int nsplit = (int)plan.parts;
     const int lane = threadIdx.x & 63, r = lane & 15;
     for (uint32_t base = plan.whole * kBlockQ + blockIdx.x * 16u; base < count;
          base += gridDim.x * 16u) {
         const uint32_t i = base + (threadIdx.x >> 4);
-        const bool live = i < count;
+        const bool live = i < count &&
+                          (fb.all_full || !fb.dense_masked || w.route[i] != kRouteScan);
         const uint32_t q = live ? (list ? list[i] : i) : 0u;
         uint2 rec = make_uint2(0u, 0u);
         if (live) {

@@ -14,7 +14,20 @@
 // them into place (v_alignbyte); other shapes assemble byte by byte.  Block 0
 // also clears the launch's ring and dense list counters, which the ring
 // kernel after it fills.
+//
+// In a launch with a ring phase each thread also routes its query while the
+// patch is in its registers (Algorithm 1's first steps): a full-search frame
+// or a missing previous match goes to the dense search; otherwise the radius
+// c = SSD(q, R[prev]), every key distance b_k and each key's ring-size lower
+// bound from its bucket counts (the ring kernel's own test) are computed, and
+// a query whose every ring certainly holds more than the routing threshold's
+// candidates goes to the dense search too.  That certainty comes from each
+// key's routing row: counts of its sorted list over buckets of sqrt(a), so a
+// ring -- sqrt(a) within sqrt(c) of sqrt(b) -- is bounded from inside by
+// whole buckets after two square roots.  The ring kernel then works only
+// on the queries left to it.
 #include "riann_internal.h"
+#include "ring_math.h"
 
 namespace riann {
 
@@ -29,6 +42,129 @@ __host__ __device__ __forceinline__ int ext_ldw(int p, int C, int s) {
 }
 __host__ __device__ __forceinline__ size_t ext_lds_bytes(int p, int C, int s) {
     return (size_t)((kTY - 1) * s + p) * ext_ldw(p, C, s) + 4;
+}
+
+// Routing tables staged in LDS after the frame region (at a 16-byte
+// boundary): each key's routing row (kRouteStride words), the key rows
+// (DP / 4 words each) and the keys' Rc.  Staged when the launch routes on
+// bounds.
+__host__ __device__ __forceinline__ size_t route_lds_offset(int p, int C, int s) {
+    return (ext_lds_bytes(p, C, s) + 15) & ~(size_t)15;
+}
+__host__ __device__ __forceinline__ size_t route_lds_bytes(int K, int DP) {
+    return (size_t)K * (kRouteStride + DP / 4 + 1) * 4;
+}
+__device__ __forceinline__ bool route_codes_on(const FrameBatch &fb, int64_t threshold) {
+    return threshold >= 0 && !fb.all_full;
+}
+__device__ __forceinline__ bool route_tables_on(const DevIndex &ix, const FrameBatch &fb,
+                                                int64_t threshold) {
+    return route_codes_on(fb, threshold) && fb.knn == 1 && ix.K > 0 && !ix.exact_mstar;
+}
+
+template <int DP>
+__device__ __forceinline__ void stage_route_tables(const DevIndex &ix, uint32_t *tab) {
+    const int nlb = ix.K * kRouteStride;          // multiple of 4
+    for (int i = threadIdx.x; i < nlb / 4; i += kTX * kTY)
+        reinterpret_cast<uint4 *>(tab)[i] = reinterpret_cast<const uint4 *>(ix.Rt)[i];
+    uint32_t *keys = tab + nlb;
+    for (int i = threadIdx.x; i < ix.K * (DP / 16); i += kTX * kTY) {
+        const int k = i / (DP / 16), part = i - k * (DP / 16);
+        reinterpret_cast<uint4 *>(keys)[i] =
+            reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)ix.keys[k] * ix.Dp)[part];
+    }
+    for (int k = threadIdx.x; k < ix.K; k += kTX * kTY)
+        keys[ix.K * (DP / 4) + k] = (uint32_t)ix.Rc[ix.keys[k]];
+}
+
+// The route of one query, in two steps so that its loads are in flight
+// early.  route_begin (before the patch is assembled): the part decided
+// without rings -- full-search frame, k-NN launch (the ring kernel takes the
+// k-NN radius), no valid previous match, no bound routing in this launch --
+// or kRouteNeedBounds, with the previous match's index, row and Rc loads
+// issued.  route_finish: c = SSD(q, R[prev]) and every key's ring tested
+// against the threshold with the key rows staged in LDS (v_dot4).
+constexpr uint8_t kRouteNeedBounds = 0xFE;
+template <int DP>
+struct RoutePrefetch {
+    uint8_t code = kRouteFull;
+    uint4 row[DP / 16];
+    int rc = 0;
+};
+
+template <int DP>
+__device__ __forceinline__ void route_begin(const DevIndex &ix, const FrameBatch &fb,
+                                            const FrameDesc &fa, int64_t ql, int64_t threshold,
+                                            RoutePrefetch<DP> &rp) {
+    if (fa.mode == kModeFull) { rp.code = kRouteFull; return; }
+    if (fb.knn != 1) { rp.code = kRouteRing; return; }
+    if (!fa.prev) { rp.code = kRouteNoPrior; return; }
+    const int32_t pv = fa.prev[ql];
+    if (pv < 0 || (int64_t)pv >= ix.n) { rp.code = kRouteNoPrior; return; }
+    if (!route_tables_on(ix, fb, threshold)) { rp.code = kRouteRing; return; }
+    rp.code = kRouteNeedBounds;
+    const uint4 *src = reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)pv * ix.Dp);
+#pragma unroll
+    for (int i = 0; i < DP / 16; ++i) rp.row[i] = src[i];
+    rp.rc = ix.Rc[pv];
+}
+
+template <int DP>
+__device__ __forceinline__ uint8_t route_finish(const DevIndex &ix, const uint32_t (&a)[DP / 4],
+                                                int Qc, int64_t threshold, const uint32_t *tab,
+                                                const RoutePrefetch<DP> &rp) {
+    if (rp.code != kRouteNeedBounds) return rp.code;
+    int d = 0;
+#pragma unroll
+    for (int i = 0; i < DP / 16; ++i) {
+        d = __builtin_amdgcn_sdot4((int)a[4 * i + 0], (int)rp.row[i].x, d, false);
+        d = __builtin_amdgcn_sdot4((int)a[4 * i + 1], (int)rp.row[i].y, d, false);
+        d = __builtin_amdgcn_sdot4((int)a[4 * i + 2], (int)rp.row[i].z, d, false);
+        d = __builtin_amdgcn_sdot4((int)a[4 * i + 3], (int)rp.row[i].w, d, false);
+    }
+    const uint32_t c = (uint32_t)(Qc + rp.rc + 2 * d);
+    const float sc = sqrtf((float)c);             // SSDs are below 2^24: exact as fp32
+    const uint32_t *keys = tab + ix.K * kRouteStride, *krc = keys + ix.K * (DP / 4);
+    for (int k = 0; k < ix.K; ++k) {
+        const uint32_t b = (uint32_t)(Qc + (int)krc[k] +
+                                      2 * dot_row<DP>(a, reinterpret_cast<const int8_t *>(
+                                                             keys + k * (DP / 4))));
+        // a ring that may hold no more than the threshold's candidates: the
+        // ring kernel decides
+        if ((int64_t)route_lower_bound(tab + k * kRouteStride, sqrtf((float)b), sc) <= threshold)
+            return kRouteRing;
+    }
+    return kRouteBound;
+}
+
+// With the dense search reading route codes (fb.dense_masked) this kernel
+// also counts what it routed: per block, the queries, and those it sent to
+// the dense search as full-search, no-prior (each with m* = n, the whole set
+// as its ring) and bound-routed queries.  `code` is 0xFF for a thread
+// without a query.  Every thread of the block calls it (one barrier).
+__device__ __forceinline__ void count_routes(const DevIndex &ix, unsigned long long *stats,
+                                             uint8_t code) {
+    constexpr int kWv = kTX * kTY / 64;
+    __shared__ unsigned long long s_rc[kWv][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long vq = __ballot(code != 0xFF), fu = __ballot(code == kRouteFull),
+                             np = __ballot(code == kRouteNoPrior), bd = __ballot(code == kRouteBound);
+    if (lane == 0) {
+        s_rc[wv][0] = (unsigned long long)__popcll(vq);
+        s_rc[wv][1] = (unsigned long long)__popcll(fu);
+        s_rc[wv][2] = (unsigned long long)__popcll(np);
+        s_rc[wv][3] = (unsigned long long)__popcll(bd);
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long v[4] = {0, 0, 0, 0};
+        for (int i = 0; i < kWv; ++i)
+            for (int j = 0; j < 4; ++j) v[j] += s_rc[i][j];
+        const int slot[5] = {ST_QUERIES, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_BOUND};
+        const unsigned long long val[5] = {v[0], v[1] + v[2] + v[3], v[2],
+                                           v[2] * (unsigned long long)ix.n, v[3]};
+        if (val[threadIdx.x]) stat_add(stats, slot[threadIdx.x], val[threadIdx.x]);
+    }
 }
 
 // The block's tile: its frame, first query position and extent, and the
@@ -76,47 +212,63 @@ __device__ __forceinline__ ExtTile load_tile(const DevIndex &ix, const FrameBatc
 }
 
 template <int DP>
-__global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb, Work w) {
-    extern __shared__ uint8_t s_tile[];
+__global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb, Work w,
+                                                     int64_t threshold,
+                                                     unsigned long long *__restrict__ stats) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t s_tile[];
     if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
     const int p = ix.p, C = ix.C, s = ix.s, D = ix.D;
+    uint32_t *tab = reinterpret_cast<uint32_t *>(s_tile + route_lds_offset(p, C, s));
+    if (route_tables_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
     const ExtTile t = load_tile(ix, fb, s_tile);
     const FrameDesc &fa = *t.fa;
     const int f = t.f, qx0 = t.qx0, qy0 = t.qy0, ldw = t.ldw;
 
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    if (tx >= t.nqx || ty >= t.nqy) return;
-    const uint8_t *win = s_tile + (ty * s) * ldw + (tx * s) * C;
-    const int rowlen = p * C;
-    uint32_t wd[DP / 4];
-    int dy = 0, rem = 0;
-    int sa2 = 0, sa = 0;
-#pragma unroll
-    for (int i = 0; i < DP / 4; ++i) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int k = 4 * i + b;
-            const bool ok = k < D;
-            const uint32_t v = ok ? ((uint32_t)win[dy * ldw + rem] ^ 0x7Fu) : 0u;
-            word |= v << (8 * b);
-            const bool wrap = rem + 1 == rowlen;
-            rem = wrap ? 0 : rem + 1;
-            dy = wrap ? dy + 1 : dy;
-            if (dy >= p) dy = p - 1;             // k >= D: stay inside the window
-        }
-        wd[i] = word;
-        sa2 = __builtin_amdgcn_sdot4((int)word, (int)word, sa2, false);
-        sa = __builtin_amdgcn_sdot4((int)word, 0x01010101, sa, false);
-    }
+    const bool valid = tx < t.nqx && ty < t.nqy;
+    const bool codes = route_codes_on(fb, threshold);
     const int64_t q = fa.qbase + (int64_t)(qy0 + ty) * fa.Wq + (qx0 + tx);
-    uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
+    RoutePrefetch<DP> rp;
+    if (valid && codes) route_begin<DP>(ix, fb, fa, q - fa.qbase, threshold, rp);
+    uint8_t code = 0xFF;
+    if (valid) {
+        const uint8_t *win = s_tile + (ty * s) * ldw + (tx * s) * C;
+        const int rowlen = p * C;
+        uint32_t wd[DP / 4];
+        int dy = 0, rem = 0;
+        int sa2 = 0, sa = 0;
 #pragma unroll
-    for (int i = 0; i < DP / 16; ++i)
-        dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
-    // padding bytes are a = 0 and add nothing to the sums
-    w.qc[q] = sa2 + 2 * sa + D;
-    w.fid[q] = (uint8_t)f;
+        for (int i = 0; i < DP / 4; ++i) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = 4 * i + b;
+                const bool ok = k < D;
+                const uint32_t v = ok ? ((uint32_t)win[dy * ldw + rem] ^ 0x7Fu) : 0u;
+                word |= v << (8 * b);
+                const bool wrap = rem + 1 == rowlen;
+                rem = wrap ? 0 : rem + 1;
+                dy = wrap ? dy + 1 : dy;
+                if (dy >= p) dy = p - 1;         // k >= D: stay inside the window
+            }
+            wd[i] = word;
+            sa2 = __builtin_amdgcn_sdot4((int)word, (int)word, sa2, false);
+            sa = __builtin_amdgcn_sdot4((int)word, 0x01010101, sa, false);
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
+#pragma unroll
+        for (int i = 0; i < DP / 16; ++i)
+            dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
+        // padding bytes are a = 0 and add nothing to the sums
+        const int Qc = sa2 + 2 * sa + D;
+        w.qc[q] = Qc;
+        w.fid[q] = (uint8_t)f;
+        if (codes) {
+            code = route_finish<DP>(ix, wd, Qc, threshold, tab, rp);
+            w.route[q] = code;
+        }
+    }
+    if (fb.dense_masked && codes) count_routes(ix, stats, code);
 }
 
 // Window rows of P*C bytes, a whole number of words: row dy of the window
@@ -125,9 +277,13 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb
 // two of them.  The LDS allocation has a spare word for the last row's extra
 // word, whose bytes beyond the row are shifted out.
 template <int DP, int P, int C>
-__global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBatch fb, Work w) {
+__global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBatch fb, Work w,
+                                                          int64_t threshold,
+                                                          unsigned long long *__restrict__ stats) {
     extern __shared__ __attribute__((aligned(16))) uint8_t s_tile[];
     if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
+    uint32_t *tab = reinterpret_cast<uint32_t *>(s_tile + route_lds_offset(P, C, ix.s));
+    if (route_tables_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
     constexpr int PC = P * C, NW = PC / 4, D = P * PC;
     static_assert(PC % 4 == 0 && D <= DP, "whole-word window rows");
     const int s = ix.s;
@@ -138,7 +294,16 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
     const ExtTile t = load_tile(ix, fb, s_tile);
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
     const bool valid = tx < t.nqx && ty < t.nqy;
-    if (!kStage && !valid) return;
+    const FrameDesc &fa = *t.fa;
+    const int64_t q0 = fa.qbase + (int64_t)(t.qy0 + ty) * fa.Wq + t.qx0;   // row's first query
+    const int64_t q = q0 + tx;
+    // the previous match's row and Rc are fetched while the patch is built
+    const bool codes = route_codes_on(fb, threshold);
+    RoutePrefetch<DP> rp;
+    if (valid && codes) route_begin<DP>(ix, fb, fa, q - fa.qbase, threshold, rp);
+    // every thread assembles a window (those without a query read inside the
+    // tile's LDS region and write nothing): the staging and the route counts
+    // below take the whole block
     const uint32_t *words = reinterpret_cast<const uint32_t *>(s_tile);
     const int base = (ty * s) * t.ldw + (tx * s) * C;
     uint32_t wd[DP / 4];
@@ -161,9 +326,6 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
     }
 #pragma unroll
     for (int i = D / 4; i < DP / 4; ++i) wd[i] = 0u;
-    const FrameDesc &fa = *t.fa;
-    const int64_t q0 = fa.qbase + (int64_t)(t.qy0 + ty) * fa.Wq + t.qx0;   // row's first query
-    const int64_t q = q0 + tx;
     if constexpr (kStage) {
         constexpr int PW = DP / 16;               // 16-byte words per patch
         uint4 *row = s_out + ty * (kTX * PW);
@@ -179,59 +341,71 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
                 if (g / PW < t.nqx) dst[g] = row[g];
             }
         }
-        if (!valid) return;
-    } else {
+    } else if (valid) {
         uint4 *dst = reinterpret_cast<uint4 *>(w.patches + q * DP);
 #pragma unroll
         for (int i = 0; i < DP / 16; ++i)
             dst[i] = make_uint4(wd[4 * i], wd[4 * i + 1], wd[4 * i + 2], wd[4 * i + 3]);
     }
-    w.qc[q] = sa2 + 2 * sa + D;
-    w.fid[q] = (uint8_t)t.f;
+    uint8_t code = 0xFF;
+    if (valid) {
+        const int Qc = sa2 + 2 * sa + D;
+        w.qc[q] = Qc;
+        w.fid[q] = (uint8_t)t.f;
+        if (codes) {
+            code = route_finish<DP>(ix, wd, Qc, threshold, tab, rp);
+            w.route[q] = code;
+        }
+    }
+    if (fb.dense_masked && codes) count_routes(ix, stats, code);
 }
 
 template <int DP>
 hipError_t launch_extract_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                            hipStream_t st) {
-    const size_t lds = ext_lds_bytes(ix.p, ix.C, ix.s);
+                            int64_t threshold, unsigned long long *stats, hipStream_t st) {
+    const bool tables = threshold >= 0 && !fb.all_full && fb.knn == 1 && ix.K > 0 &&
+                        !ix.exact_mstar;
+    const size_t lds = tables ? route_lds_offset(ix.p, ix.C, ix.s) + route_lds_bytes(ix.K, DP)
+                              : ext_lds_bytes(ix.p, ix.C, ix.s);
     const dim3 grid((unsigned)fb.ntiles), block(kTX * kTY);
     // whole-word window rows of the common shapes
     bool fast = false;
     if constexpr (DP == 64) {
         if ((fast = ix.p == 8 && ix.C == 1))
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 8, 1>), grid, block, lds,
-                               st, ix, fb, w);
+                               st, ix, fb, w, threshold, stats);
     } else if constexpr (DP == 192) {
         if ((fast = ix.p == 8 && ix.C == 3))
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 8, 3>), grid, block, lds,
-                               st, ix, fb, w);
+                               st, ix, fb, w, threshold, stats);
     } else if constexpr (DP == 160) {
         if ((fast = ix.p == 12 && ix.C == 1))
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 12, 1>), grid, block, lds,
-                               st, ix, fb, w);
+                               st, ix, fb, w, threshold, stats);
     } else if constexpr (DP == 256) {
         if ((fast = ix.p == 16 && ix.C == 1))
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract_rows<DP, 16, 1>), grid, block, lds,
-                               st, ix, fb, w);
+                               st, ix, fb, w, threshold, stats);
     }
     if (!fast)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), grid, block, lds, st, ix, fb, w);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_extract<DP>), grid, block, lds, st, ix, fb, w,
+                           threshold, stats);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                          hipStream_t st) {
+                          int64_t threshold, unsigned long long *stats, hipStream_t st) {
     switch (ix.Dp) {
-    case 32: return launch_extract_t<32>(ix, fb, w, st);
-    case 64: return launch_extract_t<64>(ix, fb, w, st);
-    case 96: return launch_extract_t<96>(ix, fb, w, st);
-    case 128: return launch_extract_t<128>(ix, fb, w, st);
-    case 160: return launch_extract_t<160>(ix, fb, w, st);
-    case 192: return launch_extract_t<192>(ix, fb, w, st);
-    case 224: return launch_extract_t<224>(ix, fb, w, st);
-    case 256: return launch_extract_t<256>(ix, fb, w, st);
+    case 32: return launch_extract_t<32>(ix, fb, w, threshold, stats, st);
+    case 64: return launch_extract_t<64>(ix, fb, w, threshold, stats, st);
+    case 96: return launch_extract_t<96>(ix, fb, w, threshold, stats, st);
+    case 128: return launch_extract_t<128>(ix, fb, w, threshold, stats, st);
+    case 160: return launch_extract_t<160>(ix, fb, w, threshold, stats, st);
+    case 192: return launch_extract_t<192>(ix, fb, w, threshold, stats, st);
+    case 224: return launch_extract_t<224>(ix, fb, w, threshold, stats, st);
+    case 256: return launch_extract_t<256>(ix, fb, w, threshold, stats, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -13,6 +13,7 @@
 //   references inside all K rings (the intersection S) and takes the argmin
 //   of the exact SSD over S with a wavefront reduction (lowest index on ties).
 #include "riann_internal.h"
+#include "ring_math.h"
 
 #include <algorithm>
 
@@ -44,22 +45,6 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
-// <a, v> over DP bytes: a in registers, v a 16-byte aligned reference row.
-template <int DP>
-__device__ __forceinline__ int dot_row(const uint32_t (&a)[DP / 4], const int8_t *__restrict__ v) {
-    const uint4 *v4 = reinterpret_cast<const uint4 *>(v);
-    int acc = 0;
-#pragma unroll
-    for (int i = 0; i < DP / 16; ++i) {
-        uint4 r = v4[i];
-        acc = __builtin_amdgcn_sdot4((int)a[4 * i + 0], (int)r.x, acc, false);
-        acc = __builtin_amdgcn_sdot4((int)a[4 * i + 1], (int)r.y, acc, false);
-        acc = __builtin_amdgcn_sdot4((int)a[4 * i + 2], (int)r.z, acc, false);
-        acc = __builtin_amdgcn_sdot4((int)a[4 * i + 3], (int)r.w, acc, false);
-    }
-    return acc;
-}
-
 __device__ __forceinline__ uint64_t isqrt_u64(uint64_t x) {
     uint64_t s = (uint64_t)sqrt((double)x);
     while (s * s > x) --s;
@@ -77,8 +62,8 @@ __device__ __forceinline__ void ring_bounds(uint32_t b, uint32_t c, uint32_t &lo
 
 // Positions in a key's sorted list: the number of entries with x < v
 // (LE = false, the lower_bound of v) or x <= v (LE = true, the upper_bound).
-// sample_count searches the list's samples in LDS (S[i] = T[16 s0l i], ns of
-// them) and returns how many satisfy the predicate; that brackets the
+// sample_count searches the list's samples (S[i] = T[16 s0l i], ns of them,
+// a table that stays in L2) and returns how many satisfy the predicate; that brackets the
 // position (pos_bracket).  exact_pos finishes the search in global memory:
 // a binary search over the first entries of 16-entry lines, then one
 // aligned 64-byte line is read and counted.
@@ -137,67 +122,133 @@ __device__ __forceinline__ uint32_t key_dist(const uint32_t (&a)[DP / 4], int Qc
     return (uint32_t)(Qc + (int)krc[k] + 2 * d);
 }
 
-// An inner and an outer approximation of key k's ring: s = floor(sqrt(4bc))
-// lies in [s_in, s_out] for the fp32 estimate widened by a relative 2^-18
-// (far above the rounding of the product, the square root and the scaling)
-// and one unit, so [lo_in, hi_in] lies inside the exact ring and
-// [lo_out, hi_out] contains it.
-__device__ __forceinline__ void ring_approx(uint32_t b, uint32_t c, uint32_t &lo_in,
-                                            uint32_t &hi_in, uint32_t &lo_out, uint32_t &hi_out) {
-    const float sf = 2.0f * sqrtf((float)b * (float)c);
-    const float si = floorf(sf * (1.0f - 0x1p-18f)) - 1.0f;
-    const float so = ceilf(sf * (1.0f + 0x1p-18f)) + 1.0f;
-    // b, c are SSDs (< 2^24): s <= 2^25 + 2 and every end below 2^27, so the
-    // arithmetic stays in 32 bits
-    const uint32_t s_in = si > 0.0f ? (uint32_t)si : 0u, s_out = (uint32_t)so;
-    const uint32_t bc = b + c;
-    lo_in = b <= c ? 0u : bc - min(s_in, bc);
-    hi_in = bc + s_in;
-    lo_out = b <= c ? 0u : bc - min(s_out, bc);
-    hi_out = bc + s_out;
-}
-
-// Bounds on the number of key-list entries inside the exact ring from the
-// key's bucket counts (row {vmin, shift, cdf[0..B]}): the whole buckets
-// inside [lo_in, hi_in] give lb, the buckets meeting [lo_out, hi_out] give ub.
-__device__ __forceinline__ void ring_size_bounds(const uint32_t *row, int B, uint32_t lo_in,
-                                                 uint32_t hi_in, uint32_t lo_out, uint32_t hi_out,
-                                                 uint32_t &lb, uint32_t &ub) {
-    // ring ends are below 2^27 and the bucket shift is at most 24 (a key's
-    // distances span less than 2^24), so 32-bit arithmetic is exact
-    const uint32_t vmin = row[0], sh = row[1];
-    const uint32_t wm = (1u << sh) - 1u;
-    // entries below vmin + d: d from the interval's ends
-    auto below = [&](uint32_t v, bool incl) -> uint32_t {
-        return v >= vmin ? v - vmin + (incl ? 1u : 0u) : 0u;
-    };
-    const uint32_t dli = below(lo_in, false), dhi = below(hi_in, true);
-    const uint32_t dlo = below(lo_out, false), dho = below(hi_out, true);
-    const uint32_t ub_ = (uint32_t)B;
-    const uint32_t jl_in = min(ub_, (dli + wm) >> sh);
-    const uint32_t jh_in = min(ub_, dhi >> sh);
-    const uint32_t jl_out = min(ub_, dlo >> sh);
-    const uint32_t jh_out = min(ub_, (dho + wm) >> sh);
-    lb = jh_in > jl_in ? row[2 + jh_in] - row[2 + jl_in] : 0u;
-    ub = jh_out > jl_out ? row[2 + jh_out] - row[2 + jl_out] : 0u;
-}
-
 __device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
     unsigned m = __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u);
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), m);
 }
 
+// ---------------------------------------------------------------- k_scan_rows
+// The ring scan over the ring-ordered pivot rows (the default layout): entry
+// j of key k's sorted list carries its reference's whole pivot row,
+// PivR[k][j] = Piv[P[k][j]] (KQ 16-byte words per row, padding keys 0), so
+// the smallest ring [st, en) of key k* is one contiguous stream of rows that
+// consecutive lanes read from consecutive addresses.  Each lane keeps U rows
+// in flight.  Ring k's test lo_k <= x <= hi_k is the unsigned
+// x - lo_k <= hi_k - lo_k; padding keys get [0, 2^32 - 1], which every
+// value meets.  The reference index (P) is read only for candidates inside
+// every ring, before their exact SSD.  One wavefront scans one query (rec =
+// {c, k*, st, en}) and writes its match; returns |S| (on every lane).
+template <int DP, int KQ, int U>
+__device__ __forceinline__ uint32_t scan_query(const DevIndex &ix, const FrameBatch &fb,
+                                               const Work &w, uint32_t qid, const uint4 rec,
+                                               int lane) {
+    const uint32_t n = (uint32_t)ix.n;
+    const uint32_t c = rec.x, ks = rec.y, st = rec.z, en = rec.w;
+    const uint32_t mine = lane < DP / 4
+        ? reinterpret_cast<const uint32_t *>(w.patches + (int64_t)qid * DP)[lane] : 0u;
+    uint32_t a[DP / 4];
+#pragma unroll
+    for (int i = 0; i < DP / 4; ++i) a[i] = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
+    const int Qc = w.qc[qid];
+    uint32_t lo = 0, wd = 0xFFFFFFFFu;
+    if (lane < ix.K) {
+        const int key = ix.keys[lane];
+        const int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
+        const uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
+        uint32_t hi;
+        ring_bounds(b, c, lo, hi);
+        wd = hi - lo;
+    }
+    unsigned long long best = ~0ull;
+    uint32_t cnt = 0;
+    const int32_t *Pk = ix.P + (int64_t)ks * n;
+    const uint4 *rows = reinterpret_cast<const uint4 *>(ix.PivR) + (int64_t)ks * ix.n16 * KQ;
+    for (uint32_t j0 = st; j0 < en; j0 += 64 * U) {
+        uint4 pv[U][KQ];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = j0 + 64 * u + lane;
+            const uint4 *row = rows + (int64_t)(j < en ? j : st) * KQ;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) pv[u][q] = row[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = j0 + 64 * u + lane;
+            bool in = j < en;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const uint32_t x[4] = {pv[u][q].x, pv[u][q].y, pv[u][q].z, pv[u][q].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, 4 * q + e);
+                    const uint32_t wk = (uint32_t)__builtin_amdgcn_readlane((int)wd, 4 * q + e);
+                    in = in && x[e] - lk <= wk;
+                }
+            }
+            if (in) {
+                ++cnt;
+                const int32_t r = Pk[j];
+                const int d = dot_row<DP>(a, ix.Rv + (int64_t)r * ix.Dp);
+                const uint32_t s = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
+                const unsigned long long key = ((unsigned long long)s << 32) | (uint32_t)r;
+                best = key < best ? key : best;
+            }
+        }
+    }
+    best = wave_min_u64(best);
+    const uint32_t tot = (uint32_t)wave_sum_u64(cnt);
+    if (lane == 0) {
+        const FrameDesc *fdp = &fb.f[w.fid[qid]];
+        const int64_t ql = (int64_t)qid - fdp->qbase;
+        fdp->out[ql] = (int32_t)(uint32_t)best;
+        if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
+    }
+    return tot;
+}
+
+// One wavefront per item of the ring list (grid-stride).
+template <int DP, int KQ>
+__global__ __launch_bounds__(kBlock) void k_scan_rows(DevIndex ix, FrameBatch fb, Work w,
+                                                       unsigned long long *__restrict__ stats) {
+    constexpr int U = KQ <= 4 ? 4 : (KQ <= 8 ? 2 : 1);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t count = w.counters[0];
+    unsigned long long surv_tot = 0, mstar_tot = 0;
+    for (uint32_t item = blockIdx.x * (kBlock / 64) + wv; item < count;
+         item += gridDim.x * (kBlock / 64)) {
+        const uint32_t qid = w.ring_list[item];
+        const uint4 rec = w.rec[qid];
+        const uint32_t tot = scan_query<DP, KQ, U>(ix, fb, w, qid, rec, lane);
+        if (lane == 0) {
+            surv_tot += tot;
+            mstar_tot += rec.w - rec.z;
+        }
+    }
+    __shared__ unsigned long long s_acc[kBlock / 64][2];
+    if (lane == 0) { s_acc[wv][0] = surv_tot; s_acc[wv][1] = mstar_tot; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
+        if (tot) stat_add(stats, threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING, tot);
+    }
+}
+
 // ---------------------------------------------------------------- k_ring
-// One lane per query.  Each block first copies into LDS (at most 64 KB): the
-// binary-search samples of all K lists, each key's bucket-count row and the
-// key rows with their Rc.  Then, per query:
+// One lane per query.  The extraction kernel before it has already sent
+// full-search queries, queries without a prior and queries whose every ring
+// certainly exceeds the routing threshold to the dense search (route codes):
+// this kernel only appends those to the dense list and counts them.  A block
+// with any other query first copies into LDS each key's bucket-count row and
+// the key rows with their Rc.  Then, per remaining query:
 //  1. every key's ring-size bounds [lb_k, ub_k] from its bucket counts, with
 //     an inner and an outer fp32 approximation of the ring (no exact square
 //     root yet); the seed key is the smallest lb (lowest k on ties).  If
 //     that lb is above the routing threshold, every ring holds more than the
 //     threshold's candidates: the query goes to the dense list with no exact
 //     ring (unless the index asks for every query's exact m*);
-//  2. the seed's exact ring: exact bounds, the LDS samples bracket the two
+//  2. the seed's exact ring: exact bounds, the samples bracket the two
 //     positions, two line reads in global memory fix them;
 //  3. the remaining keys whose lower bound can still beat (m, k) -- chosen
 //     against the seed's exact size when the bounds stay in registers (K <= 16,
@@ -215,7 +266,7 @@ __device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
 // 512-query blocks, not in 1024-query ones).
 __host__ __device__ constexpr int ring_block(int KR) { return KR > 0 ? 512 : 1024; }
 
-template <int DP, int KR>
+template <int DP, int KR, int KQ>
 __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevIndex ix, FrameBatch fb, Work w,
                                                       unsigned long long *__restrict__ stats,
                                                       int64_t threshold) {
@@ -224,51 +275,67 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     __shared__ uint32_t s_wcnt[kWv][2];
     __shared__ uint32_t s_base[2];
     __shared__ unsigned long long s_st[kWv][6];
-    const int nsamp = ix.K * ix.ns;
-    // 16-byte copies (the table is 256-byte aligned): four rounds for 64 KB
-    for (int i = threadIdx.x; i < nsamp / 4; i += kBlk)
-        reinterpret_cast<uint4 *>(s_samp)[i] = reinterpret_cast<const uint4 *>(ix.Ts)[i];
-    for (int i = (nsamp & ~3) + threadIdx.x; i < nsamp; i += kBlk) s_samp[i] = ix.Ts[i];
-    const int olb = (nsamp + 3) & ~3;             // bound rows after the samples,
-    const int olk = olb + ix.K * ix.lbS;          // then the key rows and their Rc
-    const int olc = olk + ix.K * (DP / 4);
-    for (int i = threadIdx.x; i < ix.K * ix.lbS / 4; i += kBlk)
-        reinterpret_cast<uint4 *>(s_samp + olb)[i] = reinterpret_cast<const uint4 *>(ix.Lb)[i];
-    for (int i = threadIdx.x; i < ix.K * (DP / 16); i += kBlk) {
-        const int k = i / (DP / 16), part = i - k * (DP / 16);
-        reinterpret_cast<uint4 *>(s_samp + olk)[i] =
-            reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)ix.keys[k] * ix.Dp)[part];
-    }
-    for (int k = threadIdx.x; k < ix.K; k += kBlk) s_samp[olc + k] = (uint32_t)ix.Rc[ix.keys[k]];
-    __syncthreads();
-
+    // KQ > 0: the block scans its own ring queries (ring-ordered pivot rows
+    // of KQ 16-byte words), listed here, instead of the ring list
+    __shared__ uint32_t s_rq[KQ > 0 ? kBlk : 1];
+    __shared__ uint4 s_rr[KQ > 0 ? kBlk : 1];
+    __shared__ unsigned long long s_sc[KQ > 0 ? kWv : 1][2];
     const int64_t Q = fb.Q;
-    const uint32_t n = (uint32_t)ix.n;
-    const int nlines = ix.n16 / 16;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t qid = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     const bool valid = qid < Q;
     const int64_t qq = valid ? qid : Q - 1;
+    // the extraction kernel has already routed full-search, no-prior and
+    // bound-routed queries (route codes); the rest need this kernel's work.
+    // With fb.dense_masked the extraction kernel has also counted the routed
+    // ones, so a block with no other query has nothing to do; otherwise it
+    // still appends them to the dense list and counts them, without staging
+    const uint8_t code = w.route[qq];
+    const bool work = valid && code == kRouteRing;
+    const bool any_work = __syncthreads_or(work);
+    if (fb.dense_masked && !any_work) return;
+    // queries whose statistics this kernel counts
+    const bool counted = fb.dense_masked ? work : valid;
+    // LDS: the bucket-count rows, then the key rows and their Rc (the binary
+    // searches' samples are read from L2, where the whole table stays)
+    constexpr int olb = 0;
+    const int olk = olb + ix.K * ix.lbS;
+    const int olc = olk + ix.K * (DP / 4);
+    if (any_work) {
+        for (int i = threadIdx.x; i < ix.K * ix.lbS / 4; i += kBlk)
+            reinterpret_cast<uint4 *>(s_samp + olb)[i] = reinterpret_cast<const uint4 *>(ix.Lb)[i];
+        for (int i = threadIdx.x; i < ix.K * (DP / 16); i += kBlk) {
+            const int k = i / (DP / 16), part = i - k * (DP / 16);
+            reinterpret_cast<uint4 *>(s_samp + olk)[i] =
+                reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)ix.keys[k] * ix.Dp)[part];
+        }
+        for (int k = threadIdx.x; k < ix.K; k += kBlk) s_samp[olc + k] = (uint32_t)ix.Rc[ix.keys[k]];
+        __syncthreads();
+    }
+
+    const uint32_t n = (uint32_t)ix.n;
+    const int nlines = ix.n16 / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const FrameDesc *fdp = &fb.f[w.fid[qq]];
     const bool full = fdp->mode == kModeFull;
     const int32_t *prev = full ? nullptr : fdp->prev;
     const int64_t ql = qq - fdp->qbase;
-    uint32_t a[DP / 4];
-    {
+    uint32_t a[DP / 4] = {};
+    int Qc = 0;
+    if (work) {
         const uint4 *src = reinterpret_cast<const uint4 *>(w.patches + qq * DP);
 #pragma unroll
         for (int i = 0; i < DP / 16; ++i) {
             const uint4 v = src[i];
             a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
         }
+        Qc = w.qc[qq];
     }
-    const int Qc = w.qc[qq];
     // radius: the SSD to the previous match; for k-NN fields the largest SSD
     // to the k previous matches, which must be k distinct references (then
     // the k nearest lie within it); anything else means no prior
-    bool noprior = prev == nullptr;
+    bool noprior = prev == nullptr || code == kRouteNoPrior;
     uint32_t c = 0xFFFFFFFFu;
-    if (!noprior) {
+    if (work && !noprior) {
         const int kn = fb.knn;
         uint32_t cm = 0;
         for (int j = 0; j < kn && !noprior; ++j) {
@@ -283,8 +350,10 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     }
     uint32_t best_m = n, best_k = 0, best_st = 0, best_en = n;
     uint32_t probes = 0;                      // sorted-table reads of the binary searches
-    bool by_bound = false;
-    if (!full && !noprior && ix.K > 0) {
+    // routed by the extraction kernel on the same ring-size bounds: every
+    // ring holds more than the threshold's candidates
+    bool by_bound = code == kRouteBound;
+    if (work && !full && !noprior && ix.K > 0) {
         const uint32_t *LB = s_samp + olb, *KR_ = s_samp + olk, *KC = s_samp + olc;
         const int B = ix.lbB, LS = ix.lbS;
         // 1. every key's ring-size bounds from its bucket counts: the seed is
@@ -327,7 +396,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
             {
                 uint32_t lo1, hi1;
                 ring_bounds(b1, c, lo1, hi1);
-                const uint32_t *S = s_samp + k1 * ix.ns;
+                const uint32_t *S = ix.Ts + (int64_t)k1 * ix.ns;
                 const int il = sample_count<false>(S, ix.ns, lo1, probes);
                 const int ih = sample_count<true>(S, ix.ns, hi1, probes);
                 const uint32_t *t = ix.T + (int64_t)k1 * ix.n16;
@@ -357,7 +426,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
                 uint32_t lb, ub;
                 ring_size_bounds(LB + k * LS, B, lo, hi, lo, hi, lb, ub);
                 if (lb > best_m || (lb == best_m && (uint32_t)k > best_k)) continue;
-                const uint32_t *S = s_samp + k * ix.ns;
+                const uint32_t *S = ix.Ts + (int64_t)k * ix.ns;
                 const int il = sample_count<false>(S, ix.ns, lo, probes);
                 const int ih = sample_count<true>(S, ix.ns, hi, probes);
                 uint32_t sl, sh, el, eh;
@@ -375,15 +444,22 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
             }
         }
     }
-    const bool ring = valid && !full && !noprior && ix.K > 0 && (int64_t)best_m <= threshold;
+    const bool ring = valid && !full && !noprior && !by_bound && ix.K > 0 &&
+                      (int64_t)best_m <= threshold;
     const bool dense = valid && !ring;
-    if (valid) w.rec[qq] = make_uint4(c, best_k, best_st, best_en);
+    if (ring) {                                  // for the ring scan
+        w.rec[qq] = make_uint4(c, best_k, best_st, best_en);
+        w.route[qq] = kRouteScan;
+    }
 
     // ---- list appends: per-wave ballots, one atomic per list per block
+    // (with fb.dense_masked the dense search reads the route codes instead
+    // of a dense list; with KQ > 0 the ring queries stay in this block's
+    // own list and no ring list is built)
     const unsigned long long rmask = __ballot(ring), dmask = __ballot(dense);
     if (lane == 0) {
         s_wcnt[wv][0] = (uint32_t)__popcll(rmask);
-        s_wcnt[wv][1] = (uint32_t)__popcll(dmask);
+        s_wcnt[wv][1] = fb.dense_masked ? 0u : (uint32_t)__popcll(dmask);
     }
     __syncthreads();
     if (threadIdx.x < 2) {
@@ -393,23 +469,34 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
             s_wcnt[i][threadIdx.x] = tot;
             tot += c0;
         }
-        s_base[threadIdx.x] = tot ? atomicAdd(&w.counters[threadIdx.x], tot) : 0u;
+        const bool global = threadIdx.x == 1 || KQ == 0;
+        s_base[threadIdx.x] = global ? (tot ? atomicAdd(&w.counters[threadIdx.x], tot) : 0u) : tot;
     }
     __syncthreads();
-    if (ring) w.ring_list[s_base[0] + s_wcnt[wv][0] + lane_prefix(rmask)] = (uint32_t)qq;
-    if (dense) w.dense_list[s_base[1] + s_wcnt[wv][1] + lane_prefix(dmask)] = (uint32_t)qq;
+    if (ring) {
+        const uint32_t pos = s_wcnt[wv][0] + lane_prefix(rmask);
+        if constexpr (KQ > 0) {
+            s_rq[pos] = (uint32_t)qq;
+            s_rr[pos] = make_uint4(c, best_k, best_st, best_en);
+        } else {
+            w.ring_list[s_base[0] + pos] = (uint32_t)qq;
+        }
+    }
+    if (dense && !fb.dense_masked)
+        w.dense_list[s_base[1] + s_wcnt[wv][1] + lane_prefix(dmask)] = (uint32_t)qq;
 
     // ---- statistics: wave sums, then one atomic per counter per block
     // full-search frames count as queries and dense queries only
-    const unsigned long long v0 = wave_sum_u64(valid && !full && !by_bound ? best_m : 0);
-    const unsigned long long v1 = wave_sum_u64(valid && !full && noprior ? 1 : 0);
-    const unsigned long long bmask = __ballot(valid && by_bound);
-    const unsigned long long v5 = wave_sum_u64(valid ? probes : 0u);
+    const unsigned long long v0 = wave_sum_u64(counted && !full && !by_bound ? best_m : 0);
+    const unsigned long long v1 = wave_sum_u64(counted && !full && noprior ? 1 : 0);
+    const unsigned long long bmask = __ballot(counted && by_bound);
+    const unsigned long long v5 = wave_sum_u64(counted ? probes : 0u);
+    const unsigned long long cdmask = __ballot(counted && dense);
     if (lane == 0) {
         s_st[wv][0] = v0;
         s_st[wv][1] = v1;
         s_st[wv][2] = (unsigned long long)__popcll(rmask);
-        s_st[wv][3] = (unsigned long long)__popcll(dmask);
+        s_st[wv][3] = (unsigned long long)__popcll(cdmask);
         s_st[wv][4] = (unsigned long long)__popcll(bmask);
         s_st[wv][5] = v5;
     }
@@ -418,10 +505,31 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
         unsigned long long tot = 0;
         for (int i = 0; i < kWv; ++i) tot += s_st[i][threadIdx.x];
         const int slot[6] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE, ST_BOUND, ST_PROBES};
-        if (tot) atomicAdd(&stats[slot[threadIdx.x]], tot);
-        if (threadIdx.x == 3) {
+        if (tot) stat_add(stats, slot[threadIdx.x], tot);
+        if (threadIdx.x == 3 && !fb.dense_masked) {
             const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)blockIdx.x * kBlk);
-            atomicAdd(&stats[ST_QUERIES], (unsigned long long)nv);
+            stat_add(stats, ST_QUERIES, (unsigned long long)nv);
+        }
+    }
+
+    // ---- KQ > 0: this block's ring queries, one wavefront per query
+    if constexpr (KQ > 0) {
+        const uint32_t nring = s_base[0];
+        unsigned long long surv = 0, mst = 0;
+        for (uint32_t i = (uint32_t)wv; i < nring; i += kWv) {
+            const uint4 rr = s_rr[i];
+            const uint32_t t = scan_query<DP, KQ, 2>(ix, fb, w, s_rq[i], rr, lane);
+            surv += t;
+            mst += rr.w - rr.z;
+        }
+        if (nring) {
+            if (lane == 0) { s_sc[wv][0] = surv; s_sc[wv][1] = mst; }
+            __syncthreads();
+            if (threadIdx.x < 2) {
+                unsigned long long tot = 0;
+                for (int i = 0; i < kWv; ++i) tot += s_sc[i][threadIdx.x];
+                if (tot) stat_add(stats, threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING, tot);
+            }
         }
     }
 }
@@ -509,104 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(DevIndex ix, FrameBatch fb, Wor
     if (threadIdx.x < 2) {
         unsigned long long tot = 0;
         for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
-        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
-    }
-}
-
-// ---------------------------------------------------------------- k_scan_rows
-// k_scan over the ring-ordered pivot rows (the default layout): entry j of
-// key k's sorted list carries its reference's whole pivot row,
-// PivR[k][j] = Piv[P[k][j]] (KQ 16-byte words per row, padding keys 0), so
-// the smallest ring [st, en) of key k* is one contiguous stream of rows that
-// consecutive lanes read from consecutive addresses.  Each lane keeps U rows
-// in flight.  Ring k's test lo_k <= x <= hi_k is the unsigned
-// x - lo_k <= hi_k - lo_k; padding keys get [0, 2^32 - 1], which every
-// value meets.  The reference index (P) is read only for candidates inside
-// every ring, before their exact SSD.
-template <int DP, int KQ>
-__global__ __launch_bounds__(kBlock) void k_scan_rows(DevIndex ix, FrameBatch fb, Work w,
-                                                       unsigned long long *__restrict__ stats) {
-    constexpr int U = KQ <= 4 ? 4 : (KQ <= 8 ? 2 : 1);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t count = w.counters[0];
-    const uint32_t n = (uint32_t)ix.n;
-    const int K = ix.K;
-    unsigned long long surv_tot = 0, mstar_tot = 0;
-    for (uint32_t item = blockIdx.x * (kBlock / 64) + wv; item < count;
-         item += gridDim.x * (kBlock / 64)) {
-        const uint32_t qid = w.ring_list[item];
-        const uint4 rec = w.rec[qid];
-        const uint32_t c = rec.x, ks = rec.y, st = rec.z, en = rec.w;
-        const uint32_t mine = lane < DP / 4
-            ? reinterpret_cast<const uint32_t *>(w.patches + (int64_t)qid * DP)[lane] : 0u;
-        uint32_t a[DP / 4];
-#pragma unroll
-        for (int i = 0; i < DP / 4; ++i) a[i] = (uint32_t)__builtin_amdgcn_readlane((int)mine, i);
-        const int Qc = w.qc[qid];
-        uint32_t lo = 0, wd = 0xFFFFFFFFu;
-        if (lane < K) {
-            const int key = ix.keys[lane];
-            const int d = dot_row<DP>(a, ix.Rv + (int64_t)key * ix.Dp);
-            const uint32_t b = (uint32_t)(Qc + ix.Rc[key] + 2 * d);
-            uint32_t hi;
-            ring_bounds(b, c, lo, hi);
-            wd = hi - lo;
-        }
-        unsigned long long best = ~0ull;
-        uint32_t cnt = 0;
-        const int32_t *Pk = ix.P + (int64_t)ks * n;
-        const uint4 *rows = reinterpret_cast<const uint4 *>(ix.PivR) + (int64_t)ks * ix.n16 * KQ;
-        for (uint32_t j0 = st; j0 < en; j0 += 64 * U) {
-            uint4 pv[U][KQ];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + 64 * u + lane;
-                const uint4 *row = rows + (int64_t)(j < en ? j : st) * KQ;
-#pragma unroll
-                for (int q = 0; q < KQ; ++q) pv[u][q] = row[q];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + 64 * u + lane;
-                bool in = j < en;
-#pragma unroll
-                for (int q = 0; q < KQ; ++q) {
-                    const uint32_t x[4] = {pv[u][q].x, pv[u][q].y, pv[u][q].z, pv[u][q].w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)lo, 4 * q + e);
-                        const uint32_t wk = (uint32_t)__builtin_amdgcn_readlane((int)wd, 4 * q + e);
-                        in = in && x[e] - lk <= wk;
-                    }
-                }
-                if (in) {
-                    ++cnt;
-                    const int32_t r = Pk[j];
-                    const int d = dot_row<DP>(a, ix.Rv + (int64_t)r * ix.Dp);
-                    const uint32_t s = (uint32_t)(Qc + ix.Rc[r] + 2 * d);
-                    const unsigned long long key = ((unsigned long long)s << 32) | (uint32_t)r;
-                    best = key < best ? key : best;
-                }
-            }
-        }
-        best = wave_min_u64(best);
-        const unsigned long long tot = wave_sum_u64(cnt);
-        if (lane == 0) {
-            const FrameDesc *fdp = &fb.f[w.fid[qid]];
-            const int64_t ql = (int64_t)qid - fdp->qbase;
-            fdp->out[ql] = (int32_t)(uint32_t)best;
-            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
-            surv_tot += tot;
-            mstar_tot += en - st;
-        }
-    }
-    __shared__ unsigned long long s_acc[kBlock / 64][2];
-    if (lane == 0) { s_acc[wv][0] = surv_tot; s_acc[wv][1] = mstar_tot; }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        unsigned long long tot = 0;
-        for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
-        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
+        if (tot) stat_add(stats, threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING, tot);
     }
 }
 
@@ -726,27 +737,48 @@ __global__ __launch_bounds__(kBlock) void k_scan_knn(DevIndex ix, FrameBatch fb,
     if (threadIdx.x < 2) {
         unsigned long long tot = 0;
         for (int i = 0; i < kBlock / 64; ++i) tot += s_acc[i][threadIdx.x];
-        if (tot) atomicAdd(&stats[threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING], tot);
+        if (tot) stat_add(stats, threadIdx.x == 0 ? ST_SURV : ST_MSTAR_RING, tot);
     }
+}
+
+template <int DP, int KR, int KQ>
+hipError_t launch_ring_kq(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                          unsigned long long *stats, int64_t threshold, hipStream_t st) {
+    const size_t lds = (size_t)ix.K * (ix.lbS + DP / 4 + 1) * 4;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP, KR, KQ>),
+                       dim3((unsigned)((fb.Q + ring_block(KR) - 1) / ring_block(KR))),
+                       dim3(ring_block(KR)), lds, st, ix, fb, w, stats, threshold);
+    return hipGetLastError();
+}
+
+template <int DP, int KR>
+hipError_t launch_ring_kr(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                          unsigned long long *stats, int64_t threshold, hipStream_t st) {
+    if (ring_scans_inline(ix, fb)) {
+        switch (ix.KR) {
+        case 8: return launch_ring_kq<DP, KR, 2>(ix, fb, w, stats, threshold, st);
+        case 16: return launch_ring_kq<DP, KR, 4>(ix, fb, w, stats, threshold, st);
+        }
+        if constexpr (KR == 0) {
+            switch (ix.KR) {
+            case 32: return launch_ring_kq<DP, KR, 8>(ix, fb, w, stats, threshold, st);
+            case 48: return launch_ring_kq<DP, KR, 12>(ix, fb, w, stats, threshold, st);
+            case 64: return launch_ring_kq<DP, KR, 16>(ix, fb, w, stats, threshold, st);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    return launch_ring_kq<DP, KR, 0>(ix, fb, w, stats, threshold, st);
 }
 
 template <int DP>
 hipError_t launch_ring_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                          unsigned long long *stats, int64_t threshold, hipStream_t st) {
-    const size_t lds = ((size_t)((ix.K * ix.ns + 3) & ~3) + (size_t)ix.K * (ix.lbS + DP / 4 + 1)) * 4;
     // the register-bound variant fits 80 VGPRs without spills up to Dp = 64
     if constexpr (DP <= 64) {
-        if (ix.K <= 16) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP, 16>),
-                               dim3((unsigned)((fb.Q + ring_block(16) - 1) / ring_block(16))),
-                               dim3(ring_block(16)), lds, st, ix, fb, w, stats, threshold);
-            return hipGetLastError();
-        }
+        if (ix.K <= 16) return launch_ring_kr<DP, 16>(ix, fb, w, stats, threshold, st);
     }
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ring<DP, 0>),
-                       dim3((unsigned)((fb.Q + ring_block(0) - 1) / ring_block(0))),
-                       dim3(ring_block(0)), lds, st, ix, fb, w, stats, threshold);
-    return hipGetLastError();
+    return launch_ring_kr<DP, 0>(ix, fb, w, stats, threshold, st);
 }
 
 template <int DP>
@@ -822,6 +854,10 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 }
 
 int pivr_words(int K) { return K <= 8 ? 8 : (K + 15) / 16 * 16; }
+
+bool ring_scans_inline(const DevIndex &ix, const FrameBatch &fb) {
+    return fb.dense_masked && fb.knn == 1 && ix.PivR != nullptr && ix.K > 0;
+}
 
 hipError_t launch_build_pivr(const DevIndex &ix, uint32_t *PivR, hipStream_t st) {
     const int64_t total = (int64_t)ix.K * ix.n16 * pivr_words(ix.K);

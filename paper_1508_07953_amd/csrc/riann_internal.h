@@ -36,6 +36,9 @@ constexpr int kRowMaxParts = 4;
 __host__ __device__ constexpr int lb_buckets(int K) { return K <= 16 ? 128 : (K <= 32 ? 64 : 32); }
 __host__ __device__ constexpr int lb_stride(int K) { return (lb_buckets(K) + 3 + 3) / 4 * 4; }
 constexpr int kMaxKeys = 64;
+// Routing rows (DevIndex::Rt): buckets per key, row stride in words.
+constexpr int kRouteBuckets = 128;
+constexpr int kRouteStride = kRouteBuckets + 4;
 constexpr int kMaxPatch = 16;    // p <= 16 (D = p*p*C <= 256)
 
 // Dense-search key of a (query, reference) pair, unsigned 32-bit:
@@ -88,6 +91,10 @@ struct DevIndex {
     const uint32_t *Lb;   // K x lbS ring-size lower-bound rows {vmin, shift,
                           // cdf[0..lbB]}: cdf[j] = #{T[k] < vmin + j 2^shift};
                           // copied to LDS after the samples (ns rounded to 4)
+    const uint32_t *Rt;   // K x rtS routing rows in square-root space: {origin o
+                          // (fp32 bits), scale 2^-e (fp32 bits), F[0..kRouteBuckets]}
+                          // with F[j] = #{T[k] entries a : sqrt(a) < o + j 2^e}
+    int32_t rtS;          // Rt row stride in words
     const int32_t *keys;  // K key indices
     int64_t n, n_pad;
     int32_t D, Dp, K, p, C, s;
@@ -130,6 +137,9 @@ struct FrameBatch {
     int32_t all_full;        // every frame in full-search mode
     int32_t knn;             // neighbours per query (1: prev/out/ssd are Hq x Wq;
                              // k > 1: Hq x Wq x k, each row ascending)
+    int32_t dense_masked;    // 1: the dense search takes every query in order and
+                             // skips those the ring scan answers (route code
+                             // kRouteScan) instead of reading the dense list
     FrameDesc f[kMaxBatch];
 };
 
@@ -141,6 +151,8 @@ struct Work {
     uint8_t *patches;    // Q x Dp encoded query patches (a = q ^ 0x7F, zero padded)
     int32_t *qc;         // Q, Qc of each query
     uint8_t *fid;        // Q, frame of each query within its launch
+    uint8_t *route;      // Q, route code from the extraction kernel (kRoute*),
+                         // written in launches with a ring phase
     uint4 *rec;          // Q ring records {c, kstar, st, en}, by query; after the
                          // ring scan, row-layout dense with a split reference
                          // range: part 0's result, by dense-list position
@@ -152,14 +164,38 @@ struct Work {
     int64_t capacity;    // Q capacity
 };
 
+// Route codes the extraction kernel gives each query of a launch with a ring
+// phase: kRouteRing leaves the query to the ring kernel; the others go to
+// the dense search without it -- full-search frames, queries without a
+// valid previous match, and queries whose every ring holds more than the
+// routing threshold's candidates by the per-key bucket-count lower bounds.
+// The ring kernel then marks the queries the ring scan answers kRouteScan.
+enum : uint8_t { kRouteRing = 0, kRouteFull = 1, kRouteNoPrior = 2, kRouteBound = 3,
+                 kRouteScan = 4 };
+
 // device stats block (uint64 counters, same order as riann_stats_t after `frames`)
 enum StatSlot {
     ST_QUERIES = 0, ST_RING, ST_DENSE, ST_NOPRIOR, ST_MSTAR, ST_SURV, ST_MSTAR_RING,
     ST_BOUND, ST_PROBES, ST_COUNT
 };
+// Each counter is kept as kStatReplicas partial sums, each on a cache line of
+// its own: a block adds into the replica of its block index, so the atomics of
+// a launch's thousands of blocks spread over many addresses instead of
+// queuing on one; the host sums the replicas.
+constexpr int kStatReplicas = 64;
+constexpr int kStatStride = 16;              // uint64 words: 128 bytes apart
+constexpr int kStatWords = ST_COUNT * kStatReplicas * kStatStride;
+__device__ __forceinline__ void stat_add(unsigned long long *stats, int slot,
+                                         unsigned long long v) {
+    atomicAdd(stats + ((size_t)slot * kStatReplicas + blockIdx.x % kStatReplicas) * kStatStride,
+              v);
+}
 
+// Extraction of every query patch; in launches with a ring phase also the
+// route code of each query against `threshold` (the ring kernel's; < 0: no
+// routing), and with fb.dense_masked the counts of what it routed (stats).
 hipError_t launch_extract(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                          hipStream_t st);
+                          int64_t threshold, unsigned long long *stats, hipStream_t st);
 hipError_t launch_ring(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                        unsigned long long *stats, int64_t threshold, hipStream_t st);
 hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
@@ -167,6 +203,10 @@ hipError_t launch_scan(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // Ring-ordered pivot rows (k_ring.hip): the row length for K keys, and the
 // device build of ix.PivR from ix.P and ix.Piv.
 int pivr_words(int K);
+// With the dense search reading route codes, one k-NN neighbour and the
+// ring-ordered pivot rows, the ring kernel scans its own ring queries and no
+// separate ring-scan launch follows.
+bool ring_scans_inline(const DevIndex &ix, const FrameBatch &fb);
 hipError_t launch_build_pivr(const DevIndex &ix, uint32_t *PivR, hipStream_t st);
 // all_full batches: every query (no list); otherwise the dense list and its
 // device-side count.  Reads the query patches written by launch_extract.
