@@ -42,21 +42,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def dense_traffic_bytes(workload, layout):
-    """HBM bytes per dispatch of the dominant dense kernel from the committed
-    rocprofv3 counter summary, or None when there is none for this workload
-    and layout or the kernel source changed since it was taken."""
+def dense_traffic_bytes(workload, layout, shape):
+    """HBM bytes per frame of the dense step (row kernel plus its resolve
+    pass) from the committed rocprofv3 counter summary, or None when there is
+    none for this workload, layout and block shape, or a kernel source changed
+    since it was taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", f"{workload}_dense_traffic.json")) as f:
             rec = json.load(f)
-        if rec.get("dense_layout") != layout:
+        if rec.get("dense_layout") != layout or list(rec.get("shape", [])) != list(shape):
             return None
-        with open(os.path.join(ROOT, "paper_1508_07953_amd", "csrc", rec["source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError, KeyError):
+        for name, want in rec["sources_sha256"].items():
+            with open(os.path.join(ROOT, "paper_1508_07953_amd", "csrc", name), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    return rec["bytes_per_dispatch"] if rec.get("source_sha256") == sha else None
+    return rec["bytes_per_frame"]
 
 
 def cpu_baseline(wl, f0, f1, target_s):
@@ -444,7 +447,9 @@ def main():
                     help="auto: references as MFMA rows (the library default); column: "
                          "queries as MFMA rows (RIANN_FLAG_COLUMN_DENSE)")
     ap.add_argument("--no-tune", action="store_true",
-                    help="keep the library's default routing threshold")
+                    help="keep the library's default routing threshold and block shape")
+    ap.add_argument("--dense-shape", default="", metavar="WAVES,COLS",
+                    help="use this dense block shape instead of autotuning it (e.g. 4,4)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed per-frame path: no reconstruction, k-NN or paper-mode "
                          "figures (used for kernel traces and counters)")
@@ -518,8 +523,13 @@ def main():
             fr.append(frames[t])
             pv.append(f_prev)
             f_prev = o
-        shape = tune.tune_shape(idx, fr, use_cache=False, write_cache=False)
-        log(f"tuned dense block shape {shape['shape']}: {shape['ms']}")
+        if args.dense_shape:
+            wv, cl = (int(x) for x in args.dense_shape.split(","))
+            idx.set_dense_shape(wv, cl)
+            shape = {"shape": [wv, cl], "ms": None}
+        else:
+            shape = tune.tune_shape(idx, fr, use_cache=False, write_cache=False)
+        log(f"dense block shape {shape['shape']}: {shape['ms']}")
         tuned = tune.tune_threshold(idx, fr, pv, use_cache=False, write_cache=False)
         tuned["shape"] = shape
         log(f"tuned dense threshold {tuned['threshold']}: {tuned['ms']}")
@@ -625,7 +635,9 @@ def main():
         result["roofline"] = {"bound": "mfma", "kernel": kname,
                               "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                               "frac": achieved / INT8_PEAK_TOPS,
-                              "traffic": dense_traffic_bytes(args.workload, args.dense_layout),
+                              "traffic": dense_traffic_bytes(
+                                  args.workload, args.dense_layout,
+                                  idx.dense_shapes()[0][idx.dense_shapes()[1]]),
                               "ms_per_launch": ms_per_launch,
                               "ops_per_launch": ops}
         result["kernels_ms_per_frame"] = {k: v["ms"] / max(1, v["launches"])
