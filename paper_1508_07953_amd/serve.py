@@ -17,7 +17,11 @@ each finished before the next starts.
 Frames may be device tensors or host tensors (pinned host memory for
 asynchronous copies).  Host frames are copied into the stream's device frame
 buffer on a copy stream of the server's own, so the copies of one batch
-overlap the search of the batch before it.
+overlap the search of the batch before it.  With host_results=True every
+field and distance map is also delivered to pinned host memory, copied on a
+second copy stream of the server's own once its batch has run, so those
+copies overlap the next batch's search too; a frame completes when its
+field is on the host.
 """
 from __future__ import annotations
 
@@ -37,7 +41,8 @@ class Completion:
     seq: int            # frame number within the stream
     arrival: float      # host time the frame was submitted (s)
     done: float         # host time its completion was observed (s)
-    field: object       # device (Hq, Wq) int32 tensor holding the field (valid
+    field: object       # (Hq, Wq) int32 tensor holding the field, on the device
+                        # or with host_results in pinned host memory (valid
                         # until the stream's frame after next is launched)
     ssd: object
 
@@ -47,11 +52,16 @@ class Completion:
 
 
 class _Stream:
-    def __init__(self, sid, H, W, hq, wq, device, torch, channels):
+    def __init__(self, sid, H, W, hq, wq, device, torch, channels, host_results=False):
         self.sid, self.H, self.W = sid, H, W
         self.fields = [torch.full((hq, wq), -1, dtype=torch.int32, device=device)
                        for _ in range(2)]
         self.ssd = [torch.empty((hq, wq), dtype=torch.int32, device=device) for _ in range(2)]
+        # pinned host copies of the results (host_results), one per device slot
+        self.fields_h = [torch.empty((hq, wq), dtype=torch.int32, pin_memory=True)
+                         for _ in range(2)] if host_results else None
+        self.ssd_h = [torch.empty((hq, wq), dtype=torch.int32, pin_memory=True)
+                      for _ in range(2)] if host_results else None
         # device copy of the frame in flight when frames arrive in host memory
         # (one buffer: a stream has at most one frame in flight)
         self.dframe = torch.empty((H, W, channels), dtype=torch.uint8, device=device)
@@ -68,7 +78,8 @@ class Server:
 
     def __init__(self, index: Index, max_batch: int = 40, inflight: int = 2,
                  memory_budget: Optional[int] = None, device=None,
-                 max_batch_queries: Optional[int] = 1_000_000, concurrent: bool = False):
+                 max_batch_queries: Optional[int] = 1_000_000, concurrent: bool = False,
+                 host_results: bool = False):
         import torch
         self.torch = torch
         self.index = index
@@ -87,6 +98,8 @@ class Server:
         self.hip_streams = [torch.cuda.Stream(device=self.device)
                             for _ in range(self.inflight if concurrent else 1)]
         self.copy_stream = torch.cuda.Stream(device=self.device)
+        self.host_results = host_results
+        self.result_stream = torch.cuda.Stream(device=self.device) if host_results else None
         self.budget = memory_budget
         p = index.params
         self._fp = (p.n_ref, p.n_keys, p.patch, p.channels, p.stride)
@@ -167,7 +180,8 @@ class Server:
 
     def _activate(self, sid, H, W):
         hq, wq = self.index.field_shape(H, W)
-        st = _Stream(sid, H, W, hq, wq, self.device, self.torch, int(self.index.params.channels))
+        st = _Stream(sid, H, W, hq, wq, self.device, self.torch, int(self.index.params.channels),
+                     self.host_results)
         pq = self._pending_queues.pop(sid, None)
         if pq:
             st.queue.extend(pq)
@@ -275,7 +289,18 @@ class Server:
             hs.wait_stream(self.copy_stream)
         self.index.match_batch(items, stream=hs)
         ev = torch.cuda.Event()
-        ev.record(hs)
+        if self.host_results:
+            # the results to pinned host memory on the result stream, after
+            # the batch, while the next batch's search runs on hs
+            rs = self.result_stream
+            rs.wait_stream(hs)
+            with torch.cuda.stream(rs):
+                for (sid, _, _, nxt), s in zip(meta, ready):
+                    s.fields_h[nxt].copy_(s.fields[nxt], non_blocking=True)
+                    s.ssd_h[nxt].copy_(s.ssd[nxt], non_blocking=True)
+            ev.record(rs)
+        else:
+            ev.record(hs)
         self._batches.append((ev, hs, meta, keep))
         return True
 
@@ -292,8 +317,12 @@ class Server:
                     st.cur = nxt
                     st.has_field = True
                     st.busy = False
-                    self.completed.append(Completion(sid, seq, t_arr, t, st.fields[nxt],
-                                                     st.ssd[nxt]))
+                    if self.host_results:
+                        self.completed.append(Completion(sid, seq, t_arr, t, st.fields_h[nxt],
+                                                         st.ssd_h[nxt]))
+                    else:
+                        self.completed.append(Completion(sid, seq, t_arr, t, st.fields[nxt],
+                                                         st.ssd[nxt]))
                     if st.closing:
                         self._free(sid)
                 done += 1

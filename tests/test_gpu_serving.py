@@ -167,3 +167,37 @@ def test_unreferenced_and_host_frames(env):
             assert np.array_equal(o.reshape(-1), bi), (k, t)
             assert np.array_equal(s.reshape(-1).astype(np.uint32), bd), (k, t)
     idx.close()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_host_frames_and_host_results(env, plain):
+    """Frames in pinned host memory and results delivered to pinned host
+    memory (host_results), in the plain setting (one frame at a time) and
+    the serving one: every field and SSD map on the host equals the oracle's
+    brute force, and a completion's host tensors are not device tensors."""
+    torch, riann, serve, dev = env
+    print(f"[gpu case] serving host results plain={plain}", flush=True)
+    rng = np.random.default_rng(35)
+    ref, keys = _ref_rgb(rng, n=600, K=10)
+    idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
+    vids = _streams(rng, 5)
+    srv = (serve.Server(idx, max_batch=1, inflight=1, host_results=True) if plain else
+           serve.Server(idx, max_batch=8, inflight=2, host_results=True))
+    sids = [srv.open_stream(v[0].shape[0], v[0].shape[1]) for v in vids]
+    got = {}
+    for t in range(4):
+        n0 = len(srv.completed)
+        for si, v in zip(sids, vids):
+            srv.submit(si, torch.from_numpy(v[t]).pin_memory())
+            srv.step()
+        srv.drain()
+        for c in srv.completed[n0:]:
+            assert not c.field.is_cuda and not c.ssd.is_cuda
+            got[(c.stream, c.seq)] = (c.field.numpy().copy(), c.ssd.numpy().copy())
+    for k, si in enumerate(sids):
+        for t in range(4):
+            bi, bd = oracle.brute_force(oracle.extract(vids[k][t], 8, 1), ref)
+            o, s = got[(si, t)]
+            assert np.array_equal(o.reshape(-1), bi), (k, t)
+            assert np.array_equal(s.reshape(-1).astype(np.uint32), bd), (k, t)
+    idx.close()
