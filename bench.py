@@ -662,20 +662,30 @@ def main():
         Dp = (wl.D + 31) // 32 * 32
         sec = {}
         if prof_all["ring"]["launches"]:
-            rb = Q * (Dp + 4 + 4 + wl.D + 16 + 4)
+            # the ring kernel reads every route code; the queries the
+            # extraction kernel left to it also their patch, Qc, prev, the
+            # previous match's row and Rc, and write a record
+            left = max(0, st["queries"] - st["bound_routed"] - st["no_prior"]) / K
+            rb = Q + left * (Dp + 4 + 4 + Dp + 4 + 16)
             rms = prof_all["ring"]["ms"] / prof_all["ring"]["launches"]
-            sec["k_ring"] = {"bound": "alu", "algorithmic_bytes": rb, "ms": rms,
-                             "GBps": rb / (rms * 1e-3) / 1e9, "hbm_frac": rb / (rms * 1e-3) / 1e9
-                             / HBM_PEAK_GBS,
-                             "note": "patch, Qc, prev, r_prev row, record and list entry per "
-                                     "query; VALU-bound (key distances and binary searches)"}
+            sec["k_ring"] = {"bound": "latency", "algorithmic_bytes": rb, "ms": rms,
+                             "queries_left_per_frame": left,
+                             "GBps": rb / (rms * 1e-3) / 1e9,
+                             "note": "route codes of every query, then the exact smallest-ring "
+                                     "search of the queries the extraction kernel left (binary "
+                                     "searches: latency), and their ring scan"}
         if prof_all["extract"]["launches"]:
-            eb = H * Wd * wl.channels + Q * (Dp + 4 + 1)
+            # extraction (frame once; patch, Qc, frame id, route code written)
+            # and routing (prev entry, the previous match's row and Rc read)
+            eb = H * Wd * wl.channels + Q * (Dp + 4 + 1 + 1) + Q * (4 + Dp + 4)
             ems = prof_all["extract"]["ms"] / prof_all["extract"]["launches"]
-            sec["k_extract"] = {"bound": "hbm", "algorithmic_bytes": eb, "ms": ems,
+            sec["k_extract"] = {"bound": "hbm+latency", "algorithmic_bytes": eb, "ms": ems,
                                 "GBps": eb / (ems * 1e-3) / 1e9,
                                 "hbm_frac": eb / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                "note": "frame read once, encoded patch + Qc + frame id written"}
+                                "note": "frame read once, encoded patch + Qc + frame id + route "
+                                        "code written; per query the previous match's index, "
+                                        "row and Rc read for the routing test, K key distances "
+                                        "and ring bounds computed (VALU)"}
         if prof_all["scan"]["launches"] and st["ring_queries"]:
             # ring-routed queries: record, list entry, patch, Qc read and the
             # match written; the smallest ring's P entries and pivot rows; the
