@@ -254,11 +254,15 @@ def ring_path_forced(idx, wl, frames, field, t0, nframes, hq, wq, log_fn):
            "probes_per_query": st["bsearch_probes"] / max(1, rq),
            "ring_scan": {"kernel": scan_kernel, "algorithmic_bytes": scan_bytes, "ms": scan_ms,
                          "GBps": scan_bytes / (scan_ms * 1e-3) / 1e9,
-                         "hbm_frac": scan_bytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_frac_of_hbm_peak":
+                             scan_bytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "layout": "ring-ordered pivot rows, %d words per entry" % kr,
                          "note": "per ring query 32 B + patch; per candidate of the smallest "
                                  "ring its pivot row; per survivor its index and row"
-                                 + ("; plus the ring phase's bytes per query" if inline else "")}}
+                                 + ("; plus the ring phase's bytes per query" if inline else "")
+                                 + "; algorithmic bytes, much of them served by L2 and the "
+                                   "Infinity Cache: the bytes fetched beyond L2 come from the "
+                                   "FETCH_SIZE counter (profiles/hd720_hbm_traffic.txt)"}}
     log_fn(f"ring path forced: {res['ms_per_frame']:.2f} ms/frame, ring scan "
            f"{res['ring_scan']['GBps']:.0f} GB/s, mean m* {res['mean_mstar']:.0f}")
     return res
@@ -661,6 +665,13 @@ def main():
         # bytes per frame; both are bound elsewhere, see the notes)
         Dp = (wl.D + 31) // 32 * 32
         sec = {}
+        thr = int(idx.params.dense_threshold)
+        if not prof_all["ring"]["launches"] and thr == 0:
+            sec["k_ring"] = {"launched": False,
+                             "note": "threshold 0: a query with a previous match has m* >= 1 "
+                                     "(its nearest neighbour lies in every ring), so the "
+                                     "extraction kernel routes it to the dense search on that "
+                                     "bound alone and no ring kernel is launched"}
         if prof_all["ring"]["launches"]:
             # the ring kernel reads every route code; the queries the
             # extraction kernel left to it also their patch, Qc, prev, the
@@ -677,15 +688,19 @@ def main():
         if prof_all["extract"]["launches"]:
             # extraction (frame once; patch, Qc, frame id, route code written)
             # and routing (prev entry, the previous match's row and Rc read)
-            eb = H * Wd * wl.channels + Q * (Dp + 4 + 1 + 1) + Q * (4 + Dp + 4)
+            # (at threshold 0 only the previous match's index: every query
+            # with one is routed dense on m* >= 1)
+            eb = H * Wd * wl.channels + Q * (Dp + 4 + 1 + 1) + Q * (4 + (Dp + 4 if thr else 0))
             ems = prof_all["extract"]["ms"] / prof_all["extract"]["launches"]
-            sec["k_extract"] = {"bound": "hbm+latency", "algorithmic_bytes": eb, "ms": ems,
+            sec["k_extract"] = {"bound": "hbm" if thr == 0 else "hbm+valu",
+                                "algorithmic_bytes": eb, "ms": ems,
                                 "GBps": eb / (ems * 1e-3) / 1e9,
                                 "hbm_frac": eb / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "note": "frame read once, encoded patch + Qc + frame id + route "
-                                        "code written; per query the previous match's index, "
-                                        "row and Rc read for the routing test, K key distances "
-                                        "and ring bounds computed (VALU)"}
+                                        "code written, the previous match's index read"
+                                        + ("" if thr == 0 else
+                                           "; per query the previous match's row and Rc read, "
+                                           "K key distances and ring bounds computed (VALU)")}
         if prof_all["scan"]["launches"] and st["ring_queries"]:
             # ring-routed queries: record, list entry, patch, Qc read and the
             # match written; the smallest ring's P entries and pivot rows; the

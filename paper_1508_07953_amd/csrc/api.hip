@@ -613,7 +613,12 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
         tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     }
-    if (!all_full) {
+    // With route codes and a threshold below 1 the extraction kernel has sent
+    // every query to the dense search (m* >= 1 by containment): the ring
+    // kernel would find nothing to do
+    const bool ring_empty = fb.dense_masked && knn == 1 && h->dix.K > 0 &&
+                            !h->dix.exact_mstar && threshold >= 0 && threshold < 1;
+    if (!all_full && !ring_empty) {
         {
             KTimer tm(h, RIANN_K_RING, st, timed);
             e = launch_ring(h->dix, fb, w, h->dstats, threshold, st);

@@ -61,6 +61,15 @@ __device__ __forceinline__ bool route_tables_on(const DevIndex &ix, const FrameB
                                                 int64_t threshold) {
     return route_codes_on(fb, threshold) && fb.knn == 1 && ix.K > 0 && !ix.exact_mstar;
 }
+// Below a threshold of 1 no ring can qualify: the exact nearest neighbour is
+// within sqrt(c) of q, so by the triangle inequality it lies in every ring of
+// radius sqrt(c) (the exact-mode rings of Sec. 3.2), m* >= 1 for a query with
+// a previous match, and that bound alone sends it to the dense search; c and
+// the key distances are not needed and the tables are not staged.
+__device__ __forceinline__ bool route_bounds_on(const DevIndex &ix, const FrameBatch &fb,
+                                                int64_t threshold) {
+    return route_tables_on(ix, fb, threshold) && threshold >= 1;
+}
 
 template <int DP>
 __device__ __forceinline__ void stage_route_tables(const DevIndex &ix, uint32_t *tab) {
@@ -102,6 +111,7 @@ __device__ __forceinline__ void route_begin(const DevIndex &ix, const FrameBatch
     const int32_t pv = fa.prev[ql];
     if (pv < 0 || (int64_t)pv >= ix.n) { rp.code = kRouteNoPrior; return; }
     if (!route_tables_on(ix, fb, threshold)) { rp.code = kRouteRing; return; }
+    if (threshold < 1) { rp.code = kRouteBound; return; }
     rp.code = kRouteNeedBounds;
     const uint4 *src = reinterpret_cast<const uint4 *>(ix.Rv + (int64_t)pv * ix.Dp);
 #pragma unroll
@@ -123,7 +133,7 @@ __device__ __forceinline__ uint8_t route_finish(const DevIndex &ix, const uint32
         d = __builtin_amdgcn_sdot4((int)a[4 * i + 3], (int)rp.row[i].w, d, false);
     }
     const uint32_t c = (uint32_t)(Qc + rp.rc + 2 * d);
-    const float sc = sqrtf((float)c);             // SSDs are below 2^24: exact as fp32
+    const float sc = sqrt_est((float)c);          // SSDs are below 2^24: exact as fp32
     const uint32_t *keys = tab + ix.K * kRouteStride, *krc = keys + ix.K * (DP / 4);
     for (int k = 0; k < ix.K; ++k) {
         const uint32_t b = (uint32_t)(Qc + (int)krc[k] +
@@ -131,7 +141,7 @@ __device__ __forceinline__ uint8_t route_finish(const DevIndex &ix, const uint32
                                                              keys + k * (DP / 4))));
         // a ring that may hold no more than the threshold's candidates: the
         // ring kernel decides
-        if ((int64_t)route_lower_bound(tab + k * kRouteStride, sqrtf((float)b), sc) <= threshold)
+        if ((int64_t)route_lower_bound(tab + k * kRouteStride, sqrt_est((float)b), sc) <= threshold)
             return kRouteRing;
     }
     return kRouteBound;
@@ -219,7 +229,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract(DevIndex ix, FrameBatch fb
     if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
     const int p = ix.p, C = ix.C, s = ix.s, D = ix.D;
     uint32_t *tab = reinterpret_cast<uint32_t *>(s_tile + route_lds_offset(p, C, s));
-    if (route_tables_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
+    if (route_bounds_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
     const ExtTile t = load_tile(ix, fb, s_tile);
     const FrameDesc &fa = *t.fa;
     const int f = t.f, qx0 = t.qx0, qy0 = t.qy0, ldw = t.ldw;
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
     extern __shared__ __attribute__((aligned(16))) uint8_t s_tile[];
     if (blockIdx.x == 0 && threadIdx.x < 4) w.counters[threadIdx.x] = 0u;   // ring/dense list counts
     uint32_t *tab = reinterpret_cast<uint32_t *>(s_tile + route_lds_offset(P, C, ix.s));
-    if (route_tables_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
+    if (route_bounds_on(ix, fb, threshold)) stage_route_tables<DP>(ix, tab);
     constexpr int PC = P * C, NW = PC / 4, D = P * PC;
     static_assert(PC % 4 == 0 && D <= DP, "whole-word window rows");
     const int s = ix.s;
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(kTX *kTY) void k_extract_rows(DevIndex ix, FrameBat
 template <int DP>
 hipError_t launch_extract_t(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                             int64_t threshold, unsigned long long *stats, hipStream_t st) {
-    const bool tables = threshold >= 0 && !fb.all_full && fb.knn == 1 && ix.K > 0 &&
+    const bool tables = threshold >= 1 && !fb.all_full && fb.knn == 1 && ix.K > 0 &&
                         !ix.exact_mstar;
     const size_t lds = tables ? route_lds_offset(ix.p, ix.C, ix.s) + route_lds_bytes(ix.K, DP)
                               : ext_lds_bytes(ix.p, ix.C, ix.s);

@@ -6,6 +6,13 @@
 
 namespace riann {
 
+// The hardware square root (v_sqrt_f32, about 1 ulp).  Its arguments here are
+// SSDs and products of two SSDs as fp32, zero or at least 1 (no denormal
+// inputs).  Every bound below widens its estimate by a relative 2^-18, 32 ulps,
+// far above this error, so the correctly rounded library sqrtf (a dozen more
+// instructions) is not needed.
+__device__ __forceinline__ float sqrt_est(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // <a, v> over DP bytes: a in registers, v a 16-byte aligned reference row.
 template <int DP>
 __device__ __forceinline__ int dot_row(const uint32_t (&a)[DP / 4], const int8_t *__restrict__ v) {
@@ -29,7 +36,7 @@ __device__ __forceinline__ int dot_row(const uint32_t (&a)[DP / 4], const int8_t
 // [lo_out, hi_out] contains it.
 __device__ __forceinline__ void ring_approx(uint32_t b, uint32_t c, uint32_t &lo_in,
                                             uint32_t &hi_in, uint32_t &lo_out, uint32_t &hi_out) {
-    const float sf = 2.0f * sqrtf((float)b * (float)c);
+    const float sf = 2.0f * sqrt_est((float)b * (float)c);
     const float si = floorf(sf * (1.0f - 0x1p-18f)) - 1.0f;
     const float so = ceilf(sf * (1.0f + 0x1p-18f)) + 1.0f;
     // b, c are SSDs (< 2^24): s <= 2^25 + 2 and every end below 2^27, so the

@@ -296,6 +296,16 @@ def test_profiling_levels(torch_dev, riann):
     pg = g.profile()
     assert all(pg[k]["launches"] == 1 for k in ("ring", "scan", "dense", "extract")), pg
     g.close()
+    # threshold 0: every query with a prior goes dense on m* >= 1, no ring launch
+    z = riann.Index.build(wl.ref, wl.keys, patch=8, channels=1, stride=1, dense_threshold=0)
+    z.set_profiling(True)
+    oz, sz = z.match_frame(d1, prev=o0)
+    pz = z.profile()
+    assert pz["ring"]["launches"] == 0 and pz["scan"]["launches"] == 0, pz
+    assert pz["extract"]["launches"] == 1 and pz["dense"]["launches"] == 1, pz
+    torch.cuda.synchronize()
+    check_exact(oz, sz, oracle.extract(f1, 8, 1), wl.ref, "threshold 0 frame")
+    z.close()
     assert all(p[k]["ms"] > 0 for k in ("dense", "full", "extract")), p
     idx.set_profiling("dense")
     idx.match_frame(d1, prev=o0)
@@ -799,5 +809,8 @@ def test_bound_routing_keeps_routing(torch_dev, riann, p, C, K, n, thr):
             assert total - st["sum_mstar"] >= (thr + 1) * b
             assert (b == 0) == (st["sum_mstar"] == total)
             if thr == 0:
-                assert b > 0                # the shortcut is taken
+                # m* >= 1 for every query with a prior (its nearest neighbour
+                # lies in every ring): all of them go dense on that bound
+                assert b == len(P) - st["no_prior"]
+                assert st["ring_queries"] == 0 and st["sum_mstar"] == n * st["no_prior"]
         idx.close()
