@@ -601,7 +601,7 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     const bool rows = knn == 1 && h->dense_rows && dense_rows_supported(h->dix);
     // the row-layout search takes the queries in order and skips the
     // ring-scanned ones by their route codes: no dense list is built
-    fb.dense_masked = rows && !all_full ? 1 : 0;
+    fb.dense_masked = rows && !all_full ? kDenseMasked : 0;
     const bool timed = preset == nullptr;
     // one threshold for the whole launch: the extraction kernel routes on it
     // and the ring kernel decides the rest with it
@@ -633,6 +633,9 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
             if (e != hipSuccess) return hip_fail(e, "k_scan launch");
         }
     }
+    // nothing was ring-scanned: the dense search takes every query in order
+    // without reading the route codes, as a full search does
+    if (ring_empty) fb.dense_masked = kDenseInOrder;
     {
         KTimer tm(h, all_full ? RIANN_K_FULL : RIANN_K_DENSE, st, timed);
         if (knn > 1) {

@@ -25,11 +25,11 @@
 // earlier tile.  The wavefront then recomputes the exact SSDs of that tile's
 // rows in the lane group(s) that reached the minimum and takes their (SSD,
 // index) minimum; these gathers overlap the matrix work of the other
-// wavefronts on the SIMD.  Query chunks that fill whole rounds of the resident
-// block slots run whole; the chunks of a last, partial round (or all of them
-// when there are fewer chunks than slots) split the reference range over up
-// to four blocks each, so the last round runs full and short.  The parts
-// leave records that a resolve kernel merges before the same check.
+// wavefronts on the SIMD.  A launch with at most half as many query chunks
+// as resident block slots splits each chunk's reference range over up to
+// four blocks, so a small frame fills the chip; the parts leave records that
+// a resolve kernel merges before the same check.  Larger launches run whole
+// chunks only (see row_plan).
 #pragma once
 #include "riann_internal.h"
 
@@ -322,29 +322,24 @@ struct RowCheck {
 // How a launch covers `chunks` query chunks with `slots` resident blocks:
 // the first `whole` chunks run as one block each over every reference; each
 // later chunk is split over `parts` blocks (consecutive blocks, consecutive
-// parts).  With more chunks than slots, only the remainder past whole rounds
-// is split, into as many parts as still fit one round (at most
-// kRowMaxParts); with fewer, every chunk is split so the chunks' parts cover
-// the slots.  Blocks used: whole + (chunks - whole) * parts
+// parts).  Only a launch with at most half as many chunks as slots splits:
+// every chunk into as many parts as fit the slots in one round (at most
+// kRowMaxParts), so a small frame still fills the chip.  A larger launch runs
+// whole chunks only: the blocks of its last round share the CUs with fewer
+// others and finish sooner, and splitting that round measured no faster
+// (720p: 0.3 %) while each part re-read its chunk's patches and the resolve
+// pass re-read records and candidate rows (1.8x the step's algorithmic HBM
+// bytes against 1.1x).  Blocks used: whole + (chunks - whole) * parts
 // <= chunks + min(3 * chunks, slots).
 struct RowPlan {
     uint32_t whole, parts;
 };
 __host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots) {
     const uint32_t cap = (uint32_t)kRowMaxParts;
-    uint32_t p = 1;
-    if (chunks == 0 || slots == 0) return RowPlan{chunks, 1u};
-    if (chunks <= slots) {
-        p = (slots + chunks - 1) / chunks;
-        p = p < cap ? p : cap;
-        return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
-    }
-    const uint32_t rem = chunks % slots;
-    if (rem) {
-        p = slots / rem;
-        p = p < cap ? p : cap;
-    }
-    return p > 1 ? RowPlan{chunks - rem, p} : RowPlan{chunks, 1u};
+    if (chunks == 0 || slots == 0 || chunks > slots) return RowPlan{chunks, 1u};
+    uint32_t p = slots / chunks;
+    p = p < cap ? p : cap;
+    return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
 }
 
 template <int DP, int ST, int WAVES = 0, int QB = 0>
@@ -386,7 +381,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     const uint32_t chunk = whole ? bx : plan.whole + (bx - plan.whole) / plan.parts;
     const uint32_t qbase = chunk * kBlockQ;
     if (qbase >= count) return;                   // whole block exits together
-    if (!fb.all_full && fb.dense_masked) {
+    if (fb.dense_masked == kDenseMasked) {
         // a chunk whose queries the ring scan answers, all of them, has no work
         bool any = false;
         for (uint32_t i = threadIdx.x; i < (uint32_t)kBlockQ; i += Cfg::block)
@@ -498,7 +493,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
                 rr[p] = make_uint2(__shfl(rc[qb].x, c, 64), __shfl(rc[qb].y, c, 64));
                 qq[p] = (uint32_t)__shfl((int)qid[qb], c, 64);
                 ll[p] = wbase + (uint32_t)(qb * 32 + c) < count &&
-                        (fb.all_full || !fb.dense_masked || w.route[qq[p]] != kRouteScan);
+                        (fb.dense_masked != kDenseMasked || w.route[qq[p]] != kRouteScan);
                 C[p].issue(ix, w, qq[p], rr[p], ll[p], r);
             }
 #pragma unroll
@@ -527,7 +522,7 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
          base += gridDim.x * 16u) {
         const uint32_t i = base + (threadIdx.x >> 4);
         const bool live = i < count &&
-                          (fb.all_full || !fb.dense_masked || w.route[i] != kRouteScan);
+                          (fb.dense_masked != kDenseMasked || w.route[i] != kRouteScan);
         const uint32_t q = live ? (list ? list[i] : i) : 0u;
         uint2 rec = make_uint2(0u, 0u);
         if (live) {
@@ -576,7 +571,11 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
                        dim3(Cfg::block), 0, st, ix, fb, w, slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // split queries: fewer than min(chunks, slots) chunks' worth
+    // split queries: fewer than min(chunks, slots) chunks' worth.  With the
+    // queries in order the plan is known here: no split, no resolve pass
+    if ((fb.all_full || fb.dense_masked) &&
+        row_plan((uint32_t)std::min<int64_t>(chunks, 0x7FFFFFFF), slots).parts == 1)
+        return hipSuccess;
     const int64_t sq = std::min<int64_t>(chunks, resident) * kBlockQ;
     const int64_t rb = std::min<int64_t>((sq + 15) / 16, 4096);   // 16 queries per 256-thread block
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_resolve<DP, kBlockQ>), dim3((unsigned)rb), dim3(256),

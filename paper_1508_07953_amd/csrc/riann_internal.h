@@ -130,6 +130,8 @@ struct FrameDesc {
 
 // Passed by value (kernel arguments), so a launch needs no descriptor copy
 // and can be captured in a graph as is.
+constexpr int32_t kDenseMasked = 1, kDenseInOrder = 2;
+
 struct FrameBatch {
     int32_t n;               // frames
     int32_t ntiles;          // extraction tiles over all frames
@@ -137,9 +139,11 @@ struct FrameBatch {
     int32_t all_full;        // every frame in full-search mode
     int32_t knn;             // neighbours per query (1: prev/out/ssd are Hq x Wq;
                              // k > 1: Hq x Wq x k, each row ascending)
-    int32_t dense_masked;    // 1: the dense search takes every query in order and
-                             // skips those the ring scan answers (route code
-                             // kRouteScan) instead of reading the dense list
+    int32_t dense_masked;    // kDenseMasked: the dense search takes every query in
+                             // order and skips those the ring scan answers (route
+                             // code kRouteScan) instead of reading the dense list;
+                             // kDenseInOrder: every query in order, none was
+                             // ring-scanned; 0: the dense list
     FrameDesc f[kMaxBatch];
 };
 
