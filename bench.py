@@ -398,7 +398,7 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=N
     def frame_of(s, k):
         return frames[s][k % frames_per_stream]
 
-    def run(max_batch, inflight, trace, scale, concurrent=False):
+    def run(max_batch, inflight, trace, scale, concurrent="auto"):
         srv = serve.Server(idx, max_batch=max_batch, inflight=inflight, host_results=True,
                            concurrent=concurrent)
         sids = {s: srv.open_stream(*shape_of(s)) for s in range(streams)}
@@ -421,9 +421,11 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=N
     # throughput at saturation: every frame of the trace is there from the start
     sat_trace = [(0.0, s, k) for k in range(1, 4) for s in range(streams)]
     plain_sat = run(1, 1, sat_trace, 1.0)
+    # the server's default: two batches side by side on two HIP streams
+    # while frames are left waiting (here always), back to back otherwise
     serve_sat = run(40, 2, sat_trace, 1.0)
-    # two batches side by side on two HIP streams: one batch's extraction and
-    # ring phase overlap the other's dense search
+    # batches always back to back on one HIP stream; always side by side
+    serve_sat_seq = run(40, 2, sat_trace, 1.0, concurrent=False)
     serve_sat_cc = run(40, 2, sat_trace, 1.0, concurrent=True)
     # latency at a sustainable rate: lambda * 30 fps per stream with lambda
     # set to ~70% of the serving capacity measured above
@@ -433,6 +435,7 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=N
     trace = [(t, s, k + 1) for (t, s, k) in trace]
     plain_lat = run(1, 1, trace, 1.0)
     serve_lat = run(40, 2, trace, 1.0)
+    serve_lat_seq = run(40, 2, trace, 1.0, concurrent=False)
     # latency-first setting: one batch in flight, each batch takes everything
     # ready when the previous one completes
     serve_lat1 = run(40, 1, trace, 1.0)
@@ -441,12 +444,16 @@ def serving_compare(dev, streams, frames_per_stream, seconds, log_fn, shape_of=N
     return {"workload": label or (f"{streams} RGB streams (360p/720p/1080p by id mod 3), "
                                   "8x8x3 patches, n=65536, K=32, Poisson arrivals"),
             "io": "frames from pinned host memory, fields and SSD maps back to pinned host memory",
+            "serving_mode": "two batches in flight, side by side on two HIP streams while "
+                            "frames wait beyond the batch, else back to back (concurrent='auto')",
             "saturation": {"plain": plain_sat, "serving": serve_sat,
-                           "serving_concurrent": serve_sat_cc},
+                           "serving_back_to_back": serve_sat_seq,
+                           "serving_side_by_side": serve_sat_cc},
             "lambda": lam, "offered_fps": 30.0 * lam * streams, "trace_seconds": seconds,
             "at_lambda": {"plain": plain_lat, "serving": serve_lat,
+                          "serving_back_to_back": serve_lat_seq,
                           "serving_one_in_flight": serve_lat1,
-                          "serving_concurrent": serve_lat_cc}}
+                          "serving_side_by_side": serve_lat_cc}}
 
 
 def main():

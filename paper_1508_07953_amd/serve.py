@@ -7,9 +7,12 @@ previous field resident on the device, admits streams while their device
 memory fits a budget, and forms batches from whatever frames are ready --
 at most one frame per stream in flight, since frame t+1 depends on frame t's
 field.  Each batch is one `riann_match_batch` submission; batches formed while
-others run are queued behind them on the device (or, with concurrent=True,
-run side by side on separate HIP streams).  Every
-result is exact, so a stream's fields are the same alone and in any mix.
+others run are queued behind them on the device (concurrent=False), run side
+by side on separate HIP streams (True), or (the default, "auto") run side by
+side only while frames are left waiting after the batch is formed, so a
+backlog fills the GPU through the tail of each launch while a short queue
+keeps each batch's latency that of running alone.  Every result is exact, so
+a stream's fields are the same alone and in any mix.
 
 `Server(..., max_batch=1, inflight=1)` is the plain mode: one frame at a time,
 each finished before the next starts.
@@ -78,7 +81,7 @@ class Server:
 
     def __init__(self, index: Index, max_batch: int = 40, inflight: int = 2,
                  memory_budget: Optional[int] = None, device=None,
-                 max_batch_queries: Optional[int] = 1_000_000, concurrent: bool = False,
+                 max_batch_queries: Optional[int] = 1_000_000, concurrent="auto",
                  host_results: bool = False):
         import torch
         self.torch = torch
@@ -87,7 +90,14 @@ class Server:
         self.inflight = max(1, int(inflight))
         # concurrent=False: batches queue back to back on one HIP stream (no
         # idle gap between them, no sharing slowdown); True: each in-flight
-        # batch gets its own HIP stream and they run side by side
+        # batch gets its own HIP stream and they run side by side; "auto":
+        # side by side while a backlog is left after forming the batch (the
+        # next batch's blocks fill the CUs the last round of a launch leaves
+        # idle), back to back otherwise
+        if concurrent != "auto":
+            if concurrent not in (False, True):
+                raise ValueError("concurrent must be False, True or 'auto'")
+            concurrent = bool(concurrent)
         self.concurrent = concurrent
         # a batch completes as a whole, so its size bounds the latency of the
         # small frames in it: stop adding frames once it holds this many
@@ -97,6 +107,7 @@ class Server:
         self.device = device if device is not None else torch.device("cuda")
         self.hip_streams = [torch.cuda.Stream(device=self.device)
                             for _ in range(self.inflight if concurrent else 1)]
+        self._last_hs = self.hip_streams[0]    # stream of the newest batch
         self.copy_stream = torch.cuda.Stream(device=self.device)
         self.host_results = host_results
         self.result_stream = torch.cuda.Stream(device=self.device) if host_results else None
@@ -251,12 +262,17 @@ class Server:
                 break
             picked.append(s)
             q += hq * wq
+        backlog = len(ready) > len(picked)
         ready = picked
-        if self.concurrent:
+        side_by_side = self.concurrent is True or (self.concurrent == "auto" and backlog)
+        if side_by_side:
             in_use = {id(b[1]) for b in self._batches}
             hs = next(x for x in self.hip_streams if id(x) not in in_use)
+        elif self._batches:
+            hs = self._last_hs                    # queue behind the newest batch
         else:
             hs = self.hip_streams[0]
+        self._last_hs = hs
         torch = self.torch
         items, meta, keep = [], [], []
         copies = False

@@ -36,9 +36,10 @@ def _ref_rgb(rng, n=700, K=12):
     return ref, gen.choose_keys(n, K, rng)
 
 
-def test_alone_equals_mix(env):
+@pytest.mark.parametrize("concurrent", ["auto", False, True])
+def test_alone_equals_mix(env, concurrent):
     torch, riann, serve, dev = env
-    print("[gpu case] serving alone vs mix", flush=True)
+    print(f"[gpu case] serving alone vs mix concurrent={concurrent}", flush=True)
     rng = np.random.default_rng(31)
     ref, keys = _ref_rgb(rng)
     idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
@@ -59,13 +60,15 @@ def test_alone_equals_mix(env):
         alone.append(fields)
     # mix: all streams through the server, frames submitted interleaved
     # batches of at most 3 frames, two batches in flight at once
-    srv = serve.Server(idx, max_batch=3, inflight=2)
+    srv = serve.Server(idx, max_batch=3, inflight=2, concurrent=concurrent)
     sids = [srv.open_stream(v[0].shape[0], v[0].shape[1]) for v in vids]
     got = {}
     for t in range(4):
         n0 = len(srv.completed)
         for si, v in zip(sids, dframes):
             srv.submit(si, v[t])
+            if t % 2:
+                srv.step()          # batches formed with and without a backlog
         srv.drain()
         for c in srv.completed[n0:]:
             got[(c.stream, c.seq)] = (c.field.cpu().numpy().copy(), c.ssd.cpu().numpy().copy())
@@ -94,7 +97,8 @@ def test_admission_and_close(env):
         vids.append([v.frame(t) for t in range(2)])
     dframes = [[torch.from_numpy(f).to(dev) for f in v] for v in vids]
     # budget: exactly what two active streams need -- the index once, two
-    # streams' buffers and the scratch of a batch of their two frames
+    # streams' buffers and, per HIP stream of the server, the scratch of a
+    # batch of their two frames
     probe = serve.Server(idx)
     probe.open_stream(40, 56)
     probe.open_stream(40, 56)
@@ -102,7 +106,9 @@ def test_admission_and_close(env):
     hq, wq = idx.field_shape(40, 56)
     two_frames = riann.footprint(300, 6, 8, 3, 1, 8, 8 + 2 * hq * wq - 1) - riann.footprint(
         300, 6, 8, 3, 1)
-    assert budget == probe.index_bytes + 2 * probe.stream_bytes(40, 56) + two_frames
+    assert len(probe.hip_streams) == 2              # the default: two batches in flight
+    assert budget == (probe.index_bytes + 2 * probe.stream_bytes(40, 56) +
+                      len(probe.hip_streams) * two_frames)
     assert probe.index_bytes == riann.footprint(300, 6, 8, 3, 1)
     srv = serve.Server(idx, memory_budget=budget)
     sids = [srv.open_stream(40, 56) for _ in vids]
