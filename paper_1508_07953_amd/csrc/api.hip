@@ -121,7 +121,7 @@ int64_t default_threshold(int64_t n) {
 }
 
 // Rows of the row-layout dense search's reference order (even Rc, then odd
-// Rc, each class padded to whole tiles, the whole to kRefAlign).  With
+// Rc, each class padded to whole tiles, the whole to kRowAlign).  With
 // Rc == nullptr: the most rows any reference set of this size can take.
 int64_t row_layout_rows(int64_t n, const std::vector<int32_t> *Rc) {
     int64_t n0 = n;
@@ -129,8 +129,8 @@ int64_t row_layout_rows(int64_t n, const std::vector<int32_t> *Rc) {
         n0 = 0;
         for (int64_t r = 0; r < n; ++r) n0 += ((*Rc)[(size_t)r] & 1) == 0;
     }
-    return Rc ? round_up(round_up(n0, kTile) + round_up(n - n0, kTile), kRefAlign)
-              : round_up(round_up(n, kTile) + kTile, kRefAlign);
+    return Rc ? round_up(round_up(n0, kTile) + round_up(n - n0, kTile), kRowAlign)
+              : round_up(round_up(n, kTile) + kTile, kRowAlign);
 }
 
 int64_t index_bytes(int64_t n, int D, int K, uint32_t flags) {

@@ -548,7 +548,7 @@ template <int DP, int WAVES = 0, int QB = 0>
 hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w, hipStream_t st) {
     using Cfg = RowCfg<DP, WAVES, QB>;
     constexpr int ST = DP <= 64 ? 8 : 4;
-    static_assert(kRefAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
+    static_assert(kRowAlign % (kTile * ST) == 0, "reference padding must cover whole stages");
     // The dense query count is known on the device only: the grid covers the
     // largest plan any count up to fb.Q can take, and surplus blocks return
     // at once.  (Splitting every chunk of a 720p frame -- 1,773 chunks on

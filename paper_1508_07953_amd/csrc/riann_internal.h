@@ -15,6 +15,7 @@ namespace riann {
 // Padding bytes (k >= D) are 0 on both sides and add nothing.
 constexpr int kTile = 32;        // references per dense tile (MFMA columns)
 constexpr int kRefAlign = 512;   // n is padded to whole 16-tile dense stages
+constexpr int kRowAlign = 256;   // row-layout references: whole 8-tile stages
 // Row-layout dense search: a query's running minimum over a segment of
 // 2^row_tile_bits(Dp) tiles is the key (Y << bits) | tile; every real Y is
 // below row_pad_y(Dp) = 2^(32 - bits) - 1 (Y <= Dp * 81409 / 2), the value
@@ -60,7 +61,7 @@ struct DevIndex {
     // Row-layout dense search (references as MFMA rows, queries as columns),
     // over its own reference order: first every reference with even Rc, then
     // every one with odd Rc, index order within each class, each class padded
-    // to whole tiles and the whole to kRefAlign (n_rows rows).  With
+    // to whole tiles and the whole to kRowAlign (n_rows rows).  With
     // p = Rc & 1 constant per tile, the lexicographic (Y, tile) minimum lies
     // in the tile that holds the (SSD, index) minimum.
     //   Rfr  n_rows x Dp, those rows in MFMA fragment order (as Rf)
