@@ -229,18 +229,21 @@ struct RowState {
 // Candidate check of one dense query by a 16-lane group.  rec = {Y,
 // tile << 2 | group mask}: lane r takes accumulator row r of the tile in each
 // masked lane group -- class-order row 32 tile + 8(r/4) + 4g + r%4 -- forms
-// its exact SSD with v_dot4 from the row's fragment bytes, and a 16-lane
-// reduction keeps the (SSD, reference index) minimum.  issue() starts the
-// loads that need only the record (Qc and the first masked group's row with
-// its {Rc, index}); finish() takes the query patch (global memory or LDS) and
-// does the rest, so a caller can have the loads of several queries in flight
-// before any waits.
+// its exact SSD with v_dot4 from the row's bytes, and a 16-lane reduction
+// keeps the (SSD, reference index) minimum.  The rows and their {Rc, index}
+// come from the (tile, group) block of the check table, contiguous, so a
+// query's check reads 16 Dp + 128 bytes in whole lines (the fragment layout
+// would spread them over twice the lines: at D = 64 this pass was bound by
+// those L2 reads).  issue() starts the loads that need only the record (Qc
+// and the first masked group's row with its {Rc, index}); finish() takes the
+// query patch (global memory or LDS), Qc and the query's frame and does the
+// rest, so a caller can have the loads of several queries in flight before
+// any waits.  A record whose group mask is 0 means no check (not live).
 template <int DP>
 struct RowCheck {
     static constexpr int KB = DP / 32;
     uint4 v[DP / 16];       // first candidate row of this lane (patch byte order)
     int2 ri;                // its {Rc, reference index}; index < 0: none
-    int qc;
 
     __device__ __forceinline__ static void row_bytes(const DevIndex &ix, int64_t tile, int m,
                                                      uint4 (&v)[DP / 16]) {
@@ -253,16 +256,22 @@ struct RowCheck {
         }
     }
 
-    __device__ __forceinline__ void issue(const DevIndex &ix, const Work &w, uint32_t q,
-                                          const uint2 &rec, bool live, int r) {
-        ri = make_int2(0, -1);
-        if (!live) return;
-        qc = w.qc[q];
+    // row r of the check block of (tile, group g) and its {Rc, index}
+    __device__ __forceinline__ static void check_row(const DevIndex &ix, int64_t tile, int g, int r,
+                                                     uint4 (&v)[DP / 16], int2 &ci) {
+        const int8_t *blk = ix.Rck + (tile * 2 + g) * (16 * DP + 128);
+        const uint4 *f = reinterpret_cast<const uint4 *>(blk + r * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 16; ++k) v[k] = f[k];
+        ci = reinterpret_cast<const int2 *>(blk + 16 * DP)[r];
+    }
+
+    // (the loads are unconditional -- a record without a group reads a row of
+    // tile 0 and drops it -- so a pass's loads stay countable in flight)
+    __device__ __forceinline__ void issue(const DevIndex &ix, const uint2 &rec, int r) {
         const int g = (rec.y & 1u) ? 0 : 1;
-        const int64_t tile = rec.y >> 2;
-        const int m = 8 * (r >> 2) + 4 * g + (r & 3);
-        ri = ix.Rci[tile * kTile + m];
-        row_bytes(ix, tile, m, v);
+        check_row(ix, rec.y >> 2, g, r, v, ri);
+        if ((rec.y & 3u) == 0u) ri = make_int2(0, -1);
     }
 
     __device__ __forceinline__ static int dot(const uint4 (&a)[DP / 16], const uint4 (&v)[DP / 16]) {
@@ -277,10 +286,27 @@ struct RowCheck {
         return d;
     }
 
-    __device__ __forceinline__ void finish(const DevIndex &ix, const FrameBatch &fb, const Work &w,
-                                           uint32_t q, const uint2 &rec, bool live, int lane,
-                                           const uint4 *patch) {
+    // min over the 16 lanes of a DPP row (one query's group): quad swaps,
+    // then the mirrored half-row and row, each lane ending with the minimum
+    template <int CTRL>
+    __device__ __forceinline__ static unsigned long long dpp_min(unsigned long long b) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+        const unsigned hi =
+            (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        return o < b ? o : b;
+    }
+
+    // ONE: a one-frame launch, whose field, SSD map and first query the
+    // caller passes as uniform values (out0, ssd0, qb0); otherwise the
+    // query's frame fid selects them from the descriptor table
+    template <bool ONE>
+    __device__ __forceinline__ void finish(const DevIndex &ix, const FrameBatch &fb, uint32_t q,
+                                           const uint2 &rec, int qc, int fid, int lane,
+                                           const uint4 *patch, int32_t *out0, uint32_t *ssd0,
+                                           int64_t qb0) {
         const int r = lane & 15;
+        const bool live = (rec.y & 3u) != 0u;
         unsigned long long best = ~0ull;
         if (live) {
             uint4 a[DP / 16];
@@ -291,33 +317,82 @@ struct RowCheck {
                 best = ((unsigned long long)ssd << 32) | (uint32_t)ri.y;
             }
             if ((rec.y & 3u) == 3u) {           // both lane groups reached the minimum
-                const int64_t tile = rec.y >> 2;
-                const int m = 8 * (r >> 2) + 4 + (r & 3);
-                const int2 rj = ix.Rci[tile * kTile + m];
+                uint4 u[DP / 16];
+                int2 rj;
+                check_row(ix, rec.y >> 2, 1, r, u, rj);
                 if (rj.y >= 0) {
-                    uint4 u[DP / 16];
-                    row_bytes(ix, tile, m, u);
                     const uint32_t ssd = (uint32_t)(qc + rj.x + 2 * dot(a, u));
                     const unsigned long long k2 = ((unsigned long long)ssd << 32) | (uint32_t)rj.y;
                     best = k2 < best ? k2 : best;
                 }
             }
         }
-#pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) {
-            const unsigned lo = __shfl_xor((unsigned)best, m, 64);
-            const unsigned hi = __shfl_xor((unsigned)(best >> 32), m, 64);
-            const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-            best = o < best ? o : best;
-        }
+        best = dpp_min<0xB1>(best);             // quad_perm [1,0,3,2]
+        best = dpp_min<0x4E>(best);             // quad_perm [2,3,0,1]
+        best = dpp_min<0x141>(best);            // row_half_mirror
+        best = dpp_min<0x140>(best);            // row_mirror
         if (live && r == 0) {
-            const FrameDesc *fdp = &fb.f[w.fid[q]];
-            const int64_t ql = (int64_t)q - fdp->qbase;
-            fdp->out[ql] = (int32_t)(uint32_t)best;
-            if (fdp->ssd) fdp->ssd[ql] = (uint32_t)(best >> 32);
+            int32_t *out = out0;
+            uint32_t *ssd = ssd0;
+            int64_t qbase = qb0;
+            if constexpr (!ONE) {
+                const FrameDesc *fdp = &fb.f[fid];
+                out = fdp->out;
+                ssd = fdp->ssd;
+                qbase = fdp->qbase;
+            }
+            const int64_t ql = (int64_t)q - qbase;
+            out[ql] = (int32_t)(uint32_t)best;
+            if (ssd) ssd[ql] = (uint32_t)(best >> 32);
         }
     }
 };
+
+// The candidate checks of a wavefront's 32 QB queries after its pass over
+// the references: 8 QB passes of four queries (one per 16-lane group), each
+// pass's candidate rows requested IF - 1 passes ahead, so a pass waits only
+// on its own loads.  The records, query ids, Qc and frame ids come from the
+// owning lanes by shuffles; the patches from LDS (STAGED) or global memory.
+template <int DP, int QB, int IF, bool STAGED, bool ONE>
+__device__ __forceinline__ void check_wave(const DevIndex &ix, const FrameBatch &fb, const Work &w,
+                                           const uint2 (&rc)[QB], const uint32_t (&qid)[QB],
+                                           const int (&qcl)[QB], const int (&fidl)[QB],
+                                           const int8_t *sp, int lane) {
+    constexpr int NP = QB * 8;
+    const int sub = lane >> 4, r = lane & 15;
+    int32_t *out0 = nullptr;
+    uint32_t *ssd0 = nullptr;
+    int64_t qb0 = 0;
+    if constexpr (ONE) {
+        out0 = fb.f[0].out;
+        ssd0 = fb.f[0].ssd;
+        qb0 = fb.f[0].qbase;
+    }
+    RowCheck<DP> C[IF];
+    uint2 rr[IF];
+    uint32_t qq[IF];
+    int qc[IF], fd[IF];
+    auto fetch = [&](int k) {
+        const int s = k % IF, qb = k / 8, c = (k % 8) * 4 + sub;
+        rr[s] = make_uint2(__shfl(rc[qb].x, c, 64), __shfl(rc[qb].y, c, 64));
+        qq[s] = (uint32_t)__shfl((int)qid[qb], c, 64);
+        qc[s] = __shfl(qcl[qb], c, 64);
+        fd[s] = ONE ? 0 : __shfl(fidl[qb], c, 64);
+        C[s].issue(ix, rr[s], r);
+    };
+#pragma unroll
+    for (int k = 0; k < IF - 1 && k < NP; ++k) fetch(k);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if (k + IF - 1 < NP) fetch(k + IF - 1);
+        const int s = k % IF, qb = k / 8, c = (k % 8) * 4 + sub;
+        const int8_t *patch = STAGED ? sp + (qb * 32 + c) * DP
+                                     : reinterpret_cast<const int8_t *>(w.patches) +
+                                           (int64_t)qq[s] * DP;
+        C[s].template finish<ONE>(ix, fb, qq[s], rr[s], qc[s], fd[s], lane,
+                                  reinterpret_cast<const uint4 *>(patch), out0, ssd0, qb0);
+    }
+}
 
 // How a launch covers `chunks` query chunks with `slots` resident blocks:
 // the first `whole` chunks run as one block each over every reference; each
@@ -461,11 +536,9 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
         }
         return;
     }
-    // the whole reference range: the wavefront checks its own queries, four
-    // at a time (one per 16-lane group), with the gathers of kInFlight such
-    // passes issued before any waits.  The records and query ids come from
-    // the owning lanes by shuffles, the query patches from the MFMA operand
-    // registers through the (now free) stage buffers.
+    // the whole reference range: the wavefront checks its own queries
+    // (check_wave), the query patches from the MFMA operand registers
+    // through the (now free) stage buffers.
     int8_t *const sp = s_buf + wv * (kWaveQ * DP);
     if constexpr (kStagePatches) {
         __syncthreads();                          // every wavefront is past its last tile
@@ -477,36 +550,31 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
                     S.Bq[qb][kb];
         __syncthreads();
     }
-    constexpr int kInFlight = Cfg::inflight;
-    const int sub = lane >> 4, r = lane & 15;
+    // each lane's own queries: Qc, frame id and liveness (past the dense
+    // count, or answered by the ring scan: group mask 0) read once, all
+    // loads together and unconditionally (every array holds the launch's
+    // queries), before the passes
+    int qcl[kQB], fidl[kQB];
+    uint32_t code[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-#pragma unroll
-        for (int h = 0; h < 32; h += 4 * kInFlight) {
-            RowCheck<DP> C[kInFlight];
-            uint2 rr[kInFlight];
-            uint32_t qq[kInFlight];
-            bool ll[kInFlight];
-#pragma unroll
-            for (int p = 0; p < kInFlight; ++p) {
-                const int c = h + 4 * p + sub;
-                rr[p] = make_uint2(__shfl(rc[qb].x, c, 64), __shfl(rc[qb].y, c, 64));
-                qq[p] = (uint32_t)__shfl((int)qid[qb], c, 64);
-                ll[p] = wbase + (uint32_t)(qb * 32 + c) < count &&
-                        (fb.dense_masked != kDenseMasked || w.route[qq[p]] != kRouteScan);
-                C[p].issue(ix, w, qq[p], rr[p], ll[p], r);
-            }
-#pragma unroll
-            for (int p = 0; p < kInFlight; ++p) {
-                const int c = h + 4 * p + sub;
-                const int8_t *patch = kStagePatches ? sp + (qb * 32 + c) * DP
-                                                    : reinterpret_cast<const int8_t *>(w.patches) +
-                                                          (int64_t)qq[p] * DP;
-                C[p].finish(ix, fb, w, qq[p], rr[p], ll[p], lane,
-                            reinterpret_cast<const uint4 *>(patch));
-            }
-        }
+        qcl[qb] = w.qc[qid[qb]];                  // qid is a valid query (clamped slot)
+        fidl[qb] = (int)w.fid[qid[qb]];
+        code[qb] = w.route[qid[qb]];
     }
+    const uint32_t masked = fb.dense_masked == kDenseMasked ? 1u : 0u;
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb) {
+        const uint32_t in = wbase + (uint32_t)(qb * 32 + col) < count ? 1u : 0u;
+        const uint32_t scan = code[qb] == (uint32_t)kRouteScan ? 1u : 0u;
+        rc[qb].y = (in & (masked & scan ^ 1u)) ? rc[qb].y : 0u;
+    }
+    if (fb.n == 1)
+        check_wave<DP, kQB, Cfg::inflight, kStagePatches, true>(ix, fb, w, rc, qid, qcl, fidl, sp,
+                                                               lane);
+    else
+        check_wave<DP, kQB, Cfg::inflight, kStagePatches, false>(ix, fb, w, rc, qid, qcl, fidl, sp,
+                                                                lane);
 }
 
 template <int DP, int BQ>
@@ -537,10 +605,13 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
             }
             rec = make_uint2((uint32_t)(best >> 32), (uint32_t)best);
         }
+        const int qc = live ? w.qc[q] : 0;
+        const int fid = live && fb.n > 1 ? (int)w.fid[q] : 0;
         RowCheck<DP> C;
-        C.issue(ix, w, q, rec, live, r);
-        C.finish(ix, fb, w, q, rec, live, lane,
-                 reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP));
+        C.issue(ix, rec, r);
+        C.template finish<false>(ix, fb, q, rec, qc, fid, lane,
+                                 reinterpret_cast<const uint4 *>(w.patches + (int64_t)q * DP),
+                                 nullptr, nullptr, 0);
     }
 }
 
