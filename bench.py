@@ -705,6 +705,11 @@ def main():
                              "note": "route codes of every query, then the exact smallest-ring "
                                      "search of the queries the extraction kernel left (binary "
                                      "searches: latency), and their ring scan"}
+        if not prof_all["extract"]["launches"]:
+            sec["k_extract"] = {"launched": False,
+                                "note": "every query goes dense and the patch is 8x8 gray: the "
+                                        "dense kernel cuts each query patch from the frame "
+                                        "itself (and counts the routing), no extraction launch"}
         if prof_all["extract"]["launches"]:
             # extraction (frame once; patch, Qc, frame id, route code written)
             # and routing (prev entry, the previous match's row and Rc read)

@@ -616,18 +616,24 @@ riann_status_t run_batch(riann_index *h, FrameBatch &fb, hipStream_t st, int knn
     // one threshold for the whole launch: the extraction kernel routes on it
     // and the ring kernel decides the rest with it
     const int64_t threshold = h->threshold.load();
-    {
+    // With route codes and a threshold below 1 the extraction kernel sends
+    // every query to the dense search (m* >= 1 by containment): the ring
+    // kernel would find nothing to do
+    const bool ring_empty = fb.dense_masked && knn == 1 && h->dix.K > 0 &&
+                            !h->dix.exact_mstar && threshold >= 0 && threshold < 1;
+    // One frame whose every query goes dense, of a shape the dense search can
+    // cut from the frame itself: no extraction launch (the dense kernel also
+    // counts a ring frame's routing)
+    fb.fused = rows && fb.n == 1 && (all_full || ring_empty) && dense_fused_supported(h->dix)
+                   ? 1 : 0;
+    fb.stats = h->dstats;
+    if (!fb.fused) {
         // the extraction kernel also clears the ring and dense list counters
         KTimer tm(h, RIANN_K_EXTRACT, st, timed);
         e = launch_extract(h->dix, fb, w, threshold, h->dstats, st);
         tm.stop();
         if (e != hipSuccess) return hip_fail(e, "k_extract launch");
     }
-    // With route codes and a threshold below 1 the extraction kernel has sent
-    // every query to the dense search (m* >= 1 by containment): the ring
-    // kernel would find nothing to do
-    const bool ring_empty = fb.dense_masked && knn == 1 && h->dix.K > 0 &&
-                            !h->dix.exact_mstar && threshold >= 0 && threshold < 1;
     if (!all_full && !ring_empty) {
         {
             KTimer tm(h, RIANN_K_RING, st, timed);

@@ -417,6 +417,75 @@ __host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots) {
     return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
 }
 
+// Bytes [o, o + 8) of the frame as two words: the aligned words holding
+// them, realigned (the third only when o is not word-aligned: every word read
+// holds a byte of the frame).
+__device__ __forceinline__ uint2 frame_bytes8(const uint8_t *p) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    const uint32_t r = (uint32_t)(a & 3u);
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(a - r);
+    const uint32_t d0 = d[0], d1 = d[1];
+    const uint32_t d2 = r ? d[2] : 0u;
+    return make_uint2(__builtin_amdgcn_alignbyte(d1, d0, r), __builtin_amdgcn_alignbyte(d2, d1, r));
+}
+
+// The fused dense search's own patch assembly (8 x 8 gray, one frame): query
+// q's MFMA B fragments -- bytes 32 kb + 16 grp .. + 16 of the patch in
+// (dy, dx) order, rows 4 kb + 2 grp and the next, encoded a = q ^ 0x7F --
+// and its Qc = sum (a + 1)^2 over the 64 bytes, the lane pair (grp 0 and 1)
+// each summing its half.  The extraction kernel's encoding, done in place.
+__device__ __forceinline__ void fused_patch(const FrameDesc &fa, int s, uint32_t q, int grp,
+                                            v4i (&Bq)[2], int &qc) {
+    const uint32_t qy = q / (uint32_t)fa.Wq, qx = q - qy * (uint32_t)fa.Wq;
+    const uint8_t *base = fa.frame + (int64_t)qy * s * fa.pitch + (int64_t)qx * s;
+    int sa2 = 0, sa = 0;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const int dy = 4 * kb + 2 * grp;
+        const uint2 r0 = frame_bytes8(base + (int64_t)dy * fa.pitch);
+        const uint2 r1 = frame_bytes8(base + (int64_t)(dy + 1) * fa.pitch);
+        const uint32_t wd[4] = {r0.x ^ 0x7F7F7F7Fu, r0.y ^ 0x7F7F7F7Fu, r1.x ^ 0x7F7F7F7Fu,
+                                r1.y ^ 0x7F7F7F7Fu};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sa2 = __builtin_amdgcn_sdot4((int)wd[i], (int)wd[i], sa2, false);
+            sa = __builtin_amdgcn_sdot4((int)wd[i], 0x01010101, sa, false);
+        }
+        Bq[kb] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    }
+    sa2 += __shfl_xor(sa2, 32, 64);
+    sa += __shfl_xor(sa, 32, 64);
+    qc = sa2 + 2 * sa + 64;
+}
+
+// A fused ring frame's routing counts, as the extraction kernel would have
+// made them: every query goes dense, those with a valid previous match on
+// the bound m* >= 1, the others as no-prior queries (m* = n).  Lane group 0
+// of each wavefront counts its 32 QB queries; pv holds their previous
+// matches, read before the pass over the references.
+template <int QB>
+__device__ __forceinline__ void fused_counts(const DevIndex &ix, const FrameBatch &fb,
+                                             uint32_t wbase, uint32_t count,
+                                             const int32_t (&pv)[QB], int lane) {
+    unsigned long long nq = 0, np = 0;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+        const bool valid = lane < 32 && wbase + (uint32_t)(qb * 32 + lane) < count;
+        const bool noprior = pv[qb] < 0 || (int64_t)pv[qb] >= ix.n;
+        nq += (unsigned long long)__popcll(__ballot(valid));
+        np += (unsigned long long)__popcll(__ballot(valid && noprior));
+    }
+    if (lane == 0 && nq) {
+        stat_add(fb.stats, ST_QUERIES, nq);
+        stat_add(fb.stats, ST_DENSE, nq);
+        if (np) {
+            stat_add(fb.stats, ST_NOPRIOR, np);
+            stat_add(fb.stats, ST_MSTAR, np * (unsigned long long)ix.n);
+        }
+        if (nq > np) stat_add(fb.stats, ST_BOUND, nq - np);
+    }
+}
+
 template <int DP, int ST, int WAVES = 0, int QB = 0>
 __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(DevIndex ix,
                                                                             FrameBatch fb, Work w,
@@ -475,18 +544,38 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
 
     RowState<DP, ST, kQB> S;
     uint32_t qid[kQB];
+    int qcf[kQB];                                 // Qc of this lane's queries (fused)
+    const bool fused = DP == 64 && fb.fused;
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
         const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
         qid[qb] = list ? list[slot] : slot;
-        const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) + (int64_t)qid[qb] * DP +
-                            grp * 16;
+        qcf[qb] = 0;
+        bool built = false;
+        if constexpr (DP == 64) {
+            if (fused) {
+                fused_patch(fb.f[0], ix.s, qid[qb], grp, S.Bq[qb], qcf[qb]);
+                built = true;
+            }
+        }
+        if (!built) {
+            const int8_t *src = reinterpret_cast<const int8_t *>(w.patches) +
+                                (int64_t)qid[qb] * DP + grp * 16;
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) S.Bq[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
+            for (int kb = 0; kb < KB; ++kb)
+                S.Bq[qb][kb] = *reinterpret_cast<const v4i *>(src + kb * 32);
+        }
         S.key[qb] = ~0u;
         S.bY[qb] = ~0u;
         S.bT[qb] = 0u;
     }
+    // a fused ring frame's previous matches, counted after the pass (one
+    // part of a split chunk counts its queries)
+    const bool counts = fused && !fb.all_full && split == 0;
+    int32_t pvq[kQB];
+#pragma unroll
+    for (int qb = 0; qb < kQB; ++qb)
+        pvq[qb] = counts && grp == 0 && fb.f[0].prev ? fb.f[0].prev[qid[qb]] : -1;
     __syncthreads();
 
     int seg0 = s_begin;                           // first stage of the key segment
@@ -505,6 +594,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
         }
     }
     S.fold((uint32_t)(seg0 * ST));
+    if (counts) fused_counts(ix, fb, qbase + (uint32_t)(wv * kWaveQ), count, pvq, lane);
 
     // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
     // accumulator order): the lexicographically smaller (Y, tile) wins; equal
@@ -533,6 +623,16 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
         for (int qb = 0; qb < kQB; ++qb) {
             const uint32_t slot = wbase + (uint32_t)(qb * 32 + col);
             if (slot < count && grp == 0) dst[slot] = make_uint4(rc[qb].x, rc[qb].y, 0u, 0u);
+            if (fused && split == 0 && slot < count) {
+                // the resolve pass checks these queries from their stored
+                // patches and Qc, which no extraction kernel wrote
+                int8_t *pd = reinterpret_cast<int8_t *>(w.patches) + (int64_t)qid[qb] * DP +
+                             grp * 16;
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    *reinterpret_cast<v4i *>(pd + kb * 32) = S.Bq[qb][kb];
+                if (grp == 0) w.qc[qid[qb]] = qcf[qb];
+            }
         }
         return;
     }
@@ -558,9 +658,15 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     uint32_t code[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-        qcl[qb] = w.qc[qid[qb]];                  // qid is a valid query (clamped slot)
-        fidl[qb] = (int)w.fid[qid[qb]];
-        code[qb] = w.route[qid[qb]];
+        if (fused) {                              // one frame, every query dense
+            qcl[qb] = qcf[qb];
+            fidl[qb] = 0;
+            code[qb] = kRouteFull;
+        } else {
+            qcl[qb] = w.qc[qid[qb]];              // qid is a valid query (clamped slot)
+            fidl[qb] = (int)w.fid[qid[qb]];
+            code[qb] = w.route[qid[qb]];
+        }
     }
     const uint32_t masked = fb.dense_masked == kDenseMasked ? 1u : 0u;
 #pragma unroll

@@ -217,6 +217,10 @@ hipError_t launch_rows_knn_t(const DevIndex &ix, const FrameBatch &fb, const Wor
 
 bool dense_rows_supported(const DevIndex &ix) { return ix.n_rows > 0; }
 
+bool dense_fused_supported(const DevIndex &ix) {
+    return ix.n_rows > 0 && ix.Dp == 64 && ix.p == 8 && ix.C == 1;
+}
+
 bool knn_rows_supported(const DevIndex &ix) {
     return ix.n_rows > 0 && ix.n_rows / kTile <= ((int64_t)1 << row_tile_bits(ix.Dp));
 }

@@ -151,6 +151,10 @@ struct FrameBatch {
                              // code kRouteScan) instead of reading the dense list;
                              // kDenseInOrder: every query in order, none was
                              // ring-scanned; 0: the dense list
+    int32_t fused = 0;       // 1: one frame, every query dense, no extraction
+                             // launch: the dense search reads its patches from
+                             // the frame itself (dense_fused_supported shapes)
+    unsigned long long *stats = nullptr;  // routing counts of a fused ring frame
     FrameDesc f[kMaxBatch];
 };
 
@@ -227,6 +231,10 @@ hipError_t launch_dense(const DevIndex &ix, const FrameBatch &fb, const Work &w,
 // own candidates unless the reference range is split over several blocks,
 // when a resolve kernel merges the parts first.
 bool dense_rows_supported(const DevIndex &ix);
+// Patch shapes whose row-layout dense search can assemble its query patches
+// from the frame itself (8 x 8 gray): a one-frame full search, or a ring frame
+// at routing threshold 0, then runs without the extraction launch.
+bool dense_fused_supported(const DevIndex &ix);
 hipError_t launch_dense_rows(const DevIndex &ix, const FrameBatch &fb, const Work &w,
                              hipStream_t st);
 // The block shapes built for patch width Dp as (waves, cols) pairs, the
