@@ -367,7 +367,10 @@ riann_status_t riann_get_params(riann_index_t h, riann_params_t *p);
  * riann_set_dense_threshold -- change the routing threshold (queries whose
  * smallest ring holds more than `threshold` candidates use the dense search)
  * for launches issued after the call; threshold >= 0.  Routing never changes
- * a result, only the time it takes (the autotuner picks this value).
+ * a result, only the time it takes (the autotuner picks this value).  At 0
+ * no query can be ring-scanned (every ring holds the nearest neighbour, so
+ * m* >= 1): the ring phase is not run and every query with a previous match
+ * is counted as bound_routed.
  */
 riann_status_t riann_set_dense_threshold(riann_index_t h, int64_t threshold);
 
@@ -420,7 +423,11 @@ riann_status_t riann_destroy(riann_index_t h);
  * of its own: RIANN_FLAG_GATHER_SCAN, RIANN_FLAG_COLUMN_DENSE or k-NN
  * fields), RIANN_K_DENSE (dense search of routed queries), RIANN_K_FULL
  * (dense search of whole frames), RIANN_K_EXTRACT (patch extraction, run
- * first for every frame; in a ring launch it also routes queries).
+ * first for every frame; in a ring launch it also routes queries).  A
+ * one-frame launch whose every query goes dense -- a full search, or a ring
+ * frame at routing threshold 0 -- with 8x8 one-channel patches runs no
+ * extraction: its dense search cuts the patches from the frame itself (and
+ * counts the routing), so only RIANN_K_FULL or RIANN_K_DENSE records it.
  */
 #define RIANN_K_RING 0
 #define RIANN_K_SCAN 1
