@@ -498,13 +498,17 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     // the two reference stages; after the last tile, the query patches of
     // narrow patches (wide ones are read from global memory by the check)
     constexpr bool kStagePatches = DP <= 96;
-    constexpr int PATCHES = kStagePatches ? kBlockQ * DP : 0;
-    constexpr int BUF = 2 * STAGE > PATCHES ? 2 * STAGE : PATCHES;
+    // each stage buffer is its own LDS array, so the compiler can tell a
+    // read of one from the DMA filling the other and need not wait for the
+    // DMA before computing on the first; after the last tile the two hold
+    // the query patches, the first half of the wavefronts' in each
+    constexpr int HALF_PATCHES = kStagePatches ? kBlockQ * DP / 2 : 0;
+    constexpr int HALF = STAGE > HALF_PATCHES ? STAGE : HALF_PATCHES;
     constexpr int SPS = (1 << row_tile_bits(DP)) / ST;  // stages per key segment
     static_assert(SPS % 2 == 0, "stage pairs never straddle a segment");
-    __shared__ __attribute__((aligned(16))) int8_t s_buf[BUF];
-    int8_t *const s_f0 = s_buf;
-    int8_t *const s_f1 = s_buf + STAGE;
+    static_assert(kWaves % 2 == 0, "the patch staging splits the wavefronts in halves");
+    __shared__ __attribute__((aligned(16))) int8_t s_f0[HALF];
+    __shared__ __attribute__((aligned(16))) int8_t s_f1[HALF];
     __shared__ __attribute__((aligned(16))) int32_t s_h0[ST * kTile];
     __shared__ __attribute__((aligned(16))) int32_t s_h1[ST * kTile];
 
@@ -639,7 +643,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     // the whole reference range: the wavefront checks its own queries
     // (check_wave), the query patches from the MFMA operand registers
     // through the (now free) stage buffers.
-    int8_t *const sp = s_buf + wv * (kWaveQ * DP);
+    int8_t *const sp = (wv < kWaves / 2 ? s_f0 : s_f1) + (wv % (kWaves / 2)) * (kWaveQ * DP);
     if constexpr (kStagePatches) {
         __syncthreads();                          // every wavefront is past its last tile
 #pragma unroll
