@@ -495,7 +495,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-vs-plain comparison")
     ap.add_argument("--serving-streams", type=int, default=64)
-    ap.add_argument("--serving-seconds", type=float, default=4.0)
+    ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--ring-forced-frames", type=int, default=3,
                     help="frames matched with every query on the ring path (threshold n) "
                          "after the timed region; 0 skips")
