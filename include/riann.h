@@ -209,7 +209,8 @@ riann_status_t riann_match_frame(riann_index_t h, const uint8_t *frame_dev,
  * a larger frame returns RIANN_E_UNSUPPORTED with the bytes it needs.
  * Every call on one GPU shares that array: calls that overlap on one GPU
  * (other streams, other threads, other indexes) race and must be ordered by
- * the caller.  The list counters are cleared by the call's own first kernel.
+ * the caller.  The list counters a call uses are cleared by its own
+ * extraction kernel (a call that needs no extraction uses none).
  * Kernel timing (riann_set_profiling) is not recorded for this call.
  */
 riann_status_t riann_match_frame_noalloc(riann_index_t h, const uint8_t *frame_dev,
