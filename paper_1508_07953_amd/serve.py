@@ -11,8 +11,11 @@ others run are queued behind them on the device (concurrent=False), run side
 by side on separate HIP streams (True), or (the default, "auto") run side by
 side only while frames are left waiting after the batch is formed, so a
 backlog fills the GPU through the tail of each launch while a short queue
-keeps each batch's latency that of running alone.  Every result is exact, so
-a stream's fields are the same alone and in any mix.
+keeps each batch's latency that of running alone.  A batch holds at most
+max_batch_queries queries, a cap that grows with a backlog (up to
+backlog_batch_queries): larger launches amortise the ragged last round of
+their query chunks.  Every result is exact, so a stream's fields are the same
+alone and in any mix.
 
 `Server(..., max_batch=1, inflight=1)` is the plain mode: one frame at a time,
 each finished before the next starts.
@@ -82,7 +85,8 @@ class Server:
     def __init__(self, index: Index, max_batch: int = 40, inflight: int = 2,
                  memory_budget: Optional[int] = None, device=None,
                  max_batch_queries: Optional[int] = 1_000_000, concurrent="auto",
-                 host_results: bool = False):
+                 host_results: bool = False,
+                 backlog_batch_queries: Optional[int] = 8_400_000):
         import torch
         self.torch = torch
         self.index = index
@@ -101,9 +105,14 @@ class Server:
         self.concurrent = concurrent
         # a batch completes as a whole, so its size bounds the latency of the
         # small frames in it: stop adding frames once it holds this many
-        # queries (a lone larger frame still goes alone).  About one 720p
-        # frame fills the GPU; frames that large gain nothing from batching.
+        # queries (a lone larger frame still goes alone)
         self.max_batch_queries = max_batch_queries
+        # with a backlog the cap grows to the ready queries' share per batch
+        # in flight, up to this many: each dense launch then covers more
+        # frames and the ragged last round of its query chunks weighs less
+        # (saturation throughput +4 % at 2 M queries, +8 % at 8 M on the
+        # 360p/720p/1080p mix), while a short queue keeps the small cap
+        self.backlog_batch_queries = backlog_batch_queries
         self.device = device if device is not None else torch.device("cuda")
         self.hip_streams = [torch.cuda.Stream(device=self.device)
                             for _ in range(self.inflight if concurrent else 1)]
@@ -142,8 +151,9 @@ class Server:
             return 0
         qs = sorted(frame_queries, reverse=True)
         q = sum(qs[:self.max_batch])
-        if self.max_batch_queries is not None:
-            q = min(q, max(self.max_batch_queries, qs[0]))
+        cap = self._largest_cap()
+        if cap is not None:
+            q = min(q, max(cap, qs[0]))
         p = self.index.params
         # the scratch of q queries: a 1 x q field (one patch row of width
         # patch + (q - 1) * stride)
@@ -246,6 +256,23 @@ class Server:
         n += sum(len(q) for q in self._pending_queues.values())
         return n + sum(len(b[2]) for b in self._batches)
 
+    def _largest_cap(self) -> Optional[int]:
+        """The largest query cap a batch can get (None: no cap)."""
+        if self.max_batch_queries is None:
+            return None
+        return max(self.max_batch_queries, self.backlog_batch_queries or 0)
+
+    def _batch_cap(self, ready) -> Optional[int]:
+        """The query cap of the next batch: the base cap, raised with a
+        backlog to the ready queries' share per batch in flight."""
+        if self.max_batch_queries is None:
+            return None
+        cap = self.max_batch_queries
+        if self.backlog_batch_queries:
+            rq = sum(self._queries(s.H, s.W) for s in ready)
+            cap = max(cap, min(self.backlog_batch_queries, rq // self.inflight))
+        return cap
+
     def _launch(self) -> bool:
         if len(self._batches) >= self.inflight:
             return False
@@ -253,12 +280,12 @@ class Server:
         if not ready:
             return False
         ready.sort(key=lambda s: s.queue[0][1])          # oldest arrival first
+        cap = self._batch_cap(ready)
         picked, q = [], 0
         for s in ready:
             hq, wq = self.index.field_shape(s.H, s.W)
             if picked and (len(picked) >= self.max_batch or
-                           (self.max_batch_queries is not None and
-                            q + hq * wq > self.max_batch_queries)):
+                           (cap is not None and q + hq * wq > cap)):
                 break
             picked.append(s)
             q += hq * wq

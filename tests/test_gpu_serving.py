@@ -207,3 +207,40 @@ def test_host_frames_and_host_results(env, plain):
             assert np.array_equal(o.reshape(-1), bi), (k, t)
             assert np.array_equal(s.reshape(-1).astype(np.uint32), bd), (k, t)
     idx.close()
+
+
+def test_backlog_grows_batches(env):
+    """With a backlog the batch cap grows to the ready queries' share per batch
+    in flight (up to backlog_batch_queries); without one the base cap holds.
+    Fields stay exact either way."""
+    torch, riann, serve, dev = env
+    print("[gpu case] serving backlog batch cap", flush=True)
+    rng = np.random.default_rng(37)
+    ref, keys = _ref_rgb(rng, n=500, K=8)
+    idx = riann.Index.build(ref, keys, patch=8, channels=3, stride=1)
+    vids = _streams(rng, 8)
+    qs = [idx.field_shape(v[0].shape[0], v[0].shape[1]) for v in vids]
+    qmax = max(h * w for h, w in qs)
+    for grow in (True, False):
+        srv = serve.Server(idx, max_batch=40, inflight=2, max_batch_queries=qmax,
+                           backlog_batch_queries=10 ** 7 if grow else None)
+        sids = [srv.open_stream(v[0].shape[0], v[0].shape[1]) for v in vids]
+        for si, v in zip(sids, vids):
+            srv.submit(si, torch.from_numpy(v[0]).to(dev))
+        srv.step()
+        qmap = {si: h * w for si, (h, w) in zip(sids, qs)}
+        batch_q = [sum(qmap[m[0]] for m in b[2]) for b in srv._batches]
+        total = sum(qmap.values())
+        if grow:
+            # eight ready frames, two batches in flight: the first batch's cap
+            # is half the ready queries, above the base cap
+            assert batch_q[0] > qmax and batch_q[0] <= max(qmax, total // 2), batch_q
+        else:
+            assert all(bq <= qmax for bq in batch_q), batch_q
+        srv.drain()
+        for c in srv.completed:
+            k = sids.index(c.stream)
+            bi, bd = oracle.brute_force(oracle.extract(vids[k][0], 8, 1), ref)
+            assert np.array_equal(c.field.cpu().numpy().reshape(-1), bi)
+            assert np.array_equal(c.ssd.cpu().numpy().reshape(-1).astype(np.uint32), bd)
+    idx.close()
