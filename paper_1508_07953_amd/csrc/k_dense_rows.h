@@ -29,7 +29,7 @@
 // as resident block slots splits each chunk's reference range over up to
 // four blocks, so a small frame fills the chip; the parts leave records that
 // a resolve kernel merges before the same check.  Larger launches run whole
-// chunks only (see row_plan).
+// chunks, a nearly empty last round as paired half-size blocks (row_plan).
 #pragma once
 #include "riann_internal.h"
 
@@ -88,6 +88,12 @@ struct RowCfg {
 #define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
 #endif                                         // (2: within 1 %, 25 more registers)
 constexpr int kLookahead = RIANN_ROWS_LOOKAHEAD;
+#ifndef RIANN_ROWS_PAIRS
+#define RIANN_ROWS_PAIRS 1                     // 0: the last round's chunks run whole
+#endif
+#ifndef RIANN_ROWS_PAIR_DIV
+#define RIANN_ROWS_PAIR_DIV 8                  // pair a last round of <= slots / this chunks
+#endif
 
 template <int KB, int ST, int WAVES>
 __device__ __forceinline__ void stage_dma(const int8_t *__restrict__ gf,
@@ -173,11 +179,13 @@ struct RowState {
         }
     }
 
-    // all tiles of one LDS stage, as a sequence of (tile, query block) items:
+    // NT tiles of one LDS stage (all of them, or one half for a wavefront of
+    // a pair), as a sequence of (tile, query block) items:
     // the MFMA chain of item i + LA is issued before the minimum tree of
     // item i, so the tree reads an accumulator whose chain has finished while
     // the later chains run (LA + 1 accumulators, used in turn).  The next
     // tile's LDS operands are read one item before its first chain.
+    template <int NT>
     __device__ __forceinline__ void stage(const int8_t *lf, const int32_t *lh, uint32_t t0s,
                                           int lane, int grp) {
         constexpr int LA = kLookahead;
@@ -189,15 +197,15 @@ struct RowState {
 #pragma unroll
         for (int j = 0; j < LA; ++j) mma(j, Af[0], H[0], acc[j]);
 #pragma unroll
-        for (int u = 0; u < ST; ++u) {
+        for (int u = 0; u < NT; ++u) {
             const int cur = u & 1;
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) {
                 const int it = u * QB + qb, nx = it + LA;
-                if (qb == QB - 1 - LA && u + 1 < ST)
+                if (qb == QB - 1 - LA && u + 1 < NT)
                     load_tile(lf, lh, u + 1, lane, grp, Af[cur ^ 1], H[cur ^ 1]);
                 if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(1);
-                if (nx < ST * QB)
+                if (nx < NT * QB)
                     mma(nx % QB, Af[(nx / QB) & 1], H[(nx / QB) & 1], acc[nx % (LA + 1)]);
                 if (RIANN_ROWS_SETPRIO) __builtin_amdgcn_s_setprio(0);
                 track(qb, acc[it % (LA + 1)], t0s + (uint32_t)u);
@@ -400,21 +408,32 @@ __device__ __forceinline__ void check_wave(const DevIndex &ix, const FrameBatch 
 // parts).  Only a launch with at most half as many chunks as slots splits:
 // every chunk into as many parts as fit the slots in one round (at most
 // kRowMaxParts), so a small frame still fills the chip.  A larger launch runs
-// whole chunks only: the blocks of its last round share the CUs with fewer
-// others and finish sooner, and splitting that round measured no faster
-// (720p: 0.3 %) while each part re-read its chunk's patches and the resolve
-// pass re-read records and candidate rows (1.8x the step's algorithmic HBM
-// bytes against 1.1x).  Blocks used: whole + (chunks - whole) * parts
-// <= chunks + min(3 * chunks, slots).
+// whole chunks only, except that when its last round holds at most an
+// eighth of the slots its `paired` chunks each run as two blocks of half the
+// queries, the wavefronts of each block in two halves over the same queries,
+// each half over half of every stage's tiles, merging their minima in LDS (no
+// records, no resolve pass): those few blocks, alone on their CUs, then end
+// about twice as soon.  Measured at D = 64 with 768 slots: a last round of 32
+// or 96 chunks -7 % and -6 % of the launch; 160 and 192 unchanged; 237 (a
+// 720p frame) +0.7 %; 384 -2 %.  (Splitting the last round over reference
+// parts instead measured no faster: each part re-read its chunk's patches and
+// the resolve pass re-read records and candidate rows.)  Blocks used: whole +
+// 2 paired, or whole + (chunks - whole) * parts <= chunks + min(3 * chunks,
+// slots).
 struct RowPlan {
-    uint32_t whole, parts;
+    uint32_t whole, parts, paired;
 };
-__host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots) {
+__host__ __device__ inline RowPlan row_plan(uint32_t chunks, uint32_t slots, bool pair_ok) {
     const uint32_t cap = (uint32_t)kRowMaxParts;
-    if (chunks == 0 || slots == 0 || chunks > slots) return RowPlan{chunks, 1u};
+    if (chunks == 0 || slots == 0) return RowPlan{chunks, 1u, 0u};
+    if (chunks > slots) {
+        const uint32_t tail = chunks % slots;
+        const uint32_t pr = pair_ok && tail <= slots / RIANN_ROWS_PAIR_DIV ? tail : 0u;
+        return RowPlan{chunks - pr, 1u, pr};
+    }
     uint32_t p = slots / chunks;
     p = p < cap ? p : cap;
-    return p > 1 ? RowPlan{0u, p} : RowPlan{chunks, 1u};
+    return p > 1 ? RowPlan{0u, p, 0u} : RowPlan{chunks, 1u, 0u};
 }
 
 // Bytes [o, o + 8) of the frame as two words: the aligned words holding
@@ -507,6 +526,10 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     constexpr int SPS = (1 << row_tile_bits(DP)) / ST;  // stages per key segment
     static_assert(SPS % 2 == 0, "stage pairs never straddle a segment");
     static_assert(kWaves % 2 == 0, "the patch staging splits the wavefronts in halves");
+    // paired chunks need an even split of the tiles and of the query blocks
+    constexpr int kHalfW = kWaves / 2, kHalfQB = kQB / 2;
+    constexpr bool kPair = RIANN_ROWS_PAIRS && ST % 2 == 0 && kQB % 2 == 0;
+    static_assert(kWaves * kQB * 64 * 8 <= HALF, "the pair exchange fits one stage buffer");
     __shared__ __attribute__((aligned(16))) int8_t s_f0[HALF];
     __shared__ __attribute__((aligned(16))) int8_t s_f1[HALF];
     __shared__ __attribute__((aligned(16))) int32_t s_h0[ST * kTile];
@@ -521,18 +544,22 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     // over one part of the reference stages (consecutive blocks take
     // consecutive parts and land on different XCDs, so each XCD's L2 holds
     // fewer parts)
-    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
+    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots, kPair);
     const uint32_t bx = blockIdx.x;
     const bool whole = bx < plan.whole;
-    const int nsplit = whole ? 1 : (int)plan.parts;
-    const uint32_t split = whole ? 0u : (bx - plan.whole) % plan.parts;
-    const uint32_t chunk = whole ? bx : plan.whole + (bx - plan.whole) / plan.parts;
-    const uint32_t qbase = chunk * kBlockQ;
+    // a half of a paired chunk (after the whole chunks; plan.parts is 1)
+    const bool paired = kPair && !whole && plan.paired > 0;
+    const int nsplit = whole || paired ? 1 : (int)plan.parts;
+    const uint32_t split = whole || paired ? 0u : (bx - plan.whole) % plan.parts;
+    const uint32_t chunk = whole || paired ? bx : plan.whole + (bx - plan.whole) / plan.parts;
+    const uint32_t qbase = paired ? plan.whole * kBlockQ + (bx - plan.whole) * (kBlockQ / 2)
+                                  : chunk * kBlockQ;
+    const uint32_t nbq = paired ? kBlockQ / 2 : kBlockQ;   // the block's queries
     if (qbase >= count) return;                   // whole block exits together
     if (fb.dense_masked == kDenseMasked) {
         // a chunk whose queries the ring scan answers, all of them, has no work
         bool any = false;
-        for (uint32_t i = threadIdx.x; i < (uint32_t)kBlockQ; i += Cfg::block)
+        for (uint32_t i = threadIdx.x; i < nbq; i += Cfg::block)
             any = any || (qbase + i < count && w.route[qbase + i] != kRouteScan);
         if (!__syncthreads_or(any)) return;
     }
@@ -540,6 +567,10 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     // the wavefront index is uniform: keep it (and the DMA addresses) in SGPRs
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 31, grp = lane >> 5;
+    // in a paired block, wavefronts wq and wq + kHalfW hold the same queries,
+    // the first over tiles [0, ST / 2) of every stage, the second over the rest
+    const int half = paired ? wv / kHalfW : 0;
+    const int wq = paired ? wv % kHalfW : wv;
     const int ns_all = (int)(ix.n_rows / (kTile * ST));
     const int s_begin = (int)((int64_t)split * ns_all / nsplit);
     const int s_end = (int)((int64_t)(split + 1) * ns_all / nsplit);
@@ -552,7 +583,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     const bool fused = DP == 64 && fb.fused;
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb) {
-        const uint32_t slot = min(qbase + (uint32_t)(wv * kWaveQ + qb * 32 + col), count - 1);
+        const uint32_t slot = min(qbase + (uint32_t)(wq * kWaveQ + qb * 32 + col), count - 1);
         qid[qb] = list ? list[slot] : slot;
         qcf[qb] = 0;
         bool built = false;
@@ -575,13 +606,25 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     }
     // a fused ring frame's previous matches, counted after the pass (one
     // part of a split chunk counts its queries)
-    const bool counts = fused && !fb.all_full && split == 0;
+    const bool counts = fused && !fb.all_full && split == 0 && half == 0;
     int32_t pvq[kQB];
 #pragma unroll
     for (int qb = 0; qb < kQB; ++qb)
         pvq[qb] = counts && grp == 0 && fb.f[0].prev ? fb.f[0].prev[qid[qb]] : -1;
     __syncthreads();
 
+    // one stage's tiles: all of them, or this wavefront's half in a pair
+    auto run_stage = [&](const int8_t *lf, const int32_t *lh, uint32_t t0s) {
+        if constexpr (kPair) {
+            if (paired) {
+                constexpr int NH = ST / 2;
+                S.template stage<NH>(lf + half * (NH * KB * 1024), lh + half * (NH * kTile),
+                                     t0s + (uint32_t)(half * NH), lane, grp);
+                return;
+            }
+        }
+        S.template stage<ST>(lf, lh, t0s, lane, grp);
+    };
     int seg0 = s_begin;                           // first stage of the key segment
     for (int sg = s_begin; sg < s_end; sg += 2) {
         if (sg - seg0 == SPS) {
@@ -589,16 +632,36 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
             seg0 = sg;
         }
         if (sg + 1 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
-        S.stage(s_f0, s_h0, (uint32_t)((sg - seg0) * ST), lane, grp);
+        run_stage(s_f0, s_h0, (uint32_t)((sg - seg0) * ST));
         __syncthreads();
         if (sg + 1 < s_end) {
             if (sg + 2 < s_end) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
-            S.stage(s_f1, s_h1, (uint32_t)((sg + 1 - seg0) * ST), lane, grp);
+            run_stage(s_f1, s_h1, (uint32_t)((sg + 1 - seg0) * ST));
             __syncthreads();
         }
     }
     S.fold((uint32_t)(seg0 * ST));
-    if (counts) fused_counts(ix, fb, qbase + (uint32_t)(wv * kWaveQ), count, pvq, lane);
+    if (counts) fused_counts(ix, fb, qbase + (uint32_t)(wq * kWaveQ), count, pvq, lane);
+    if constexpr (kPair) {
+        if (paired) {
+            // the two wavefronts of a pair saw disjoint tiles of the same
+            // queries: each takes the lexicographic (Y, tile) minimum of both,
+            // exchanged through a stage buffer (no DMA is in flight here)
+            uint2 *xo = reinterpret_cast<uint2 *>(s_f0) + wv * (kQB * 64);
+            const uint2 *xi =
+                reinterpret_cast<const uint2 *>(s_f0) + ((wv + kHalfW) % kWaves) * (kQB * 64);
+#pragma unroll
+            for (int qb = 0; qb < kQB; ++qb) xo[qb * 64 + lane] = make_uint2(S.bY[qb], S.bT[qb]);
+            __syncthreads();
+#pragma unroll
+            for (int qb = 0; qb < kQB; ++qb) {
+                const uint2 o = xi[qb * 64 + lane];
+                const bool lt = o.x < S.bY[qb] || (o.x == S.bY[qb] && o.y < S.bT[qb]);
+                S.bY[qb] = lt ? o.x : S.bY[qb];
+                S.bT[qb] = lt ? o.y : S.bT[qb];
+            }
+        }
+    }
 
     // ---- merge the two lane groups (rows 0-15 and 16-31 of every tile's
     // accumulator order): the lexicographically smaller (Y, tile) wins; equal
@@ -617,7 +680,7 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
         rc[qb] = make_uint2(mine || same ? y : oy, ((mine || same ? t : ot) << 2) | gm);
     }
 
-    const uint32_t wbase = qbase + (uint32_t)(wv * kWaveQ);
+    const uint32_t wbase = qbase + (uint32_t)(wq * kWaveQ);
     if (nsplit > 1) {
         // one part of the reference range: the record goes to the resolve
         // kernel at the query's dense-list position (the records are free
@@ -679,6 +742,31 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
         const uint32_t scan = code[qb] == (uint32_t)kRouteScan ? 1u : 0u;
         rc[qb].y = (in & (masked & scan ^ 1u)) ? rc[qb].y : 0u;
     }
+    if constexpr (kPair) {
+        if (paired) {
+            // the two wavefronts of a pair hold the same merged records:
+            // each checks half of the query blocks
+            uint2 rh[kHalfQB];
+            uint32_t qh[kHalfQB];
+            int ch[kHalfQB], fh[kHalfQB];
+#pragma unroll
+            for (int i = 0; i < kHalfQB; ++i) {
+                const int j = i + kHalfQB;
+                rh[i] = half ? rc[j] : rc[i];
+                qh[i] = half ? qid[j] : qid[i];
+                ch[i] = half ? qcl[j] : qcl[i];
+                fh[i] = half ? fidl[j] : fidl[i];
+            }
+            const int8_t *sph = sp + half * (kHalfQB * 32 * DP);
+            if (fb.n == 1)
+                check_wave<DP, kHalfQB, Cfg::inflight, kStagePatches, true>(ix, fb, w, rh, qh, ch,
+                                                                           fh, sph, lane);
+            else
+                check_wave<DP, kHalfQB, Cfg::inflight, kStagePatches, false>(ix, fb, w, rh, qh, ch,
+                                                                            fh, sph, lane);
+            return;
+        }
+    }
     if (fb.n == 1)
         check_wave<DP, kQB, Cfg::inflight, kStagePatches, true>(ix, fb, w, rc, qid, qcl, fidl, sp,
                                                                lane);
@@ -693,7 +781,7 @@ __global__ __launch_bounds__(256) void k_resolve(DevIndex ix, FrameBatch fb, Wor
     const bool natural = fb.all_full || fb.dense_masked;
     const uint32_t *list = natural ? nullptr : w.dense_list;
     const uint32_t count = natural ? (uint32_t)fb.Q : w.counters[1];
-    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots);
+    const RowPlan plan = row_plan((count + kBlockQ - 1) / kBlockQ, slots, false);
     const int nsplit = (int)plan.parts;
     const int lane = threadIdx.x & 63, r = lane & 15;
     for (uint32_t base = plan.whole * kBlockQ + blockIdx.x * 16u; base < count;
@@ -755,7 +843,7 @@ hipError_t launch_rows_t(const DevIndex &ix, const FrameBatch &fb, const Work &w
     // split queries: fewer than min(chunks, slots) chunks' worth.  With the
     // queries in order the plan is known here: no split, no resolve pass
     if ((fb.all_full || fb.dense_masked) &&
-        row_plan((uint32_t)std::min<int64_t>(chunks, 0x7FFFFFFF), slots).parts == 1)
+        row_plan((uint32_t)std::min<int64_t>(chunks, 0x7FFFFFFF), slots, false).parts == 1)
         return hipSuccess;
     const int64_t sq = std::min<int64_t>(chunks, resident) * kBlockQ;
     const int64_t rb = std::min<int64_t>((sq + 15) / 16, 4096);   // 16 queries per 256-thread block

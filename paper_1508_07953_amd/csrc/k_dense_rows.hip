@@ -68,12 +68,12 @@ __global__ __launch_bounds__(RowCfg<DP>::block) void k_dense_rows_knn(DevIndex i
     __syncthreads();
     for (int sg = 0; sg < ns_all; sg += 2) {
         if (sg + 1 < ns_all) stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 1, s_f1, s_h1, wv, lane);
-        S.stage(s_f0, s_h0, (uint32_t)(sg * ST), lane, grp);
+        S.template stage<ST>(s_f0, s_h0, (uint32_t)(sg * ST), lane, grp);
         __syncthreads();
         if (sg + 1 < ns_all) {
             if (sg + 2 < ns_all)
                 stage_dma<KB, ST, kWaves>(ix.Rfr, ix.Hf, sg + 2, s_f0, s_h0, wv, lane);
-            S.stage(s_f1, s_h1, (uint32_t)((sg + 1) * ST), lane, grp);
+            S.template stage<ST>(s_f1, s_h1, (uint32_t)((sg + 1) * ST), lane, grp);
             __syncthreads();
         }
     }
