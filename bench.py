@@ -65,6 +65,7 @@ def dense_traffic_bytes(workload, layout, shape):
 def cpu_baseline(wl, f0, f1, target_s):
     """Oracle exact-mode RIANN timed on the host's cores on a sample of one
     frame's queries; its previous field is the oracle's own brute force."""
+    import gen
     import oracle
     p, s = wl.patch, wl.stride
     P0 = oracle.extract(f0, p, s)
@@ -76,7 +77,9 @@ def cpu_baseline(wl, f0, f1, target_s):
     elapsed, done = 0.0, 0
     while True:
         sel = rng.choice(Q, size=min(m, Q), replace=False)
+        t0 = time.perf_counter()
         prev, _ = oracle.brute_force(P0[sel], wl.ref)
+        dt_bf = time.perf_counter() - t0
         t0 = time.perf_counter()
         tabs.riann(P1[sel], prev)
         dt = time.perf_counter() - t0
@@ -93,12 +96,38 @@ def cpu_baseline(wl, f0, f1, target_s):
     tabs.riann(P1[sel1], prev1)
     dt1 = time.perf_counter() - t0
     oracle.set_threads(cores)
+    # the small configuration (64x64 frames, 1,024 references, 8 keys): every
+    # frame, frame 0 by brute force, then exact-mode RIANN from its own fields
+    tw = gen.make_workload("tiny")
+    ttabs = oracle.Tables(tw.ref, tw.keys)
+    tq, prev_t, t0 = 0, None, time.perf_counter()
+    for t in range(tw.frames):
+        Pt = oracle.extract(tw.frame(t), tw.patch, tw.stride)
+        prev_t = (oracle.brute_force(Pt, tw.ref)[0] if prev_t is None
+                  else ttabs.riann(Pt, prev_t)["idx"])
+        tq += len(Pt)
+    dt_tiny = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": done / elapsed, "unit": "patches/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} random queries of frame 1 ({Q} per frame), exact-mode RIANN "
                       f"with the oracle's brute-force field of frame 0 as prev; "
                       f"{elapsed:.2f} s wall, table build excluded",
             "single_core_value": len(sel1) / dt1,
-            "single_core_sample": f"{len(sel1)} of the same queries on 1 thread, {dt1:.2f} s"}
+            "single_core_sample": f"{len(sel1)} of the same queries on 1 thread, {dt1:.2f} s",
+            "brute_force_value": done / dt_bf,
+            "brute_force_sample": f"the oracle's brute force on the same {done} queries of "
+                                  f"frame 0, {dt_bf:.2f} s",
+            "tiny_value": tq / dt_tiny,
+            "tiny_sample": f"every frame of the 64x64 workload ({tw.frames} frames, {tq} "
+                           f"queries; frame 0 by brute force, then exact-mode RIANN from "
+                           f"its own fields), {dt_tiny:.2f} s, table build excluded",
+            "cpu_model": model}
 
 
 def paper_mode(idx, frames, hq, wq, dev, log_fn, nframes=12, timed=6):
