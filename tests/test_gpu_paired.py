@@ -5,8 +5,8 @@ wavefronts split the reference tiles and merge their minima in LDS.  Frame
 sizes put the chunk count just past one round (a ragged last chunk), at the
 largest paired last round, and one chunk beyond it (run whole); each case
 runs a full search (patches cut in the dense kernel), a ring frame at the
-default routing threshold and a two-frame batch (patches from the extraction
-kernel), and compares the last chunks' queries, all of them, plus a sample of
+default routing threshold and at threshold 0 (its routing counts as well) and a
+two-frame batch (patches from the extraction kernel), and compares the last chunks' queries, all of them, plus a sample of
 the rest.  Integer work: fields and SSDs bit for bit."""
 import numpy as np
 import pytest
@@ -78,6 +78,22 @@ def test_last_round(env, H, W):
     check(f[2], o2, s2, wl.ref, sel, "ring frame")
     st = idx.stats()
     assert st["queries"] == Q and st["ring_queries"] + st["dense_queries"] == Q
+
+    # threshold 0: every query dense, patches cut and routing counted by the
+    # dense kernel itself (one wavefront of each pair counts)
+    thr = idx.params.dense_threshold
+    idx.set_dense_threshold(0)
+    pv = host(o1).copy()
+    pv[rng.random(pv.size) < 0.1] = -1
+    nop = int((pv < 0).sum())
+    idx.reset_stats()
+    o3, s3 = idx.match_frame(d[2], prev=torch.from_numpy(pv.reshape(o1.shape)).to(dev))
+    torch.cuda.synchronize()
+    check(f[2], o3, s3, wl.ref, sel, "ring frame, threshold 0")
+    st = idx.stats()
+    assert st["queries"] == Q and st["dense_queries"] == Q and st["no_prior"] == nop
+    assert st["bound_routed"] == Q - nop and st["ring_queries"] == 0
+    idx.set_dense_threshold(thr)
 
     # two frames in one launch: 2 Q queries, patches from the extraction kernel
     outs = [torch.empty((hq, wq), dtype=torch.int32, device=dev) for _ in range(2)]
