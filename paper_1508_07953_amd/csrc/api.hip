@@ -141,7 +141,7 @@ int64_t index_bytes(int64_t n, int D, int K, uint32_t flags) {
     const int64_t pivr = (K > 0 && !(flags & RIANN_FLAG_GATHER_SCAN))
                              ? (int64_t)K * n16 * pivr_words(K) * 4 + 256 : 0;
     return 2 * (n_pad * Dp + n_pad * 4) + n_pad * 4 + (int64_t)K * (n16 + n) * 4 + n * Kp * 4 +
-           n_rows * (2 * (int64_t)Dp + 20) + (int64_t)K * 4 + (int64_t)kStatWords * 8 + 65536 + 4096 + pivr +
+           n_rows * ((int64_t)Dp + 12) + (int64_t)K * 4 + (int64_t)kStatWords * 8 + 65536 + 4096 + pivr +
            (int64_t)std::max(K, 1) * kRouteStride * 4 + 256;
 }
 
@@ -229,7 +229,6 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     std::vector<int8_t> Rfr((size_t)n_rows * Dp, 0);
     std::vector<int32_t> Hf((size_t)n_rows, row_pad_y(Dp));
     std::vector<int32_t> Rci((size_t)n_rows * 2, 0);
-    std::vector<int8_t> Rck((size_t)n_rows * (Dp + 8), 0);
     {
         std::vector<int64_t> order((size_t)n_rows, -1);
         int64_t pos = 0;
@@ -252,14 +251,9 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         for (int64_t t = 0; t < n_rows / kTile; ++t)
             for (int g = 0; g < 2; ++g)
                 for (int r = 0; r < 16; ++r) {
+                    // accumulator order: entry g * 16 + r of a tile is row 8(r/4) + 4g + r%4
                     const int64_t ref = order[(size_t)(t * kTile + 8 * (r / 4) + 4 * g + r % 4)];
-                    // candidate-check block of (tile, group): the group's 16 rows
-                    // in accumulator order, row bytes then {Rc, index}
-                    int8_t *blk = &Rck[(size_t)((t * 2 + g) * (16 * Dp + 128))];
-                    const int32_t ci[2] = {ref < 0 ? 0 : Rc[(size_t)ref], (int32_t)ref};
-                    std::memcpy(blk + 16 * Dp + 8 * r, ci, 8);
                     if (ref < 0) continue;
-                    std::memcpy(blk + (size_t)r * Dp, &Rv[(size_t)(ref * Dp)], (size_t)Dp);
                     const int64_t rc = Rc[(size_t)ref];
                     Hf[(size_t)(t * kTile + g * 16 + r)] = (int32_t)((rc + bias - (rc & 1)) / 2);
                 }
@@ -345,15 +339,14 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
                  szP = (size_t)std::max<int64_t>(K * n, 1) * 4,
                  szPiv = (size_t)n * Kp * 4, szK = (size_t)std::max(K, 1) * 4,
                  szS = (size_t)kStatWords * 8, szTs = Ts.size() * 4, szLb = Lb.size() * 4;
-    const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8,
-                 szRck = (size_t)n_rows * (Dp + 8);
+    const size_t szRfr = (size_t)n_rows * Dp, szHf = (size_t)n_rows * 4, szRci = (size_t)n_rows * 8;
     const bool pivr = K > 0 && !(h->prm.flags & RIANN_FLAG_GATHER_SCAN);
     const size_t szPivR = pivr ? (size_t)K * n16 * pivr_words(K) * 4 : 0;
     const size_t szRt = Rt.size() * 4;
-    size_t off[17], tot = 0;
-    const size_t sz[17] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
-                           szLb, szPivR, szRt, szRck};
-    for (int i = 0; i < 17; ++i) {
+    size_t off[16], tot = 0;
+    const size_t sz[16] = {szRv, szRc, szT, szP, szPiv, szK, szS, szRv, szRc, szTs, szHf, szRfr, szRci,
+                           szLb, szPivR, szRt};
+    for (int i = 0; i < 16; ++i) {
         off[i] = tot;
         tot += round_up((int64_t)sz[i], 256);
     }
@@ -387,7 +380,6 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
     h->dix.Hf = (const int32_t *)(b + off[10]);
     h->dix.Rfr = (const int8_t *)(b + off[11]);
     h->dix.Rci = (const int2 *)(b + off[12]);
-    h->dix.Rck = (const int8_t *)(b + off[16]);
     h->dix.n_rows = n_rows;
     h->dix.n16 = (int32_t)n16;
     h->dix.ns = (int32_t)ns;
@@ -413,7 +405,6 @@ riann_status_t upload(riann_index *h, hipStream_t st) {
         {b + off[10], Hf.data(), szHf},
         {b + off[11], Rfr.data(), szRfr},
         {b + off[12], Rci.data(), szRci},
-        {b + off[16], Rck.data(), szRck},
     };
     for (auto &c : cp) {
         if (c.n == 0) continue;

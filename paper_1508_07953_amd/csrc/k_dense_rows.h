@@ -238,11 +238,12 @@ struct RowState {
 // tile << 2 | group mask}: lane r takes accumulator row r of the tile in each
 // masked lane group -- class-order row 32 tile + 8(r/4) + 4g + r%4 -- forms
 // its exact SSD with v_dot4 from the row's bytes, and a 16-lane reduction
-// keeps the (SSD, reference index) minimum.  The rows and their {Rc, index}
-// come from the (tile, group) block of the check table, contiguous, so a
-// query's check reads 16 Dp + 128 bytes in whole lines (the fragment layout
-// would spread them over twice the lines: at D = 64 this pass was bound by
-// those L2 reads).  issue() starts the loads that need only the record (Qc
+// keeps the (SSD, reference index) minimum.  The rows come from the
+// fragment table the pass stages (already in each XCD's L2) and their
+// {Rc, index} from Rci.  (A separate table holding each (tile, group)'s 16
+// rows contiguously read fewer lines but measured no faster once the check
+// passes were pipelined, and every XCD fetched it into its L2 as well: 1.2 MB
+// more per XCD at 720p.)  issue() starts the loads that need only the record (Qc
 // and the first masked group's row with its {Rc, index}); finish() takes the
 // query patch (global memory or LDS), Qc and the query's frame and does the
 // rest, so a caller can have the loads of several queries in flight before
@@ -264,14 +265,13 @@ struct RowCheck {
         }
     }
 
-    // row r of the check block of (tile, group g) and its {Rc, index}
+    // accumulator row r of lane group g of a tile (tile row 8(r/4) + 4g +
+    // r%4) and its {Rc, index}
     __device__ __forceinline__ static void check_row(const DevIndex &ix, int64_t tile, int g, int r,
                                                      uint4 (&v)[DP / 16], int2 &ci) {
-        const int8_t *blk = ix.Rck + (tile * 2 + g) * (16 * DP + 128);
-        const uint4 *f = reinterpret_cast<const uint4 *>(blk + r * DP);
-#pragma unroll
-        for (int k = 0; k < DP / 16; ++k) v[k] = f[k];
-        ci = reinterpret_cast<const int2 *>(blk + 16 * DP)[r];
+        const int m = 8 * (r >> 2) + 4 * g + (r & 3);
+        row_bytes(ix, tile, m, v);
+        ci = ix.Rci[tile * kTile + m];
     }
 
     // (the loads are unconditional -- a record without a group reads a row of

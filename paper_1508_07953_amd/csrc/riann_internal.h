@@ -75,12 +75,6 @@ struct DevIndex {
     const int8_t *Rfr;
     const int32_t *Hf;
     const int2 *Rci;
-    //   Rck  per (tile t, lane group g) a block of 16 Dp + 128 bytes at
-    //        (2t + g)(16 Dp + 128): the group's 16 rows in accumulator order
-    //        (row 32t + 8(r/4) + 4g + r%4 at r Dp, natural byte order), then
-    //        their {Rc, index} at 16 Dp + 8r: what the candidate check of a
-    //        query whose minimum lies in (t, g) reads, contiguous
-    const int8_t *Rck;
     int64_t n_rows;
     const uint32_t *T;    // K x n16, SSD(key_k, r) ascending; each key's list is
                           // padded to whole 16-entry (64-byte) lines with
