@@ -88,6 +88,9 @@ struct RowCfg {
 #define RIANN_ROWS_LOOKAHEAD 1                 // MFMA chains issued ahead of the tree
 #endif                                         // (2: within 1 %, 25 more registers)
 constexpr int kLookahead = RIANN_ROWS_LOOKAHEAD;
+#ifndef RIANN_ROWS_XCD_RANGES
+#define RIANN_ROWS_XCD_RANGES 1                // 0: whole chunk = block index
+#endif
 #ifndef RIANN_ROWS_PAIRS
 #define RIANN_ROWS_PAIRS 1                     // 0: the last round's chunks run whole
 #endif
@@ -505,6 +508,8 @@ __device__ __forceinline__ void fused_counts(const DevIndex &ix, const FrameBatc
     }
 }
 
+constexpr uint32_t kXcds = 8;                  // accelerator dies (L2 domains) of the chip
+
 template <int DP, int ST, int WAVES = 0, int QB = 0>
 __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(DevIndex ix,
                                                                             FrameBatch fb, Work w,
@@ -551,7 +556,16 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     const bool paired = kPair && !whole && plan.paired > 0;
     const int nsplit = whole || paired ? 1 : (int)plan.parts;
     const uint32_t split = whole || paired ? 0u : (bx - plan.whole) % plan.parts;
-    const uint32_t chunk = whole || paired ? bx : plan.whole + (bx - plan.whole) / plan.parts;
+    // whole chunks: the hardware deals blocks to the 8 XCDs in turn (block b
+    // to XCD b mod 8), so block b takes chunk i = b / 8 of the b mod 8-th
+    // eighth of the whole chunks -- each XCD's L2 then holds the frame rows of
+    // one contiguous range of queries instead of all of them
+    uint32_t wc = bx;
+    if (RIANN_ROWS_XCD_RANGES && whole) {
+        const uint32_t x = bx % kXcds, per = plan.whole / kXcds, rem = plan.whole % kXcds;
+        wc = x * per + min(x, rem) + bx / kXcds;
+    }
+    const uint32_t chunk = whole ? wc : paired ? bx : plan.whole + (bx - plan.whole) / plan.parts;
     const uint32_t qbase = paired ? plan.whole * kBlockQ + (bx - plan.whole) * (kBlockQ / 2)
                                   : chunk * kBlockQ;
     const uint32_t nbq = paired ? kBlockQ / 2 : kBlockQ;   // the block's queries
