@@ -508,8 +508,6 @@ __device__ __forceinline__ void fused_counts(const DevIndex &ix, const FrameBatc
     }
 }
 
-constexpr uint32_t kXcds = 8;                  // accelerator dies (L2 domains) of the chip
-
 template <int DP, int ST, int WAVES = 0, int QB = 0>
 __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(DevIndex ix,
                                                                             FrameBatch fb, Work w,
@@ -556,15 +554,9 @@ __global__ __launch_bounds__((RowCfg<DP, WAVES, QB>::block)) void k_dense_rows(D
     const bool paired = kPair && !whole && plan.paired > 0;
     const int nsplit = whole || paired ? 1 : (int)plan.parts;
     const uint32_t split = whole || paired ? 0u : (bx - plan.whole) % plan.parts;
-    // whole chunks: the hardware deals blocks to the 8 XCDs in turn (block b
-    // to XCD b mod 8), so block b takes chunk i = b / 8 of the b mod 8-th
-    // eighth of the whole chunks -- each XCD's L2 then holds the frame rows of
-    // one contiguous range of queries instead of all of them
-    uint32_t wc = bx;
-    if (RIANN_ROWS_XCD_RANGES && whole) {
-        const uint32_t x = bx % kXcds, per = plan.whole / kXcds, rem = plan.whole % kXcds;
-        wc = x * per + min(x, rem) + bx / kXcds;
-    }
+    // whole chunks by XCD bands: each XCD's L2 then holds the frame rows of
+    // one contiguous range of queries instead of rows from all of them
+    const uint32_t wc = RIANN_ROWS_XCD_RANGES && whole ? xcd_band(bx, plan.whole) : bx;
     const uint32_t chunk = whole ? wc : paired ? bx : plan.whole + (bx - plan.whole) / plan.parts;
     const uint32_t qbase = paired ? plan.whole * kBlockQ + (bx - plan.whole) * (kBlockQ / 2)
                                   : chunk * kBlockQ;

@@ -281,7 +281,10 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
     __shared__ uint4 s_rr[KQ > 0 ? kBlk : 1];
     __shared__ unsigned long long s_sc[KQ > 0 ? kWv : 1][2];
     const int64_t Q = fb.Q;
-    const int64_t qid = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    // (blocks in XCD bands, as the dense search takes its chunks, measured
+    // 2-4 % slower here: a band of costly rings loads one XCD)
+    const uint32_t bx = blockIdx.x;
+    const int64_t qid = (int64_t)bx * kBlk + threadIdx.x;
     const bool valid = qid < Q;
     const int64_t qq = valid ? qid : Q - 1;
     // the extraction kernel has already routed full-search, no-prior and
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(ring_block(KR), KR > 0 ? 6 : 1) void k_ring(DevInde
         const int slot[6] = {ST_MSTAR, ST_NOPRIOR, ST_RING, ST_DENSE, ST_BOUND, ST_PROBES};
         if (tot) stat_add(stats, slot[threadIdx.x], tot);
         if (threadIdx.x == 3 && !fb.dense_masked) {
-            const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)blockIdx.x * kBlk);
+            const int64_t nv = min<int64_t>(kBlk, Q - (int64_t)bx * kBlk);
             stat_add(stats, ST_QUERIES, (unsigned long long)nv);
         }
     }

@@ -200,6 +200,17 @@ __device__ __forceinline__ void stat_add(unsigned long long *stats, int slot,
               v);
 }
 
+// The hardware deals a launch's blocks to the chip's 8 XCDs (each with its
+// own L2) in turn: block b runs on XCD b mod 8.  xcd_band(b, nb) maps block b
+// of nb to the work item b / 8 of the (b mod 8)-th eighth of [0, nb) (a
+// bijection), so each XCD works through one contiguous band of the items and
+// its L2 holds what neighbouring items share.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_band(uint32_t b, uint32_t nb) {
+    const uint32_t x = b % kXcds, per = nb / kXcds, rem = nb % kXcds;
+    return x * per + min(x, rem) + b / kXcds;
+}
+
 // Extraction of every query patch; in launches with a ring phase also the
 // route code of each query against `threshold` (the ring kernel's; < 0: no
 // routing), and with fb.dense_masked the counts of what it routed (stats).
